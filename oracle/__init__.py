@@ -1,0 +1,184 @@
+"""FP64 CPU oracle for DWT-reduced local hyperspectral anomaly detection.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import this package.  It shares no code with the HIP library in
+``paper_1201_2025_amd``, and the product path never falls back to it.
+
+The arithmetic is in ``hsad_oracle.c``, plain C in double precision.  Filter design
+is in ``db4.py``, evaluation in ``evaluate.py`` and the MLP in ``mlp.py``.  This module
+only marshals numpy arrays.  Paper references follow the section and equation numbers
+of Zare Baghbidi et al., SIPIJ 2(4), 2011.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import evaluate
+from ._lib import build, lib, ptr, set_threads
+from .db4 import DB4, daubechies_lowpass, highpass
+from .evaluate import auc, auc_counts, mask, threshold
+
+__all__ = [
+    "DB4", "daubechies_lowpass", "highpass", "build", "set_threads", "dwt_out_len",
+    "levels_for", "dwt_level", "dwt_approx", "dwt_full", "idwt_full", "window_stats",
+    "loading", "cholesky", "lrx_dwrx", "jacobi_eig", "dwest", "threshold", "mask", "auc",
+    "auc_counts", "evaluate",
+]
+
+_D = ctypes.c_double
+
+
+def dwt_out_len(L: int, levels: int) -> int:
+    """Approximation length after `levels` levels; -1 when a level input would be < 2."""
+    return int(lib().orc_dwt_out_len(int(L), int(levels)))
+
+
+def levels_for(L: int, target: int = 4) -> int:
+    """Sec. 4 decomposes "until four samples are left".  The number of levels is the
+    largest J whose approximation still has at least `target` samples."""
+    J, n = 0, int(L)
+    while n >= 2 and (n + 1) // 2 >= target:
+        n = (n + 1) // 2
+        J += 1
+    return J
+
+
+def _filt(h):
+    h = np.ascontiguousarray(DB4 if h is None else h, dtype=np.float64)
+    return h, len(h)
+
+
+def dwt_level(x: np.ndarray, h=None, detail: bool = True):
+    """One analysis level (eqs. 8-9) of a 1-D signal; returns (a, d) or a."""
+    h, nt = _filt(h)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = len(x)
+    m = (n + (n & 1)) // 2
+    a = np.empty(m)
+    d = np.empty(m) if detail else None
+    lib().orc_dwt_level(ptr(x, _D), n, ptr(h, _D), nt, ptr(a, _D), ptr(d, _D))
+    return (a, d) if detail else a
+
+
+def dwt_approx(cube: np.ndarray, levels: int, h=None) -> np.ndarray:
+    """Approximation matrix of Sec. 4.  `cube` is (..., L) float32, and the result has
+    shape (..., L') in float64."""
+    h, nt = _filt(h)
+    c = np.ascontiguousarray(cube, dtype=np.float32)
+    L = c.shape[-1]
+    npix = c.size // L if L else 0
+    Lp = dwt_out_len(L, levels)
+    if Lp < 0:
+        raise ValueError("levels too deep for L=%d" % L)
+    out = np.empty(c.shape[:-1] + (Lp,), dtype=np.float64)
+    lib().orc_dwt_approx(ptr(c, ctypes.c_float), npix, L, int(levels), ptr(h, _D), nt,
+                         ptr(out, _D))
+    return out
+
+
+def dwt_full(x: np.ndarray, levels: int, h=None) -> np.ndarray:
+    """[a_J d_J ... d_1] of a 1-D signal (even length at every level)."""
+    h, nt = _filt(h)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    if lib().orc_dwt_full(ptr(x, _D), len(x), int(levels), ptr(h, _D), nt, ptr(out, _D)):
+        raise ValueError("full DWT needs even lengths at every level")
+    return out
+
+
+def idwt_full(c: np.ndarray, levels: int, h=None) -> np.ndarray:
+    h, nt = _filt(h)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.empty_like(c)
+    if lib().orc_idwt_full(ptr(c, _D), len(c), int(levels), ptr(h, _D), nt, ptr(out, _D)):
+        raise ValueError("full DWT needs even lengths at every level")
+    return out
+
+
+def _cube64(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim != 3:
+        raise ValueError("expected an H x W x L' cube")
+    return x
+
+
+def _check_windows(inner: int, outer: int):
+    if outer < 1 or outer % 2 == 0 or inner < 0 or (inner and inner % 2 == 0) or inner >= outer:
+        raise ValueError("windows must be odd with 0 <= inner < outer")
+
+
+def window_stats(x: np.ndarray, inner: int, outer: int, py: int, px: int):
+    """(n_a, mu_a, C_a, n_in, m_in, C_in) of one pixel (clipped windows, 1/n)."""
+    x = _cube64(x)
+    _check_windows(inner, outer)
+    H, W, Lp = x.shape
+    mu, C = np.zeros(Lp), np.zeros((Lp, Lp))
+    mi, Ci = np.zeros(Lp), np.zeros((Lp, Lp))
+    n = np.zeros(2, dtype=np.int64)
+    lib().orc_window_stats(ptr(x, _D), H, W, Lp, inner, outer, py, px, ptr(mu, _D),
+                           ptr(C, _D), ptr(mi, _D), ptr(Ci, _D), ptr(n, ctypes.c_int64))
+    return int(n[0]), mu, C, int(n[1]), mi, Ci
+
+
+def loading(C: np.ndarray, load_rel: float) -> float:
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    return float(lib().orc_loading(ptr(C, _D), C.shape[0], float(load_rel)))
+
+
+def cholesky(A: np.ndarray):
+    """Lower Cholesky factor or None if A is not numerically positive definite."""
+    A = np.array(A, dtype=np.float64, order="C", copy=True)
+    if lib().orc_cholesky(ptr(A, _D), A.shape[0]):
+        return None
+    return np.tril(A)
+
+
+def _idx(H: int, W: int, idx) -> np.ndarray:
+    if idx is None:
+        return np.arange(H * W, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64).ravel()
+    if idx.size and (idx.min() < 0 or idx.max() >= H * W):
+        raise ValueError("pixel index out of range")
+    return idx
+
+
+def lrx_dwrx(x: np.ndarray, inner: int, outer: int, load_rel: float = 1e-6, idx=None,
+             want=("lrx", "dwrx")):
+    """LRX (eq. 1, annulus background) and DWRX (eq. 5) at pixels `idx` (flat y*W+x, all
+    pixels by default).  Returns (lrx, dwrx) as float64; an unrequested output is None."""
+    x = _cube64(x)
+    _check_windows(inner, outer)
+    H, W, Lp = x.shape
+    idx = _idx(H, W, idx)
+    lrx = np.empty(idx.size) if "lrx" in want else None
+    dwrx = np.empty(idx.size) if "dwrx" in want else None
+    lib().orc_lrx_dwrx(ptr(x, _D), H, W, Lp, inner, outer, float(load_rel),
+                       ptr(idx, ctypes.c_int64), idx.size, ptr(lrx, _D), ptr(dwrx, _D))
+    return lrx, dwrx
+
+
+def jacobi_eig(A: np.ndarray, tol_rel: float = 1e-14, max_sweeps: int = 100):
+    """(eigenvalues, eigenvectors as columns, sweeps) by cyclic Jacobi."""
+    A = np.array(A, dtype=np.float64, order="C", copy=True)
+    n = A.shape[0]
+    ev, V = np.empty(n), np.empty((n, n))
+    sweeps = lib().orc_jacobi_eig(n, ptr(A, _D), ptr(ev, _D), ptr(V, _D), tol_rel, max_sweeps)
+    return ev, V, int(sweeps)
+
+
+def dwest(x: np.ndarray, inner: int, outer: int, idx=None):
+    """DWEST (eqs. 2-4).  Returns (score, literal, npos), where score is
+    ||V_P^T m_diff||_2, literal is sum_P |v_i^T m_diff|, and npos is |P|."""
+    x = _cube64(x)
+    _check_windows(inner, outer)
+    if inner < 1:
+        raise ValueError("DWEST needs an inner window")
+    H, W, Lp = x.shape
+    idx = _idx(H, W, idx)
+    s, lit = np.empty(idx.size), np.empty(idx.size)
+    npos = np.empty(idx.size, dtype=np.int32)
+    lib().orc_dwest(ptr(x, _D), H, W, Lp, inner, outer, ptr(idx, ctypes.c_int64), idx.size,
+                    ptr(s, _D), ptr(lit, _D), ptr(npos, ctypes.c_int32))
+    return s, lit, npos

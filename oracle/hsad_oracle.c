@@ -1,0 +1,442 @@
+/*
+ * hsad_oracle.c -- plain FP64 CPU oracle for DWT-reduced local anomaly detection.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or call
+ * this file; only the tests, the smoke check and the benchmark's CPU-baseline leg use it.
+ * It shares no code, header, table or constant with the HIP library.
+ *
+ * Method: Zare Baghbidi, Jamshidi, Naghsh Nilchi, Homayouni, "Improvement of anomaly
+ * detection algorithms in hyperspectral images using discrete wavelet transform",
+ * SIPIJ 2(4), 2011.
+ *   - Sec. 3, eqs. (8)-(9), Fig. 1: one analysis level, low-pass y_low[k] = sum_n x[n] h[2k-n],
+ *     high-pass with g, iterated on the low-pass branch.
+ *   - Sec. 4: keep only the approximation coefficients of every pixel spectrum.
+ *   - Sec. 2.1, eq. (1): RX score (r-mu)^T C^-1 (r-mu); local background window (LRX).
+ *   - Sec. 2.2, eqs. (2)-(4): DWEST on the difference covariance of inner/outer windows.
+ *   - Sec. 2.3, eq. (5): DWRX, m_diff^T C_outer^-1 m_diff.
+ *
+ * Everything is computed in double precision straight from the definitions: windows are
+ * gathered pixel by pixel, means and covariances are two-pass (exact centring), the loaded
+ * covariance is factored by an unblocked Cholesky, and DWEST uses a cyclic Jacobi
+ * eigensolver.  Pixels are independent; OpenMP only splits the pixel list across threads.
+ *
+ * Readings of points the paper leaves open (each one is also listed in the design notes):
+ *   periodised filtering with index (2k - m) mod n; an odd-length level input is extended
+ *   by repeating its last sample; square windows centred on the pixel and clipped to the
+ *   image; background = outer window minus inner window (inner = 0 means no guard window);
+ *   covariances normalised by the sample count; diagonal loading
+ *   lambda = load_rel * tr(C)/L' with a floor of 1e-30; DWEST keeps eigenvalues greater
+ *   than 1e-12 * max|lambda| and reports ||V_P^T m_diff||_2 and sum_P |v_i^T m_diff|.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_LOAD_FLOOR 1e-30
+#define ORC_POS_EIG_REL 1e-12
+
+/* Thread count for the pixel loops (n <= 0 leaves the runtime default). */
+void orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------------------ */
+/* DWT (Sec. 3, eqs. 8-9; Sec. 4)                                                        */
+/* ------------------------------------------------------------------------------------ */
+
+/* Length of the approximation after `levels` levels; -1 if a level input would be < 2. */
+int64_t orc_dwt_out_len(int64_t L, int levels)
+{
+    if (L < 1 || levels < 0) return -1;
+    int64_t n = L;
+    for (int j = 0; j < levels; ++j) {
+        if (n < 2) return -1;
+        n = (n + 1) / 2;
+    }
+    return n;
+}
+
+static int64_t pmod(int64_t a, int64_t n)
+{
+    int64_t r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+/* One analysis level of eqs. (8)-(9) on a periodised signal.  If n is odd the signal is
+ * first extended to n+1 samples by repeating x[n-1].  a (and d, if not NULL) receive
+ * ne/2 values where ne is the (even) extended length. */
+void orc_dwt_level(const double *x, int64_t n, const double *h, int ntaps,
+                   double *a, double *d)
+{
+    int64_t ne = n + (n & 1);
+    int64_t m = ne / 2;
+    for (int64_t k = 0; k < m; ++k) {
+        double sa = 0.0, sd = 0.0;
+        for (int t = 0; t < ntaps; ++t) {
+            int64_t i = pmod(2 * k - t, ne);
+            double xv = (i < n) ? x[i] : x[n - 1];
+            sa += h[t] * xv;
+            if (d) {
+                /* quadrature mirror: g[t] = (-1)^t h[ntaps-1-t] */
+                double g = ((t & 1) ? -1.0 : 1.0) * h[ntaps - 1 - t];
+                sd += g * xv;
+            }
+        }
+        a[k] = sa;
+        if (d) d[k] = sd;
+    }
+}
+
+/* Approximation coefficients after `levels` levels for each of npix spectra of length L
+ * (row-major pixel x band).  out holds npix * L' doubles. Returns L' or -1. */
+int64_t orc_dwt_approx(const float *cube, int64_t npix, int64_t L, int levels,
+                       const double *h, int ntaps, double *out)
+{
+    int64_t Lp = orc_dwt_out_len(L, levels);
+    if (Lp < 0) return -1;
+#pragma omp parallel
+    {
+        double *buf0 = (double *)malloc(sizeof(double) * (size_t)(L + 1));
+        double *buf1 = (double *)malloc(sizeof(double) * (size_t)(L + 1));
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < npix; ++p) {
+            const float *src = cube + p * L;
+            for (int64_t i = 0; i < L; ++i) buf0[i] = (double)src[i];
+            double *cur = buf0, *nxt = buf1;
+            int64_t n = L;
+            for (int j = 0; j < levels; ++j) {
+                orc_dwt_level(cur, n, h, ntaps, nxt, NULL);
+                n = (n + 1) / 2;
+                double *t = cur; cur = nxt; nxt = t;
+            }
+            memcpy(out + p * Lp, cur, sizeof(double) * (size_t)Lp);
+        }
+        free(buf0);
+        free(buf1);
+    }
+    return Lp;
+}
+
+/* Full decomposition, concatenated as [a_J d_J d_{J-1} ... d_1] (Sec. 3, last paragraph).
+ * Only for chains whose every level input has even length.  Returns 0 or -1. */
+int orc_dwt_full(const double *x, int64_t n, int levels, const double *h, int ntaps,
+                 double *out)
+{
+    int64_t len = n;
+    for (int j = 0; j < levels; ++j) {
+        if (len < 2 || (len & 1)) return -1;
+        len /= 2;
+    }
+    double *cur = (double *)malloc(sizeof(double) * (size_t)n);
+    double *a = (double *)malloc(sizeof(double) * (size_t)n);
+    memcpy(cur, x, sizeof(double) * (size_t)n);
+    len = n;
+    for (int j = 0; j < levels; ++j) {
+        int64_t m = len / 2;
+        /* details of level j+1 go right after the slot reserved for coarser levels */
+        orc_dwt_level(cur, len, h, ntaps, a, out + m);
+        memcpy(cur, a, sizeof(double) * (size_t)m);
+        len = m;
+    }
+    memcpy(out, cur, sizeof(double) * (size_t)len);
+    free(cur);
+    free(a);
+    return 0;
+}
+
+/* Synthesis: the adjoint of one analysis level (x = A^T a + D^T d).  Equal to the inverse
+ * exactly when the analysis matrix is orthogonal, which the tests check. */
+static void orc_level_adjoint(const double *a, const double *d, int64_t n, const double *h,
+                              int ntaps, double *x)
+{
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    for (int64_t k = 0; k < n / 2; ++k) {
+        for (int t = 0; t < ntaps; ++t) {
+            int64_t i = pmod(2 * k - t, n);
+            double g = ((t & 1) ? -1.0 : 1.0) * h[ntaps - 1 - t];
+            x[i] += h[t] * a[k] + g * d[k];
+        }
+    }
+}
+
+int orc_idwt_full(const double *c, int64_t n, int levels, const double *h, int ntaps,
+                  double *out)
+{
+    int64_t len = n;
+    for (int j = 0; j < levels; ++j) {
+        if (len < 2 || (len & 1)) return -1;
+        len /= 2;
+    }
+    double *cur = (double *)malloc(sizeof(double) * (size_t)n);
+    double *nxt = (double *)malloc(sizeof(double) * (size_t)n);
+    memcpy(cur, c, sizeof(double) * (size_t)len);
+    for (int j = levels - 1; j >= 0; --j) {
+        int64_t m = len;              /* current approximation length */
+        orc_level_adjoint(cur, c + m, 2 * m, h, ntaps, nxt);
+        len = 2 * m;
+        memcpy(cur, nxt, sizeof(double) * (size_t)len);
+    }
+    memcpy(out, cur, sizeof(double) * (size_t)n);
+    free(cur);
+    free(nxt);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Window statistics (Sec. 2.1 local background; Sec. 2.2 inner/outer windows)          */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;          /* sample count */
+    double *mean;       /* Lp */
+    double *cov;        /* Lp*Lp, normalised by n */
+} orc_stats;
+
+static int in_box(int64_t dy, int64_t dx, int half)
+{
+    return llabs(dy) <= half && llabs(dx) <= half;
+}
+
+/* Gathers the statistics of one pixel: annulus = outer window minus inner window (both
+ * clipped to the image), and the inner window itself.  Two-pass: mean, then centred
+ * outer products. */
+static void orc_pixel_stats(const double *x, int64_t H, int64_t W, int64_t Lp, int inner,
+                            int outer, int64_t py, int64_t px, orc_stats *ann,
+                            orc_stats *inn)
+{
+    const int ro = outer / 2, ri = inner / 2;
+    const int64_t y0 = py - ro < 0 ? 0 : py - ro, y1 = py + ro >= H ? H - 1 : py + ro;
+    const int64_t x0 = px - ro < 0 ? 0 : px - ro, x1 = px + ro >= W ? W - 1 : px + ro;
+    orc_stats *sets[2] = {ann, inn};
+    for (int s = 0; s < 2; ++s) {
+        orc_stats *st = sets[s];
+        if (!st) continue;
+        st->n = 0;
+        for (int64_t i = 0; i < Lp; ++i) st->mean[i] = 0.0;
+        for (int64_t i = 0; i < Lp * Lp; ++i) st->cov[i] = 0.0;
+    }
+    /* pass 1: sums */
+    for (int64_t y = y0; y <= y1; ++y)
+        for (int64_t xx = x0; xx <= x1; ++xx) {
+            int inside = inner > 0 && in_box(y - py, xx - px, ri);
+            orc_stats *st = inside ? inn : ann;
+            if (!st) continue;
+            const double *v = x + (y * W + xx) * Lp;
+            st->n += 1;
+            for (int64_t i = 0; i < Lp; ++i) st->mean[i] += v[i];
+        }
+    for (int s = 0; s < 2; ++s) {
+        orc_stats *st = sets[s];
+        if (!st || st->n == 0) continue;
+        for (int64_t i = 0; i < Lp; ++i) st->mean[i] /= (double)st->n;
+    }
+    /* pass 2: centred outer products */
+    double *c = (double *)malloc(sizeof(double) * (size_t)Lp);
+    for (int64_t y = y0; y <= y1; ++y)
+        for (int64_t xx = x0; xx <= x1; ++xx) {
+            int inside = inner > 0 && in_box(y - py, xx - px, ri);
+            orc_stats *st = inside ? inn : ann;
+            if (!st) continue;
+            const double *v = x + (y * W + xx) * Lp;
+            for (int64_t i = 0; i < Lp; ++i) c[i] = v[i] - st->mean[i];
+            for (int64_t i = 0; i < Lp; ++i)
+                for (int64_t j = 0; j < Lp; ++j) st->cov[i * Lp + j] += c[i] * c[j];
+        }
+    free(c);
+    for (int s = 0; s < 2; ++s) {
+        orc_stats *st = sets[s];
+        if (!st || st->n == 0) continue;
+        for (int64_t i = 0; i < Lp * Lp; ++i) st->cov[i] /= (double)st->n;
+    }
+}
+
+/* Exposed for tests: statistics of one pixel.  n_out = {n_annulus, n_inner}. */
+void orc_window_stats(const double *x, int64_t H, int64_t W, int64_t Lp, int inner,
+                      int outer, int64_t py, int64_t px, double *mu_a, double *C_a,
+                      double *m_in, double *C_in, int64_t *n_out)
+{
+    orc_stats a = {0, mu_a, C_a}, b = {0, m_in, C_in};
+    orc_pixel_stats(x, H, W, Lp, inner, outer, py, px, &a, &b);
+    n_out[0] = a.n;
+    n_out[1] = b.n;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Loading, Cholesky and the RX forms (eqs. 1 and 5)                                     */
+/* ------------------------------------------------------------------------------------ */
+
+double orc_loading(const double *C, int64_t Lp, double load_rel)
+{
+    double tr = 0.0;
+    for (int64_t i = 0; i < Lp; ++i) tr += C[i * Lp + i];
+    double lam = load_rel * tr / (double)Lp;
+    return lam < ORC_LOAD_FLOOR ? ORC_LOAD_FLOOR : lam;
+}
+
+/* In-place lower Cholesky of A (n x n, row-major).  Returns 0, or -1 if a pivot is not
+ * positive (the matrix is not numerically positive definite). */
+int orc_cholesky(double *A, int64_t n)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int64_t k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+        if (!(s > 0.0)) return -1;
+        double ljj = sqrt(s);
+        A[j * n + j] = ljj;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int64_t k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = t / ljj;
+        }
+    }
+    return 0;
+}
+
+/* ||L^-1 b||^2 = b^T (L L^T)^-1 b by forward substitution. */
+static double orc_quad_form(const double *Lf, int64_t n, const double *b, double *z)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = b[i];
+        for (int64_t k = 0; k < i; ++k) t -= Lf[i * n + k] * z[k];
+        z[i] = t / Lf[i * n + i];
+        s += z[i] * z[i];
+    }
+    return s;
+}
+
+/* LRX (eq. 1 with the annulus as local background) and DWRX (eq. 5) at the listed pixels.
+ * x: H x W x Lp reduced cube.  Either output may be NULL.  A covariance that is not
+ * positive definite after loading gives +inf. */
+void orc_lrx_dwrx(const double *x, int64_t H, int64_t W, int64_t Lp, int inner, int outer,
+                  double load_rel, const int64_t *idx, int64_t nidx, double *lrx,
+                  double *dwrx)
+{
+#pragma omp parallel
+    {
+        size_t l2 = (size_t)(Lp * Lp);
+        double *mu = malloc(sizeof(double) * (size_t)Lp), *C = malloc(sizeof(double) * l2);
+        double *mi = malloc(sizeof(double) * (size_t)Lp), *Ci = malloc(sizeof(double) * l2);
+        double *d = malloc(sizeof(double) * (size_t)Lp), *z = malloc(sizeof(double) * (size_t)Lp);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < nidx; ++t) {
+            int64_t p = idx[t], py = p / W, px = p % W;
+            orc_stats a = {0, mu, C}, b = {0, mi, Ci};
+            orc_pixel_stats(x, H, W, Lp, inner, outer, py, px, &a, dwrx ? &b : NULL);
+            double lam = orc_loading(C, Lp, load_rel);
+            for (int64_t i = 0; i < Lp; ++i) C[i * Lp + i] += lam;
+            int ok = orc_cholesky(C, Lp) == 0;
+            if (lrx) {
+                const double *r = x + p * Lp;
+                for (int64_t i = 0; i < Lp; ++i) d[i] = r[i] - mu[i];
+                lrx[t] = ok ? orc_quad_form(C, Lp, d, z) : INFINITY;
+            }
+            if (dwrx) {
+                for (int64_t i = 0; i < Lp; ++i) d[i] = mi[i] - mu[i];
+                /* |.| of eq. (5) is kept although the loaded form is never negative */
+                dwrx[t] = ok ? fabs(orc_quad_form(C, Lp, d, z)) : INFINITY;
+            }
+        }
+        free(mu); free(C); free(mi); free(Ci); free(d); free(z);
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* DWEST (Sec. 2.2, eqs. 2-4)                                                            */
+/* ------------------------------------------------------------------------------------ */
+
+/* Cyclic-by-row Jacobi eigensolver for a symmetric n x n matrix A (destroyed).
+ * evals[i], eigenvector i in column i of V (row-major n x n).  Stops when the
+ * off-diagonal Frobenius norm is <= tol_rel * ||A||_F.  Returns the sweeps used. */
+int orc_jacobi_eig(int64_t n, double *A, double *evals, double *V, double tol_rel,
+                   int max_sweeps)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+    double fro = 0.0;
+    for (int64_t i = 0; i < n * n; ++i) fro += A[i] * A[i];
+    fro = sqrt(fro);
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        double off = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+        if (sqrt(off) <= tol_rel * fro) break;
+        for (int64_t p = 0; p < n - 1; ++p)
+            for (int64_t q = p + 1; q < n; ++q) {
+                double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                /* rotation that annihilates A[p][q] (Golub & Van Loan, symmetric Schur) */
+                double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int64_t k = 0; k < n; ++k) {       /* A <- A J */
+                    double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int64_t k = 0; k < n; ++k) {       /* A <- J^T A */
+                    double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+                for (int64_t k = 0; k < n; ++k) {       /* V <- V J */
+                    double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    for (int64_t i = 0; i < n; ++i) evals[i] = A[i * n + i];
+    return sweep;
+}
+
+/* DWEST at the listed pixels: C_diff = C_inner - C_annulus (eq. 2), m_diff = m_inner -
+ * m_annulus (eq. 3), projection of m_diff on the eigenvectors with positive eigenvalues
+ * (eq. 4).  score = ||V_P^T m_diff||_2; literal = sum_P |v_i^T m_diff| (eq. 4 with each
+ * eigenvector's sign chosen so that its projection is non-negative); npos = |P|.
+ * Any output may be NULL. */
+void orc_dwest(const double *x, int64_t H, int64_t W, int64_t Lp, int inner, int outer,
+               const int64_t *idx, int64_t nidx, double *score, double *literal,
+               int32_t *npos)
+{
+#pragma omp parallel
+    {
+        size_t l2 = (size_t)(Lp * Lp);
+        double *mu = malloc(sizeof(double) * (size_t)Lp), *C = malloc(sizeof(double) * l2);
+        double *mi = malloc(sizeof(double) * (size_t)Lp), *Ci = malloc(sizeof(double) * l2);
+        double *ev = malloc(sizeof(double) * (size_t)Lp), *V = malloc(sizeof(double) * l2);
+        double *md = malloc(sizeof(double) * (size_t)Lp);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < nidx; ++t) {
+            int64_t p = idx[t], py = p / W, px = p % W;
+            orc_stats a = {0, mu, C}, b = {0, mi, Ci};
+            orc_pixel_stats(x, H, W, Lp, inner, outer, py, px, &a, &b);
+            for (int64_t i = 0; i < (int64_t)l2; ++i) Ci[i] -= C[i];
+            for (int64_t i = 0; i < Lp; ++i) md[i] = mi[i] - mu[i];
+            orc_jacobi_eig(Lp, Ci, ev, V, 1e-14, 100);
+            double emax = 0.0;
+            for (int64_t i = 0; i < Lp; ++i) emax = fmax(emax, fabs(ev[i]));
+            double s2 = 0.0, s1 = 0.0;
+            int32_t np = 0;
+            for (int64_t i = 0; i < Lp; ++i) {
+                if (!(ev[i] > ORC_POS_EIG_REL * emax)) continue;
+                double pr = 0.0;
+                for (int64_t k = 0; k < Lp; ++k) pr += V[k * Lp + i] * md[k];
+                s2 += pr * pr;
+                s1 += fabs(pr);
+                ++np;
+            }
+            if (score) score[t] = sqrt(s2);
+            if (literal) literal[t] = s1;
+            if (npos) npos[t] = np;
+        }
+        free(mu); free(C); free(mi); free(Ci); free(ev); free(V); free(md);
+    }
+}
