@@ -1,0 +1,150 @@
+/*
+ * hsad.h -- C ABI of libhsad, DWT-reduced local hyperspectral anomaly detection on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zare Baghbidi, Jamshidi, Naghsh Nilchi, Homayouni, "Improvement of anomaly
+ * detection algorithms in hyperspectral images using discrete wavelet transform",
+ * SIPIJ 2(4), 2011.  Each pixel spectrum r (L bands, Sec. 2.1) is reduced by a
+ * Daubechies-4 DWT to its approximation coefficients (Sec. 3 eqs. 8-9, Sec. 4).  Local
+ * detectors then score the reduced cube: LRX (Sec. 2.1, eq. 1), DWRX (Sec. 2.3, eq. 5)
+ * and DWEST (Sec. 2.2, eqs. 2-4).
+ *
+ * Conventions shared by every entry point
+ *   - Layout: cubes are dense row-major [y][x][band] float32 (band fastest, "BIP").  The
+ *     reduced cube is [y][x][k], k < L'.  Score maps are [y][x] float32.
+ *   - Pointers named cube/x/approx/scores/mask/ws/... are DEVICE pointers owned by the
+ *     caller.  The library never allocates or frees device memory in these calls.  A call
+ *     validates its arguments on the host, enqueues kernels on `stream` and returns
+ *     without synchronising.  Passing stream 0 means the null stream.
+ *   - Return codes: HSAD_OK (0) or a negative HSAD_E*.  Argument errors are detected
+ *     before any launch, and nothing is enqueued then.  hsad_last_error() gives a
+ *     message for the calling thread.
+ *   - Numerical events inside a pixel are not errors.  A non-finite input gives a
+ *     non-finite score for every window that contains it.  A covariance that is not
+ *     positive definite after loading gives +inf.
+ *   - Windows: odd square windows centred on the pixel and clipped to the image
+ *     (Sec. 2.2, Sec. 5.2).  The background of LRX/DWRX/DWEST is the outer window minus
+ *     the inner window.  inner == 0 means no guard window, so the background
+ *     includes the pixel itself.  inner == 1 excludes only the pixel.
+ *   - Covariances are normalised by the sample count.  Diagonal loading (LRX/DWRX)
+ *     adds lambda * I with lambda = load_rel * tr(C) / L', and lambda is at least 1e-30.
+ */
+#ifndef HSAD_H
+#define HSAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define HSAD_OK 0
+#define HSAD_EINVAL (-1)       /* bad size, window, level, null pointer, n_a = 0 somewhere */
+#define HSAD_ENOMEM (-2)       /* workspace smaller than hsad_workspace_bytes' minimum */
+#define HSAD_EHIP (-3)         /* a HIP launch or runtime call failed */
+#define HSAD_EUNSUPPORTED (-4) /* size or precision combination not built */
+
+/* precision of the window covariance (Gram) */
+#define HSAD_PREC_AUTO 0       /* exact: FP64 sums / FP64 MFMA Gram, FP64 factorisation */
+#define HSAD_PREC_FP32 1       /* FP32 MFMA Gram on exactly centred samples, FP64 factor */
+#define HSAD_PREC_FP64 2       /* same as AUTO, requested explicitly */
+#define HSAD_PREC_GRAM_BF16 3  /* BF16 MFMA Gram (FP32 accumulate), FP64 factorisation */
+#define HSAD_PREC_GRAM_FP16 4  /* FP16 MFMA Gram (FP32 accumulate), FP64 factorisation */
+
+/* operations (for hsad_workspace_bytes) */
+#define HSAD_OP_LRX 1
+#define HSAD_OP_DWRX 2
+#define HSAD_OP_LRX_DWRX 3
+#define HSAD_OP_DWEST 4
+
+#define HSAD_MAX_LP 512        /* largest reduced band count the detectors accept */
+#define HSAD_MAX_WINDOW 63     /* largest outer window side */
+
+typedef struct hsad_window_params {
+    int32_t inner;     /* odd inner (guard) window side, or 0 = none */
+    int32_t outer;     /* odd outer window side, > inner, <= HSAD_MAX_WINDOW */
+    double load_rel;   /* diagonal loading relative to tr(C)/L' (LRX, DWRX); >= 0 */
+    int32_t precision; /* HSAD_PREC_* */
+    int32_t reserved;  /* must be 0 */
+} hsad_window_params;
+
+/* Library version string, e.g. "hsad 0.1.0 gfx950". */
+const char *hsad_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *hsad_last_error(void);
+
+/* Approximation length after `levels` analysis levels (Sec. 3, eq. 9 iterated on the
+ * low-pass branch, Fig. 1).  An odd level input of length n is extended to n+1 by
+ * repeating its last sample, so every level maps n to ceil(n/2).  Host only.
+ * Returns HSAD_EINVAL if L < 1, levels < 0 or a level input would be shorter than 2. */
+int hsad_dwt_out_len(int64_t L, int levels, int64_t *Lp);
+
+/* Level count of Sec. 4 ("until four samples are left"): the largest J whose
+ * approximation keeps at least `target` samples (target = 4 in the paper).  Returns
+ * the level count (0 if L < 2*target-1), or HSAD_EINVAL for L < 1 or target < 1. */
+int hsad_levels_for(int64_t L, int target);
+
+/* Periodised Daubechies-4 (8-tap, 4 vanishing moments) DWT of every pixel spectrum,
+ * keeping only the approximation coefficients (Sec. 4 "approximation matrix").
+ * Each level computes y[k] = sum_m h[m] x[(2k - m) mod n]  (eq. 9, periodic index),
+ * after the odd-length extension above.
+ *   cube   : device, H*W*L float32, [y][x][band]
+ *   approx : device, H*W*L' float32, [y][x][k]; must not overlap cube
+ *   levels : 0 copies the cube
+ * Errors: HSAD_EINVAL (H, W, L < 1, bad levels, null pointers), HSAD_EHIP. */
+int hsad_dwt(const float *cube, int64_t H, int64_t W, int64_t L, int levels, float *approx,
+             hipStream_t stream);
+
+/* Device workspace in bytes for `op` on an H x W x Lp reduced cube with these windows
+ * (0 if none is needed).  Passing more lets the detectors process larger pixel chunks
+ * per launch; passing less than this value but at least the minimum returned for a
+ * 1 x 1 image is allowed and only costs launches.  Returns 0 on invalid arguments. */
+size_t hsad_workspace_bytes(int op, int64_t H, int64_t W, int64_t Lp,
+                            const hsad_window_params *p);
+
+/* LRX: eq. (1) with a local background, the annulus of the pixel.  For pixel r:
+ * mu, C = mean and 1/n covariance of the annulus samples,
+ * score = (r - mu)^T (C + lambda I)^-1 (r - mu).
+ *   x      : device, H*W*Lp float32 reduced (or full-band) cube
+ *   scores : device, H*W float32
+ *   ws     : device workspace of ws_bytes (may be NULL when hsad_workspace_bytes is 0)
+ * Errors: HSAD_EINVAL (sizes, windows, load_rel < 0, reserved != 0, Lp > HSAD_MAX_LP,
+ * an empty annulus for some pixel), HSAD_ENOMEM, HSAD_EUNSUPPORTED, HSAD_EHIP. */
+int hsad_lrx(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+             float *scores, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* DWRX: eq. (5), m_diff^T (C_outer + lambda I)^-1 m_diff with m_diff = inner-window mean
+ * minus annulus mean (eq. 3) and C_outer the annulus covariance.  Needs inner >= 1.
+ * Arguments and errors as hsad_lrx. */
+int hsad_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+              float *scores, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* LRX and DWRX from one pass (they share the annulus statistics and the factorisation).
+ * Either output may be NULL (not both).  Arguments and errors as hsad_lrx. */
+int hsad_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp,
+                  const hsad_window_params *p, float *lrx, float *dwrx, void *ws,
+                  size_t ws_bytes, hipStream_t stream);
+
+/* DWEST, eqs. (2)-(4): C_diff = C_inner - C_annulus, m_diff = m_inner - m_annulus.
+ * The eigenvectors of C_diff with eigenvalue > 1e-12 * max|eigenvalue| ("positive")
+ * are found by an FP64 cyclic Jacobi.  Outputs, each a device [y][x] array:
+ *   scores         : ||V_P^T m_diff||_2 (invariant to eigenvector signs), float32
+ *   scores_literal : sum_P |v_i^T m_diff| (eq. 4 with each v_i signed so that its
+ *                    projection is >= 0), float32, may be NULL
+ *   npos           : |P| per pixel, int32, may be NULL
+ * Needs inner >= 1.  load_rel is ignored (DWEST does not invert a covariance).
+ * Errors as hsad_lrx. */
+int hsad_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+               float *scores, float *scores_literal, int32_t *npos, void *ws,
+               size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSAD_H */

@@ -1,0 +1,19 @@
+"""paper_1201_2025_amd: DWT-reduced local hyperspectral anomaly detection on MI355X.
+
+A thin ctypes binding over ``libhsad.so`` (C ABI in ``include/hsad.h``).  The functions
+carry the C names and only marshal arguments: device pointers of torch tensors and the
+current HIP stream.  Every computation runs in the library's HIP kernels.  When the
+library is not built, every call raises; there is no CPU fallback.
+
+Method: Zare Baghbidi et al., "Improvement of anomaly detection algorithms in
+hyperspectral images using discrete wavelet transform", SIPIJ 2(4), 2011.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    HSAD_EHIP, HSAD_EINVAL, HSAD_ENOMEM, HSAD_EUNSUPPORTED, HSAD_OK, HSAD_OP_DWEST,
+    HSAD_OP_DWRX, HSAD_OP_LRX, HSAD_OP_LRX_DWRX, HSAD_PREC_AUTO, HSAD_PREC_FP32,
+    HSAD_PREC_FP64, HSAD_PREC_GRAM_BF16, HSAD_PREC_GRAM_FP16, HsadError, WindowParams,
+    hsad_dwest, hsad_dwrx, hsad_dwt, hsad_dwt_out_len, hsad_last_error, hsad_levels_for,
+    hsad_lrx, hsad_lrx_dwrx, hsad_version, hsad_workspace_bytes, lib, lib_path,
+)

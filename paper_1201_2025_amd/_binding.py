@@ -1,0 +1,241 @@
+"""ctypes binding of libhsad (argument marshalling only).
+
+Tensors are torch tensors on the GPU.  Each call passes their data pointers and the
+handle of torch's current stream, then raises HsadError on a non-zero return code.
+Workspaces the caller does not supply are allocated here as torch tensors.  That is
+caller-side memory, and the library itself never allocates.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libhsad.so")
+
+HSAD_OK, HSAD_EINVAL, HSAD_ENOMEM, HSAD_EHIP, HSAD_EUNSUPPORTED = 0, -1, -2, -3, -4
+HSAD_PREC_AUTO, HSAD_PREC_FP32, HSAD_PREC_FP64, HSAD_PREC_GRAM_BF16, HSAD_PREC_GRAM_FP16 = 0, 1, 2, 3, 4
+HSAD_OP_LRX, HSAD_OP_DWRX, HSAD_OP_LRX_DWRX, HSAD_OP_DWEST = 1, 2, 3, 4
+
+
+class HsadError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__("%s failed (%d): %s" % (fn, code, msg))
+        self.code = code
+
+
+class WindowParams(ctypes.Structure):
+    _fields_ = [("inner", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("load_rel", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_P = ctypes.POINTER(WindowParams)
+
+# (name, restype, argtypes) for every entry point declared in include/hsad.h
+SIGNATURES = [
+    ("hsad_version", ctypes.c_char_p, []),
+    ("hsad_last_error", ctypes.c_char_p, []),
+    ("hsad_dwt_out_len", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(_i64)]),
+    ("hsad_levels_for", ctypes.c_int, [_i64, ctypes.c_int]),
+    ("hsad_dwt", ctypes.c_int, [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp]),
+    ("hsad_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64, _i64, _i64, _P]),
+    ("hsad_lrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_dwrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_lrx_dwrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_dwest", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+]
+
+
+# step-level entry points used by the tests (exported, not declared in the header)
+INTERNAL_SIGNATURES = [
+    ("hsad_internal_filter", ctypes.c_int, [ctypes.POINTER(ctypes.c_double)]),
+    ("hsad_internal_dwt_force", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_gram", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.c_int, ctypes.c_int,
+                                          _i64, ctypes.c_int, _vp, _vp]),
+]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded libhsad; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise ImportError("libhsad.so is not built (run python -m paper_1201_2025_amd.build)")
+            L = ctypes.CDLL(_LIB_PATH)
+            for name, res, args in SIGNATURES + INTERNAL_SIGNATURES:
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def hsad_version() -> str:
+    return lib().hsad_version().decode()
+
+
+def hsad_last_error() -> str:
+    return lib().hsad_last_error().decode()
+
+
+def _check(fn: str, rc: int):
+    if rc != HSAD_OK:
+        raise HsadError(fn, rc, hsad_last_error())
+
+
+def hsad_dwt_out_len(L: int, levels: int) -> int:
+    out = _i64(0)
+    _check("hsad_dwt_out_len", lib().hsad_dwt_out_len(int(L), int(levels), ctypes.byref(out)))
+    return int(out.value)
+
+
+def hsad_levels_for(L: int, target: int = 4) -> int:
+    rc = lib().hsad_levels_for(int(L), int(target))
+    if rc < 0:
+        _check("hsad_levels_for", rc)
+    return rc
+
+
+def _params(inner, outer, load_rel=1e-6, precision=HSAD_PREC_AUTO) -> WindowParams:
+    return WindowParams(int(inner), int(outer), float(load_rel), int(precision), 0)
+
+
+def hsad_workspace_bytes(op: int, H: int, W: int, Lp: int, inner: int, outer: int,
+                         load_rel: float = 1e-6, precision: int = HSAD_PREC_AUTO) -> int:
+    p = _params(inner, outer, load_rel, precision)
+    return int(lib().hsad_workspace_bytes(int(op), int(H), int(W), int(Lp), ctypes.byref(p)))
+
+
+# ---- torch marshalling ----------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name, dtype=None, ndim=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError("%s must have %d dimensions" % (name, ndim))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_or_null(t, name, dtype):
+    return ctypes.c_void_p(None) if t is None else _dev(t, name, dtype)
+
+
+def hsad_dwt(cube, levels: int, out=None, stream=None):
+    """cube: (H, W, L) float32 GPU tensor -> (H, W, L') approximation coefficients."""
+    torch = _torch()
+    pc = _dev(cube, "cube", torch.float32, 3)
+    H, W, L = cube.shape
+    Lp = hsad_dwt_out_len(L, levels)
+    if out is None:
+        out = torch.empty((H, W, Lp), dtype=torch.float32, device=cube.device)
+    po = _dev(out, "out", torch.float32)
+    if out.numel() != H * W * Lp:
+        raise ValueError("out must hold H*W*L' values")
+    _check("hsad_dwt", lib().hsad_dwt(pc, H, W, L, int(levels), po, _stream(stream)))
+    return out
+
+
+def _workspace(op, x, p, ws):
+    torch = _torch()
+    H, W, Lp = x.shape
+    need = int(lib().hsad_workspace_bytes(op, H, W, Lp, ctypes.byref(p)))
+    if ws is None:
+        if need == 0:
+            return ctypes.c_void_p(None), 0, None
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    return _dev(ws, "ws"), ws.numel() * ws.element_size(), ws
+
+
+def hsad_lrx_dwrx(x, inner: int, outer: int, load_rel: float = 1e-6,
+                  precision: int = HSAD_PREC_AUTO, lrx=True, dwrx=True, ws=None, stream=None):
+    """LRX (eq. 1) and DWRX (eq. 5) maps of a reduced cube x (H, W, L').  Pass a tensor as
+    lrx/dwrx to write into it, True to allocate, None to skip."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    p = _params(inner, outer, load_rel, precision)
+    outs = []
+    for o in (lrx, dwrx):
+        if o is True:
+            o = torch.empty((H, W), dtype=torch.float32, device=x.device)
+        elif o is False:
+            o = None
+        outs.append(o)
+    op = HSAD_OP_LRX_DWRX if outs[1] is not None else HSAD_OP_LRX
+    pws, nws, keep = _workspace(op, x, p, ws)
+    rc = lib().hsad_lrx_dwrx(px, H, W, Lp, ctypes.byref(p),
+                             _ptr_or_null(outs[0], "lrx", torch.float32),
+                             _ptr_or_null(outs[1], "dwrx", torch.float32), pws, nws, _stream(stream))
+    _check("hsad_lrx_dwrx", rc)
+    return outs[0], outs[1]
+
+
+def hsad_lrx(x, inner: int, outer: int, load_rel: float = 1e-6, precision: int = HSAD_PREC_AUTO,
+             out=None, ws=None, stream=None):
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    p = _params(inner, outer, load_rel, precision)
+    out = torch.empty((H, W), dtype=torch.float32, device=x.device) if out is None else out
+    pws, nws, keep = _workspace(HSAD_OP_LRX, x, p, ws)
+    _check("hsad_lrx", lib().hsad_lrx(px, H, W, Lp, ctypes.byref(p), _dev(out, "out", torch.float32),
+                                      pws, nws, _stream(stream)))
+    return out
+
+
+def hsad_dwrx(x, inner: int, outer: int, load_rel: float = 1e-6, precision: int = HSAD_PREC_AUTO,
+              out=None, ws=None, stream=None):
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    p = _params(inner, outer, load_rel, precision)
+    out = torch.empty((H, W), dtype=torch.float32, device=x.device) if out is None else out
+    pws, nws, keep = _workspace(HSAD_OP_DWRX, x, p, ws)
+    _check("hsad_dwrx", lib().hsad_dwrx(px, H, W, Lp, ctypes.byref(p), _dev(out, "out", torch.float32),
+                                        pws, nws, _stream(stream)))
+    return out
+
+
+def hsad_dwest(x, inner: int, outer: int, literal: bool = True, npos: bool = True, ws=None,
+               stream=None):
+    """DWEST (eqs. 2-4): returns (score, literal or None, npos or None)."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    p = _params(inner, outer, 0.0, HSAD_PREC_AUTO)
+    s = torch.empty((H, W), dtype=torch.float32, device=x.device)
+    lit = torch.empty((H, W), dtype=torch.float32, device=x.device) if literal else None
+    npo = torch.empty((H, W), dtype=torch.int32, device=x.device) if npos else None
+    pws, nws, keep = _workspace(HSAD_OP_DWEST, x, p, ws)
+    rc = lib().hsad_dwest(px, H, W, Lp, ctypes.byref(p), _dev(s, "scores", torch.float32),
+                          _ptr_or_null(lit, "scores_literal", torch.float32),
+                          _ptr_or_null(npo, "npos", torch.int32), pws, nws, _stream(stream))
+    _check("hsad_dwest", rc)
+    return s, lit, npo

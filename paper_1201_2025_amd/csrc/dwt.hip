@@ -1,0 +1,342 @@
+// dwt.hip -- per-pixel Daubechies-4 approximation (Sec. 3 eqs. 8-9, Fig. 1; Sec. 4).
+//
+// Two kernels produce the same linear map, the J-level low-pass cascade.  At every
+// level a[k] = sum_m h[m] x[(2k - m) mod n]; an odd n is first extended by repeating
+// its last sample.
+//
+//  * dwt_equiv_kernel<LP, VEC>: used when the output is short (L' <= 16).  The J-level
+//    cascade is linear, so it collapses into one equivalent-filter matrix A_J (L' x L).
+//    This is the noble identity of multirate filter banks, with the periodisation and
+//    odd-length rule folded in.  The matrix is built once per (L, J) on the host in
+//    FP64 and kept in device memory.  Each lane owns one pixel and streams that
+//    pixel's spectrum with VEC-wide loads; all lanes fetch the same coefficients
+//    (uniform, scalar cache).  It does L'*L FMAs per pixel, fewer than the cascade's
+//    8*sum_j L_j for the deep decompositions that give a short L'.  The kernel is
+//    bound by HBM, and each lane's loads walk whole 128-byte lines.
+//  * dwt_cascade_kernel: for longer outputs.  A workgroup stages P pixel spectra in
+//    LDS with coalesced loads, then runs the levels in LDS with ping-pong buffers.
+//    Each level is 8 taps per output; the workgroup barriers between levels.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace hsad {
+
+// ------------------------------------------------------------------------------------
+// host: equivalent-filter matrix
+// ------------------------------------------------------------------------------------
+static void cascade_level(const double *x, int64_t n, const double *h, double *y)
+{
+    const int64_t ne = n + (n & 1), m = ne / 2;
+    for (int64_t k = 0; k < m; ++k) {
+        double s = 0.0;
+        for (int t = 0; t < 8; ++t) {
+            int64_t i = (2 * k - t) % ne;
+            if (i < 0) i += ne;
+            s += h[t] * (i < n ? x[i] : x[n - 1]);
+        }
+        y[k] = s;
+    }
+}
+
+void dwt_composite_matrix(int64_t L, int levels, double *A)
+{
+    const double *h = db4_filter();
+    std::vector<double> a(L + 1), b(L + 1);
+    int64_t Lp = L;
+    for (int j = 0; j < levels; ++j) Lp = (Lp + 1) / 2;
+    for (int64_t i = 0; i < L; ++i) {
+        std::fill(a.begin(), a.end(), 0.0);
+        a[i] = 1.0;
+        int64_t n = L;
+        for (int j = 0; j < levels; ++j) {
+            cascade_level(a.data(), n, h, b.data());
+            n = (n + 1) / 2;
+            std::swap(a, b);
+        }
+        for (int64_t k = 0; k < Lp; ++k) A[k * L + i] = a[k];
+    }
+}
+
+// Device-resident cache of equivalent-filter matrices (append-only arena, FP64).
+static constexpr size_t kCoefArenaDoubles = 1u << 19;   // 4 MiB per device
+__device__ double g_coef_arena[kCoefArenaDoubles];
+
+namespace {
+struct CoefKey {
+    int dev;
+    int64_t L;
+    int levels;
+    int vec;
+    bool operator<(const CoefKey &o) const
+    {
+        if (dev != o.dev) return dev < o.dev;
+        if (L != o.L) return L < o.L;
+        if (levels != o.levels) return levels < o.levels;
+        return vec < o.vec;
+    }
+};
+struct CoefEntry {
+    size_t offset;               // in doubles
+    std::vector<double> host;    // kept alive for the asynchronous upload
+};
+std::mutex g_coef_mu;
+std::map<CoefKey, CoefEntry> g_coef;
+std::map<int, size_t> g_coef_used;
+}  // namespace
+
+// Returns a device pointer to the interleaved [L/VEC][L'][VEC] matrix, or nullptr when the
+// arena is full (the caller then uses the cascade kernel).
+static const double *composite_coefs(int64_t L, int levels, int64_t Lp, int vec, hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_coef_mu);
+    double *base = nullptr;
+    if (hipGetSymbolAddress((void **)&base, HIP_SYMBOL(g_coef_arena)) != hipSuccess) return nullptr;
+    CoefKey key{dev, L, levels, vec};
+    auto it = g_coef.find(key);
+    if (it != g_coef.end()) return base + it->second.offset;
+    const size_t nfl = (size_t)(Lp * L);
+    size_t &used = g_coef_used[dev];
+    size_t off = (used + 31) & ~(size_t)31;      // 256-byte aligned entries
+    if (off + nfl > kCoefArenaDoubles) return nullptr;
+    std::vector<double> A((size_t)(Lp * L));
+    dwt_composite_matrix(L, levels, A.data());
+    CoefEntry e;
+    e.offset = off;
+    e.host.resize(nfl);
+    const int64_t nc = L / vec;
+    for (int64_t c = 0; c < nc; ++c)
+        for (int64_t k = 0; k < Lp; ++k)
+            for (int v = 0; v < vec; ++v)
+                e.host[(size_t)((c * Lp + k) * vec + v)] = A[(size_t)(k * L + c * vec + v)];
+    if (hipMemcpyAsync(base + off, e.host.data(), nfl * sizeof(double), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return nullptr;
+    if (hipStreamSynchronize(s) != hipSuccess) return nullptr;   // once per (L, J)
+    used = off + nfl;
+    auto res = g_coef.emplace(key, std::move(e));
+    return base + res.first->second.offset;
+}
+
+// ------------------------------------------------------------------------------------
+// device: equivalent-filter kernel
+// ------------------------------------------------------------------------------------
+typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+template <int VEC> struct VecT;
+template <> struct VecT<1> { using T = float; };
+template <> struct VecT<2> { using T = fv2; };
+template <> struct VecT<4> { using T = fv4; };
+
+template <int VEC>
+__device__ __forceinline__ float lane_elem(const typename VecT<VEC>::T &v, int e)
+{
+    if constexpr (VEC == 1) {
+        return v;
+    } else {
+        return v[e];
+    }
+}
+
+template <int LP, int VEC>
+__global__ __launch_bounds__(256) void dwt_equiv_kernel(const float *__restrict__ cube,
+                                                        int64_t npix, int L,
+                                                        const double *__restrict__ coef,
+                                                        float *__restrict__ out)
+{
+    using V = typename VecT<VEC>::T;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    const V *src = reinterpret_cast<const V *>(cube + p * (int64_t)L);
+    // FP64 accumulation: the only rounding left is the final FP32 store.  The detectors
+    // downstream divide by the noise level, so an FP32 running sum (~1e-6 relative of a
+    // coefficient) would already be visible in their scores; FP64 FMAs are free here
+    // because the kernel waits on HBM.
+    double acc[LP];
+#pragma unroll
+    for (int k = 0; k < LP; ++k) acc[k] = 0.0;
+    const int nc = L / VEC;
+    constexpr int U = 8;   // 8 chunks in flight per lane: 8*VEC*4 bytes
+    int c = 0;
+    for (; c + U <= nc; c += U) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + c + u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double *cf = coef + (size_t)(c + u) * (LP * VEC);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const double xv = (double)lane_elem<VEC>(v[u], e);
+#pragma unroll
+                for (int k = 0; k < LP; ++k) acc[k] = fma(cf[k * VEC + e], xv, acc[k]);
+            }
+        }
+    }
+    for (; c < nc; ++c) {
+        V v = src[c];
+        const double *cf = coef + (size_t)c * (LP * VEC);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const double xv = (double)lane_elem<VEC>(v, e);
+#pragma unroll
+            for (int k = 0; k < LP; ++k) acc[k] = fma(cf[k * VEC + e], xv, acc[k]);
+        }
+    }
+    float *dst = out + p * LP;
+    if constexpr (LP % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < LP; k += 4)
+            *reinterpret_cast<float4 *>(dst + k) =
+                make_float4((float)acc[k], (float)acc[k + 1], (float)acc[k + 2], (float)acc[k + 3]);
+    } else if constexpr (LP % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < LP; k += 2)
+            *reinterpret_cast<float2 *>(dst + k) = make_float2((float)acc[k], (float)acc[k + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < LP; ++k) dst[k] = (float)acc[k];
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// device: LDS cascade kernel
+// ------------------------------------------------------------------------------------
+struct Taps {
+    double h[8];
+};
+
+__global__ __launch_bounds__(256) void dwt_cascade_kernel(const float *__restrict__ cube,
+                                                          int64_t npix, int L, int levels,
+                                                          int Lp, int P, Taps taps,
+                                                          float *__restrict__ out)
+{
+    extern __shared__ double ldsd[];
+    const int S0 = L + 1;                 // odd stride of the level-0 buffer
+    const int S1 = (L + 1) / 2 + 1;       // stride of the level-1 buffer
+    double *buf0 = ldsd;                  // P * S0, FP64 levels (see dwt_equiv_kernel)
+    double *buf1 = ldsd + (size_t)P * S0; // P * S1
+    const int64_t p0 = (int64_t)blockIdx.x * P;
+    const int np = (int)((npix - p0) < P ? (npix - p0) : P);
+    const int tid = threadIdx.x;
+
+    // coalesced load of np contiguous spectra
+    const float *src = cube + p0 * (int64_t)L;
+    const int total = np * L;
+    for (int t = tid; t < total; t += 256) {
+        const int p = t / L, i = t - p * L;
+        buf0[p * S0 + i] = (double)src[t];
+    }
+    __syncthreads();
+
+    double *cur = buf0, *nxt = buf1;
+    int scur = S0, snxt = S1;
+    int n = L;
+    for (int j = 0; j < levels; ++j) {
+        const int ne = n + (n & 1), m = ne / 2;
+        // lanes over k (64 per pixel row), 4 pixel rows per pass of 256 threads
+        for (int p = tid >> 6; p < np; p += 4) {
+            const double *x = cur + p * scur;
+            for (int k = tid & 63; k < m; k += 64) {
+                double s = 0.0;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    int i = 2 * k - t;       // >= -7; short levels (ne < 8) wrap twice
+                    while (i < 0) i += ne;
+                    s = fma(taps.h[t], x[i < n ? i : n - 1], s);
+                }
+                nxt[p * snxt + k] = s;
+            }
+        }
+        __syncthreads();
+        double *tp = cur; cur = nxt; nxt = tp;
+        int ts = scur; scur = snxt; snxt = ts;
+        n = m;
+    }
+    // coalesced store of np * Lp outputs
+    float *dst = out + p0 * (int64_t)Lp;
+    for (int t = tid; t < np * Lp; t += 256) {
+        const int p = t / Lp, k = t - p * Lp;
+        dst[t] = (float)cur[p * scur + k];
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// dispatch
+// ------------------------------------------------------------------------------------
+template <int LP>
+static int launch_equiv(const float *cube, int64_t npix, int64_t L, const double *coef, int vec,
+                        float *out, hipStream_t s)
+{
+    dim3 grid((unsigned)((npix + 255) / 256)), block(256);
+    if (vec == 4)
+        hipLaunchKernelGGL((dwt_equiv_kernel<LP, 4>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+    else if (vec == 2)
+        hipLaunchKernelGGL((dwt_equiv_kernel<LP, 2>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+    else
+        hipLaunchKernelGGL((dwt_equiv_kernel<LP, 1>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+    return check_launch("dwt_equiv_kernel");
+}
+
+static int launch_equiv_lp(int64_t Lp, const float *cube, int64_t npix, int64_t L,
+                           const double *coef, int vec, float *out, hipStream_t s)
+{
+    switch (Lp) {
+#define HSAD_EQ_CASE(n) \
+    case n: return launch_equiv<n>(cube, npix, L, coef, vec, out, s);
+        HSAD_EQ_CASE(1) HSAD_EQ_CASE(2) HSAD_EQ_CASE(3) HSAD_EQ_CASE(4) HSAD_EQ_CASE(5)
+        HSAD_EQ_CASE(6) HSAD_EQ_CASE(7) HSAD_EQ_CASE(8) HSAD_EQ_CASE(9) HSAD_EQ_CASE(10)
+        HSAD_EQ_CASE(11) HSAD_EQ_CASE(12) HSAD_EQ_CASE(13) HSAD_EQ_CASE(14) HSAD_EQ_CASE(15)
+        HSAD_EQ_CASE(16)
+#undef HSAD_EQ_CASE
+    default: return HSAD_EUNSUPPORTED;
+    }
+}
+
+static int g_dwt_force = -1;   // -1 auto, 0 cascade, 1 equivalent filter (tests/tuning)
+
+int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t Lp,
+               float *approx, hipStream_t s)
+{
+    if (npix == 0) return HSAD_OK;
+    if (levels == 0) {
+        if (hipMemcpyAsync(approx, cube, (size_t)(npix * L) * sizeof(float),
+                           hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return fail(HSAD_EHIP, "hsad_dwt: device copy failed");
+        return HSAD_OK;
+    }
+    const bool equiv_ok = Lp <= 16;
+    if (equiv_ok && g_dwt_force != 0) {
+        const int vec = (L % 4 == 0) ? 4 : ((L % 2 == 0) ? 2 : 1);
+        const double *coef = composite_coefs(L, levels, Lp, vec, s);
+        if (coef) return launch_equiv_lp(Lp, cube, npix, L, coef, vec, approx, s);
+    }
+    // cascade: size the pixel tile so that both ping-pong buffers fit in 64 KiB of LDS
+    const int64_t per_pix = (L + 1) + ((L + 1) / 2 + 1);
+    int64_t P = (64 * 1024 / 8) / per_pix;
+    if (P > 64) P = 64;
+    if (P < 1) return fail(HSAD_EUNSUPPORTED, "hsad_dwt: L too large for the LDS cascade");
+    Taps taps;
+    const double *h = db4_filter();
+    for (int t = 0; t < 8; ++t) taps.h[t] = h[t];
+    const size_t shmem = (size_t)(P * per_pix) * sizeof(double);
+    dim3 grid((unsigned)((npix + P - 1) / P)), block(256);
+    hipLaunchKernelGGL(dwt_cascade_kernel, grid, block, shmem, s, cube, npix, (int)L, levels,
+                       (int)Lp, (int)P, taps, approx);
+    return check_launch("dwt_cascade_kernel");
+}
+
+}  // namespace hsad
+
+extern "C" int hsad_internal_dwt_force(int mode)
+{
+    hsad::g_dwt_force = mode;
+    return 0;
+}

@@ -1,0 +1,84 @@
+// generic.hip -- chunked orchestration of the matrix-core path: Gram -> Cholesky (LRX,
+// DWRX) or Gram -> Jacobi (DWEST).  Pixels are processed in chunks that fit the caller's
+// workspace; each chunk is two launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace hsad {
+
+size_t gram_lds_per_wave(int64_t Lp, int prec);
+int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, int mode,
+                int prec, int64_t pix0, int npix, double *ws, hipStream_t s);
+size_t chol_smem(int64_t Lp);
+int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
+                float *dwrx, hipStream_t s);
+size_t jacobi_smem(int64_t n);
+int jacobi_launch(const double *ws, int64_t n, int npix, int64_t pix0, float *score,
+                  float *literal, int32_t *npos, hipStream_t s);
+
+size_t generic_ws_per_pixel(int64_t Lp, GramMode)
+{
+    return (size_t)((Lp + 2) * Lp) * sizeof(double);
+}
+
+static int64_t chunk_pixels(int64_t total, int64_t Lp, size_t ws_bytes)
+{
+    int64_t P = (int64_t)(ws_bytes / generic_ws_per_pixel(Lp, GRAM_LRX));
+    if (P > total) P = total;
+    if (P > (1 << 30)) P = 1 << 30;
+    return P;
+}
+
+int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                     double load_rel, GramPrec prec, float *lrx, float *dwrx, void *ws,
+                     size_t ws_bytes, hipStream_t s)
+{
+    if (gram_lds_per_wave(Lp, prec) > 160 * 1024 || chol_smem(Lp) > 160 * 1024)
+        return fail(HSAD_EUNSUPPORTED, "generic path: L' too large");
+    const int64_t total = H * W;
+    const int64_t P = chunk_pixels(total, Lp, ws_bytes);
+    if (P < 1) return fail(HSAD_ENOMEM, "generic path: workspace below one pixel");
+    for (int64_t p0 = 0; p0 < total; p0 += P) {
+        const int n = (int)((total - p0) < P ? (total - p0) : P);
+        int rc = gram_launch(x, H, W, Lp, w, GRAM_LRX, prec, p0, n, (double *)ws, s);
+        if (rc) return rc;
+        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s);
+        if (rc) return rc;
+    }
+    return HSAD_OK;
+}
+
+int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                  float *score, float *literal, int32_t *npos, void *ws, size_t ws_bytes,
+                  hipStream_t s)
+{
+    if (jacobi_smem(Lp) > 160 * 1024 || gram_lds_per_wave(Lp, GP_FP64) > 160 * 1024)
+        return fail(HSAD_EUNSUPPORTED, "hsad_dwest: L' above the Jacobi LDS limit (88)");
+    const int64_t total = H * W;
+    const int64_t P = chunk_pixels(total, Lp, ws_bytes);
+    if (P < 1) return fail(HSAD_ENOMEM, "hsad_dwest: workspace below one pixel");
+    for (int64_t p0 = 0; p0 < total; p0 += P) {
+        const int n = (int)((total - p0) < P ? (total - p0) : P);
+        int rc = gram_launch(x, H, W, Lp, w, GRAM_DWEST, GP_FP64, p0, n, (double *)ws, s);
+        if (rc) return rc;
+        rc = jacobi_launch((const double *)ws, Lp, n, p0, score, literal, npos, s);
+        if (rc) return rc;
+    }
+    return HSAD_OK;
+}
+
+}  // namespace hsad
+
+// ---- step-level entry points for tests (not part of the public header) ----
+extern "C" int hsad_internal_gram(const float *x, int64_t H, int64_t W, int64_t Lp,
+                                  const hsad_window_params *p, int mode, int prec, int64_t pix0,
+                                  int npix, double *ws, hipStream_t s)
+{
+    using namespace hsad;
+    if (!x || !p || !ws || H < 1 || W < 1 || Lp < 1 || Lp > HSAD_MAX_LP || npix < 1 ||
+        pix0 < 0 || pix0 + npix > H * W || (p->outer & 1) == 0 || p->inner >= p->outer)
+        return fail(HSAD_EINVAL, "hsad_internal_gram: bad arguments");
+    Windows w{p->inner, p->outer, p->inner / 2, p->outer / 2};
+    return gram_launch(x, H, W, Lp, w, mode, prec, pix0, npix, ws, s);
+}

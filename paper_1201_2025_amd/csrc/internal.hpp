@@ -1,0 +1,57 @@
+// internal.hpp -- shared declarations of the libhsad translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/hsad.h"
+
+namespace hsad {
+
+// ---- error reporting (thread-local message, see hsad_last_error) ----
+void set_error(const std::string &msg);
+void clear_error();
+int fail(int code, const std::string &msg);
+int check_launch(const char *what);
+// Raises a kernel's dynamic-LDS limit when a launch needs more than the 64 KiB default.
+int allow_lds(const void *kernel, size_t bytes, const char *what);
+
+// ---- filter design (api.hip) ----
+// 8-tap Daubechies low-pass, time order of eq. (9).
+const double *db4_filter();
+
+// ---- DWT (dwt.hip) ----
+// Composite (equivalent-filter) matrix of `levels` levels applied to length L:
+// Lp x L, row-major, double.  Pushes unit vectors through the cascade with the
+// odd-length extension.
+void dwt_composite_matrix(int64_t L, int levels, double *A /* Lp*L */);
+int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t Lp,
+               float *approx, hipStream_t s);
+
+// ---- window geometry ----
+struct Windows {
+    int inner, outer;
+    int ri, ro;   // half sizes
+};
+
+// ---- small-L' fused box-sum detector (box.hip) ----
+bool box_supported(int64_t Lp, const Windows &w);
+int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                        double load_rel, float *lrx, float *dwrx, hipStream_t s);
+
+// ---- generic Gram + factorisation path (gram.hip, chol.hip, jacobi.hip) ----
+enum GramMode { GRAM_LRX = 0, GRAM_DWEST = 1 };
+enum GramPrec { GP_FP64 = 0, GP_FP32 = 1, GP_BF16 = 2, GP_FP16 = 3 };
+
+// Bytes of workspace per pixel and the fixed part for the generic path.
+size_t generic_ws_per_pixel(int64_t Lp, GramMode mode);
+int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                     double load_rel, GramPrec prec, float *lrx, float *dwrx, void *ws,
+                     size_t ws_bytes, hipStream_t s);
+int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                  float *score, float *literal, int32_t *npos, void *ws, size_t ws_bytes,
+                  hipStream_t s);
+
+}  // namespace hsad

@@ -1,0 +1,117 @@
+"""C-ABI contract checks that need no GPU: the library loads and exports every symbol the
+header declares.  Host-only helpers agree with the oracle.  Bad arguments are rejected
+before any launch, with a message.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1201_2025_amd as hs
+from paper_1201_2025_amd import _binding
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hsad.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsad_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hs.lib()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert {n for n, _, _ in _binding.SIGNATURES} == set(names)
+
+
+def test_version():
+    assert hs.hsad_version().startswith("hsad ") and "gfx950" in hs.hsad_version()
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 7, 64, 100, 189, 224, 430, 1000])
+def test_out_len_and_levels_match_oracle(L):
+    for lv in range(0, 12):
+        o = oracle.dwt_out_len(L, lv)
+        if o < 0:
+            with pytest.raises(hs.HsadError) as e:
+                hs.hsad_dwt_out_len(L, lv)
+            assert e.value.code == hs.HSAD_EINVAL and "level" in str(e.value)
+        else:
+            assert hs.hsad_dwt_out_len(L, lv) == o
+    assert hs.hsad_levels_for(L) == oracle.levels_for(L)
+
+
+def test_library_filter_matches_oracle_derivation():
+    # two independent derivations: spectral factorisation (oracle) and Gauss-Newton from
+    # the printed table (library)
+    h = (ctypes.c_double * 8)()
+    assert hs.lib().hsad_internal_filter(h) == 0
+    assert np.max(np.abs(np.array(h[:]) - oracle.DB4)) < 2e-16
+
+
+def _p(inner, outer, load=1e-6, prec=0, reserved=0):
+    return hs.WindowParams(inner, outer, load, prec, reserved)
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("inner,outer,load,prec,res,H,W,Lp,msg", [
+    (3, 4, 1e-6, 0, 0, 8, 8, 4, "outer"),
+    (4, 9, 1e-6, 0, 0, 8, 8, 4, "inner"),
+    (9, 9, 1e-6, 0, 0, 8, 8, 4, "inner"),
+    (3, 9, -1.0, 0, 0, 8, 8, 4, "load_rel"),
+    (3, 9, float("nan"), 0, 0, 8, 8, 4, "load_rel"),
+    (3, 9, 1e-6, 7, 0, 8, 8, 4, "precision"),
+    (3, 9, 1e-6, 0, 1, 8, 8, 4, "reserved"),
+    (3, 9, 1e-6, 0, 0, 0, 8, 4, ">= 1"),
+    (3, 9, 1e-6, 0, 0, 3, 3, 4, "annulus"),
+    (3, 65, 1e-6, 0, 0, 8, 8, 4, "outer"),
+])
+def test_window_validation(inner, outer, load, prec, res, H, W, Lp, msg):
+    L = hs.lib()
+    p = _p(inner, outer, load, prec, res)
+    rc = L.hsad_lrx_dwrx(FAKE, H, W, Lp, ctypes.byref(p), FAKE, FAKE, FAKE, 1 << 30, None)
+    assert rc == hs.HSAD_EINVAL
+    assert msg in hs.hsad_last_error()
+    assert L.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, H, W, Lp, ctypes.byref(p)) == 0
+
+
+def test_other_argument_errors():
+    L = hs.lib()
+    p = _p(3, 9)
+    assert L.hsad_lrx_dwrx(FAKE, 8, 8, 4, None, FAKE, FAKE, None, 0, None) == hs.HSAD_EINVAL
+    assert L.hsad_lrx_dwrx(None, 8, 8, 4, ctypes.byref(p), FAKE, FAKE, None, 0, None) == hs.HSAD_EINVAL
+    assert L.hsad_lrx_dwrx(FAKE, 8, 8, 4, ctypes.byref(p), None, None, None, 0, None) == hs.HSAD_EINVAL
+    assert L.hsad_lrx(FAKE, 8, 8, 4, ctypes.byref(p), None, None, 0, None) == hs.HSAD_EINVAL
+    q = _p(0, 9)
+    assert L.hsad_dwrx(FAKE, 8, 8, 4, ctypes.byref(q), FAKE, None, 0, None) == hs.HSAD_EINVAL
+    assert "inner" in hs.hsad_last_error()
+    assert L.hsad_dwest(FAKE, 8, 8, 4, ctypes.byref(q), FAKE, None, None, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    # generic path without workspace
+    assert L.hsad_lrx(FAKE, 8, 8, 20, ctypes.byref(p), FAKE, None, 0, None) == hs.HSAD_ENOMEM
+    assert L.hsad_lrx(FAKE, 8, 8, 600, ctypes.byref(p), FAKE, FAKE, 1 << 30, None) == hs.HSAD_EUNSUPPORTED
+    assert L.hsad_dwt(FAKE, 8, 8, 224, 9, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_dwt(None, 8, 8, 224, 2, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_dwt(FAKE, 0, 8, 224, 2, FAKE, None) == hs.HSAD_EINVAL
+
+
+def test_workspace_sizes():
+    L = hs.lib()
+    p = _p(5, 15)
+    # box path (exact, L' <= 8) needs none; the generic path needs (L'+2) L' doubles/pixel
+    assert L.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, 512, 512, 4, ctypes.byref(p)) == 0
+    n = L.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, 64, 64, 14, ctypes.byref(p))
+    assert n == 64 * 64 * 16 * 14 * 8
+    big = L.hsad_workspace_bytes(hs.HSAD_OP_LRX, 512, 512, 224, ctypes.byref(p))
+    assert 0 < big <= (1 << 30) and big % (226 * 224 * 8) == 0
+    pb = _p(5, 15, prec=hs.HSAD_PREC_GRAM_BF16)
+    assert L.hsad_workspace_bytes(hs.HSAD_OP_LRX, 64, 64, 4, ctypes.byref(pb)) > 0
+    assert L.hsad_workspace_bytes(hs.HSAD_OP_DWEST, 64, 64, 4, ctypes.byref(p)) > 0

@@ -1,0 +1,89 @@
+"""GPU parity of hsad_dwt against the FP64 oracle (Sec. 3 eqs. 8-9, Sec. 4).
+
+Bound: per-pixel normwise relative error <= 1e-5 (FP32 arithmetic).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1201_2025_amd as hs
+from gpu_util import dwt_rel_err, sample_pixels, scene
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _gpu_dwt(cube, levels):
+    import torch
+    t = torch.from_numpy(cube).cuda()
+    out = hs.hsad_dwt(t, levels)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+CASES = [(37, 29, 224, lv) for lv in range(0, 7)] + [
+    (13, 50, 189, 5), (9, 7, 189, 1), (5, 300, 100, 3), (21, 19, 430, 2), (30, 11, 131, 4),
+    (17, 16, 430, 5), (3, 5, 2, 1), (4, 4, 3, 1), (2, 3, 7, 3), (1, 1, 224, 6), (16, 16, 64, 4),
+    (7, 9, 1001, 9), (11, 3, 250, 3)]
+
+
+@pytest.mark.parametrize("H,W,L,levels", CASES)
+def test_dwt_parity(H, W, L, levels):
+    print("dwt parity", H, W, L, levels, flush=True)
+    s = scene(1000 + L + levels, H, W, L)
+    got = _gpu_dwt(s.cube, levels)
+    ref = oracle.dwt_approx(s.cube, levels)
+    assert got.shape == ref.shape
+    assert dwt_rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("L,levels", [(224, 6), (224, 4), (189, 5), (131, 5)])
+def test_dwt_equivalent_filter_and_cascade_agree(L, levels):
+    print("dwt kernels", L, levels, flush=True)
+    s = scene(77, 19, 23, L)
+    ref = oracle.dwt_approx(s.cube, levels)
+    L_ = hs.lib()
+    try:
+        L_.hsad_internal_dwt_force(ctypes.c_int(0))
+        casc = _gpu_dwt(s.cube, levels)
+        L_.hsad_internal_dwt_force(ctypes.c_int(1))
+        eq = _gpu_dwt(s.cube, levels)
+    finally:
+        L_.hsad_internal_dwt_force(ctypes.c_int(-1))
+    assert dwt_rel_err(casc, ref) <= TOL
+    assert dwt_rel_err(eq, ref) <= TOL
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6])
+def test_dwt_full_size_sampled(levels):
+    # the 512 x 512 x 224 cube at the bench's launch configuration; the oracle is evaluated
+    # on a sample of pixels only
+    import torch
+    print("dwt full size", levels, flush=True)
+    from paper_1201_2025_amd import synth
+    c = synth.CONFIGS["C2"]
+    s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"],
+                         n_blob=c["n_blob"])
+    got = _gpu_dwt(s.cube, levels).reshape(-1, hs.hsad_dwt_out_len(224, levels))
+    idx = sample_pixels(512, 512, 3000, seed=levels)
+    ref = oracle.dwt_approx(s.cube.reshape(-1, 224)[idx], levels)
+    assert dwt_rel_err(got[idx], ref) <= TOL
+
+
+def test_dwt_deterministic():
+    import torch
+    s = scene(5, 33, 31, 224)
+    a = _gpu_dwt(s.cube, 6)
+    b = _gpu_dwt(s.cube, 6)
+    assert np.array_equal(a, b)
+
+
+def test_dwt_nan_stays_in_its_pixel():
+    s = scene(6, 8, 9, 224)
+    cube = s.cube.copy()
+    cube[3, 4, 17] = np.nan
+    got = _gpu_dwt(cube, 4)
+    bad = ~np.isfinite(got).all(axis=2)
+    assert bad[3, 4] and bad.sum() == 1
