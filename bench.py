@@ -1,0 +1,279 @@
+"""Throughput of the DWT-reduced local anomaly detector on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--level J] [--no-sweep] [--no-cpu]
+
+Workload: a 512 x 512 x 224 FP32 synthetic cube (8 endmembers, 200 implanted anomaly
+objects including 2x2 blobs).  One step is the detection hot path over the cube:
+  1. hsad_dwt        per-pixel db4 DWT to L' approximation coefficients (Sec. 4);
+  2. hsad_lrx_dwrx   LRX (eq. 1) and DWRX (eq. 5) with a 5x5 inner / 15x15 outer window,
+                     from one pass of window statistics;
+  3. hsad_threshold  eq. (12) cut-off tau = mu + 3 sigma and the anomaly mask.
+The default depth is the paper's rule, "until four samples are left": J = 6, L' = 4.
+Inputs are resident in HBM before timing.  Two copies of the cube alternate between
+steps so that the 256 MB Infinity Cache cannot hold the input.  One JSON line is
+printed.  Beside the timed step, the script also measures:
+  * the same detector at full band (no DWT, L' = 224, exact FP64 Gram) on the same cube;
+  * the DWT levels 1..5 sweep;
+  * ROC AUC of the GPU scores minus that of the FP64 oracle scores (truth mask known);
+  * the FP64 CPU oracle on the host cores, for the same workload (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+METRIC = "pixels/s for DWT+LRX at 512×512×224 vs full-band GPU; ROC AUC delta vs FP64"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--level", type=int, default=None, help="DWT levels (default: paper rule)")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fullband", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1201_2025_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        e = d.get(kernel, {}).get(workload)
+        if not e or e.get("source_hash") != src_hash:
+            return None
+        return float(e["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the per-GPU "
+              "workload is the whole cube; see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1201_2025_amd as hs
+    from paper_1201_2025_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    c = synth.CONFIGS["C2"]
+    H, W, L = c["H"], c["W"], c["L"]
+    J = hs.hsad_levels_for(L, 4) if args.level is None else args.level
+    Lp = hs.hsad_dwt_out_len(L, J)
+    inner, outer, load = c["inner"], c["outer"], c["load_rel"]
+    scene = synth.make_scene(c["seed"], H, W, L, K=c["K"], n_single=c["n_single"],
+                             n_blob=c["n_blob"])
+    npix = H * W
+
+    cubes = [torch.from_numpy(scene.cube).to(dev) for _ in range(2)]
+    approx = torch.empty((H, W, Lp), dtype=torch.float32, device=dev)
+    lrx = torch.empty((H, W), dtype=torch.float32, device=dev)
+    dwrx = torch.empty((H, W), dtype=torch.float32, device=dev)
+    mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    ws_bytes = hs.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, H, W, Lp, inner, outer, load)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    th_ws = torch.empty(hs.hsad_threshold_workspace_bytes(npix), dtype=torch.uint8, device=dev)
+    th_out = torch.empty(4, dtype=torch.float64, device=dev)
+
+    def step(i, ev=None):
+        if ev is not None:
+            ev[0].record()
+        hs.hsad_dwt(cubes[i & 1], J, out=approx)
+        if ev is not None:
+            ev[1].record()
+        hs.hsad_lrx_dwrx(approx, inner, outer, load, lrx=lrx, dwrx=dwrx, ws=ws if ws_bytes else None)
+        if ev is not None:
+            ev[2].record()
+        hs.hsad_threshold(lrx, 3.0, stats=th_out, mask=mask, ws=th_ws)
+        if ev is not None:
+            ev[3].record()
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for i in range(args.steps):
+        step(i, evs[i])
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = t0.elapsed_time(t1) / args.steps
+    dwt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    det_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    thr_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    value = npix / (ms_step * 1e-3)
+
+    # dominant kernel: the DWT, bound by HBM.  Algorithmic bytes per launch: read the cube
+    # once (H W L 4) and write the approximation matrix (H W L' 4).
+    dwt_bytes = npix * L * 4 + npix * Lp * 4
+    achieved = dwt_bytes / (dwt_ms * 1e-3)
+    dwt_kernel = "dwt_equiv_kernel" if Lp <= 16 else "dwt_cascade_kernel"
+    src_hash = kernel_source_hash(["dwt.hip"])
+    traffic = load_traffic(dwt_kernel, "C2_L%d_J%d" % (L, J), src_hash)
+
+    # ROC AUC of the GPU scores vs the FP64 oracle scores on the same cube
+    gl = lrx.cpu().numpy().ravel()
+    gd = dwrx.cpu().numpy().ravel()
+    result_extra = {}
+    cpu = None
+    try:
+        import oracle
+        threads = oracle.set_threads(None)
+        t = time.perf_counter()
+        ra = oracle.dwt_approx(scene.cube, J)
+        rl, rd = oracle.lrx_dwrx(ra, inner, outer, load)
+        tau_ref = oracle.threshold(rl, 3.0)
+        ref_mask = oracle.mask(rl, tau_ref)
+        cpu_s = time.perf_counter() - t
+        auc_gpu, auc_ref = oracle.auc(gl, scene.truth), oracle.auc(rl, scene.truth)
+        dauc_gpu, dauc_ref = oracle.auc(gd, scene.truth), oracle.auc(rd, scene.truth)
+        rel = np.abs(gl - rl) / np.maximum(np.abs(rl), 1e-3 * np.median(np.abs(rl)))
+        result_extra["auc"] = {"lrx_gpu": auc_gpu, "lrx_fp64": auc_ref, "lrx_delta": auc_gpu - auc_ref,
+                               "dwrx_gpu": dauc_gpu, "dwrx_fp64": dauc_ref,
+                               "dwrx_delta": dauc_gpu - dauc_ref,
+                               "lrx_rel_err_max": float(rel.max()),
+                               "lrx_rel_err_median": float(np.median(rel)),
+                               "mask_mismatch": int((mask.cpu().numpy().ravel() != ref_mask).sum())}
+        if not args.no_cpu:
+            # the whole workload once (the oracle takes about a second on 16 cores)
+            reps = []
+            for _ in range(3):
+                t = time.perf_counter()
+                ra = oracle.dwt_approx(scene.cube, J)
+                oracle.lrx_dwrx(ra, inner, outer, load)
+                oracle.threshold(rl, 3.0)
+                reps.append(time.perf_counter() - t)
+            cpu = {"value": npix / float(np.median(reps)), "unit": "pixels/s", "cores": threads,
+                   "kind": "oracle",
+                   "sample": "whole 512x512x224 cube, DWT J=%d + LRX/DWRX + eq. 12; median of 3" % J}
+    except Exception as e:       # the oracle is test infrastructure; report, don't fail
+        result_extra["oracle_error"] = repr(e)
+
+    # full band on the GPU: the same detector on the raw cube (L' = 224), exact FP64 Gram
+    full = None
+    if not args.no_fullband:
+        fb_ws_bytes = hs.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, H, W, L, inner, outer, load)
+        fb_ws = torch.empty(fb_ws_bytes, dtype=torch.uint8, device=dev)
+        fl = torch.empty((H, W), dtype=torch.float32, device=dev)
+        fd = torch.empty((H, W), dtype=torch.float32, device=dev)
+        res = {}
+        for name, prec in (("fp64", hs.HSAD_PREC_AUTO), ("bf16_gram", hs.HSAD_PREC_GRAM_BF16)):
+            hs.hsad_lrx_dwrx(cubes[0], inner, outer, load, prec, lrx=fl, dwrx=fd, ws=fb_ws)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            hs.hsad_lrx_dwrx(cubes[1], inner, outer, load, prec, lrx=fl, dwrx=fd, ws=fb_ws)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            fsc = fl.cpu().numpy().ravel()
+            r = {"ms": ms, "value": npix / (ms * 1e-3)}
+            try:
+                import oracle
+                r["auc_lrx"] = oracle.auc(fsc, scene.truth)
+            except Exception:
+                pass
+            res[name] = r
+        del fb_ws
+        full = res
+        full["speedup_dwt_vs_fullband_fp64"] = value / res["fp64"]["value"]
+
+    sweep = []
+    if not args.no_sweep:
+        for j in range(1, 7):
+            lpj = hs.hsad_dwt_out_len(L, j)
+            apx = torch.empty((H, W, lpj), dtype=torch.float32, device=dev)
+            wsb = hs.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, H, W, lpj, inner, outer, load)
+            wsj = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+            sl = torch.empty((H, W), dtype=torch.float32, device=dev)
+            sd = torch.empty((H, W), dtype=torch.float32, device=dev)
+            n = 3 if lpj > 16 else 20
+            for i in range(2):
+                hs.hsad_dwt(cubes[i & 1], j, out=apx)
+                hs.hsad_lrx_dwrx(apx, inner, outer, load, lrx=sl, dwrx=sd, ws=wsj if wsb else None)
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            dts, lts = [], []
+            for i in range(n):
+                e[0].record()
+                hs.hsad_dwt(cubes[i & 1], j, out=apx)
+                e[1].record()
+                hs.hsad_lrx_dwrx(apx, inner, outer, load, lrx=sl, dwrx=sd, ws=wsj if wsb else None)
+                e[2].record()
+                torch.cuda.synchronize()
+                dts.append(e[0].elapsed_time(e[1]))
+                lts.append(e[1].elapsed_time(e[2]))
+            dm, lm = float(np.mean(dts)), float(np.mean(lts))
+            sweep.append({"levels": j, "Lp": lpj, "dwt_ms": dm, "lrx_dwrx_ms": lm,
+                          "pixels_per_s": npix / ((dm + lm) * 1e-3),
+                          "dwt_hbm_frac": (npix * (L + lpj) * 4) / (dm * 1e-3) / HBM_PEAK})
+            del wsj
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "512x512x224 FP32 cube; db4 DWT J=%d (L'=%d) + LRX/DWRX inner 5 "
+                               "outer 15 + eq. 12 mask" % (J, Lp),
+                   "H": H, "W": W, "L": L, "levels": J, "Lp": Lp, "inner": inner,
+                   "outer": outer, "load_rel": load, "storage": "f32", "parallelism": "1 GPU"},
+        "kernel_ms": {"dwt": dwt_ms, "lrx_dwrx": det_ms, "threshold": thr_ms},
+        "wall_s_timed": wall,
+        "roofline": {"bound": "hbm", "kernel": dwt_kernel, "achieved": achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": dwt_bytes,
+                     "source_hash": src_hash},
+        "cpu_baseline": cpu,
+        "full_band_gpu": full,
+        "sweep": sweep,
+    }
+    out.update(result_extra)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

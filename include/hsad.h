@@ -143,6 +143,32 @@ int hsad_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_wind
                float *scores, float *scores_literal, int32_t *npos, void *ws,
                size_t ws_bytes, hipStream_t stream);
 
+/* Device workspace for hsad_threshold (bytes; independent of the caller's stream). */
+size_t hsad_threshold_workspace_bytes(int64_t n);
+
+/* Adaptive cut-off of eq. (12), tau = mu_d + z_alpha * sigma_d (Sec. 5.3.2).  mu_d and
+ * sigma_d are the mean and population standard deviation of the finite entries of the
+ * anomaly map.  They come from two FP64 passes with a fixed reduction tree, so the
+ * result is deterministic.
+ *   scores : device, n float32
+ *   stats  : device, 4 doubles written {count, mu_d, sigma_d, tau}
+ *   mask   : device, n uint8 written (scores > tau), or NULL for stats only
+ * Errors: HSAD_EINVAL (n < 1, NULL scores/stats, non-finite z_alpha), HSAD_ENOMEM, HSAD_EHIP. */
+int hsad_threshold(const float *scores, int64_t n, double z_alpha, double *stats, uint8_t *mask,
+                   void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Device workspace for hsad_auc (bytes). */
+size_t hsad_auc_workspace_bytes(int64_t n);
+
+/* Exact pixel-level ROC AUC counts (Sec. 5.3.1): over all pairs (positive p, negative q)
+ * of the truth mask, counts[0] = #{s_p > s_q}, counts[1] = #{s_p == s_q}, counts[2] =
+ * number of positives, counts[3] = number of negatives (device, 4 uint64).  The area is
+ * (counts[0] + counts[1]/2) / (counts[2] * counts[3]).  Scores must be finite (NaN compares
+ * false).  Cost is n x positives comparisons.
+ * Errors: HSAD_EINVAL, HSAD_ENOMEM, HSAD_EHIP. */
+int hsad_auc(const float *scores, const uint8_t *truth, int64_t n, uint64_t *counts, void *ws,
+             size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

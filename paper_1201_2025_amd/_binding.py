@@ -50,6 +50,10 @@ SIGNATURES = [
     ("hsad_dwrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_lrx_dwrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_dwest", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_threshold_workspace_bytes", ctypes.c_size_t, [_i64]),
+    ("hsad_threshold", ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_auc_workspace_bytes", ctypes.c_size_t, [_i64]),
+    ("hsad_auc", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_size_t, _vp]),
 ]
 
 
@@ -239,3 +243,55 @@ def hsad_dwest(x, inner: int, outer: int, literal: bool = True, npos: bool = Tru
                           _ptr_or_null(npo, "npos", torch.int32), pws, nws, _stream(stream))
     _check("hsad_dwest", rc)
     return s, lit, npo
+
+
+def hsad_threshold_workspace_bytes(n: int) -> int:
+    return int(lib().hsad_threshold_workspace_bytes(int(n)))
+
+
+def hsad_threshold(scores, z_alpha: float = 3.0, stats=None, mask=True, ws=None, stream=None):
+    """eq. (12) on a score map: returns (stats tensor {count, mu, sigma, tau}, mask or None)."""
+    torch = _torch()
+    ps = _dev(scores, "scores", torch.float32)
+    n = scores.numel()
+    if stats is None:
+        stats = torch.empty(4, dtype=torch.float64, device=scores.device)
+    if mask is True:
+        mask = torch.empty(scores.shape, dtype=torch.uint8, device=scores.device)
+    elif mask is False:
+        mask = None
+    if ws is None:
+        ws = torch.empty(hsad_threshold_workspace_bytes(n), dtype=torch.uint8, device=scores.device)
+    rc = lib().hsad_threshold(ps, n, float(z_alpha), _dev(stats, "stats", torch.float64),
+                              _ptr_or_null(mask, "mask", torch.uint8), _dev(ws, "ws"),
+                              ws.numel() * ws.element_size(), _stream(stream))
+    _check("hsad_threshold", rc)
+    return stats, mask
+
+
+def hsad_auc_workspace_bytes(n: int) -> int:
+    return int(lib().hsad_auc_workspace_bytes(int(n)))
+
+
+def hsad_auc(scores, truth, counts=None, ws=None, stream=None):
+    """Exact ROC AUC counts on the GPU; returns the counts tensor {greater, equal, npos, nneg}
+    (int64 view of the uint64 counts)."""
+    torch = _torch()
+    ps = _dev(scores, "scores", torch.float32)
+    pt = _dev(truth, "truth", torch.uint8)
+    n = scores.numel()
+    if truth.numel() != n:
+        raise ValueError("truth must have as many entries as scores")
+    if counts is None:
+        counts = torch.zeros(4, dtype=torch.int64, device=scores.device)
+    if ws is None:
+        ws = torch.empty(hsad_auc_workspace_bytes(n), dtype=torch.uint8, device=scores.device)
+    rc = lib().hsad_auc(ps, pt, n, _dev(counts, "counts", torch.int64), _dev(ws, "ws"),
+                        ws.numel() * ws.element_size(), _stream(stream))
+    _check("hsad_auc", rc)
+    return counts
+
+
+def auc_from_counts(counts) -> float:
+    g, e, npos, nneg = [int(v) for v in counts.tolist()]
+    return (g + 0.5 * e) / (npos * nneg) if npos and nneg else float("nan")
