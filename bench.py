@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fullband", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="timed steps only, then 3 plain 256 MiB device copies (counter calibration)")
     return ap.parse_args()
 
 
@@ -137,6 +139,17 @@ def main():
     det_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     thr_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
     value = npix / (ms_step * 1e-3)
+
+    if args.profile:
+        # plain copies of known size: what FETCH_SIZE / WRITE_SIZE read for 256 MiB moved
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.steps, "ms_per_step": ms_step, "dwt_ms": dwt_ms,
+                          "lrx_dwrx_ms": det_ms, "threshold_ms": thr_ms}))
+        return
 
     # dominant kernel: the DWT, bound by HBM.  Algorithmic bytes per launch: read the cube
     # once (H W L 4) and write the approximation matrix (H W L' 4).

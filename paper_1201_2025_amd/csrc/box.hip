@@ -6,22 +6,27 @@
 // covariance come from box sums of the features
 //     f_i = x_i - ref_i          (L' linear features)
 //     q_ij = f_i f_j, i <= j     (L'(L'+1)/2 quadratic features)
+//     b = [pixel has a non-finite component]
 // where ref is one pixel of the tile.  Every feature is exact in FP64: the difference of
 // two FP32 values and the product of two such differences both fit in 53 bits.  The sums
 // are FP64, so C = Q/n - mu_f mu_f^T keeps about 12 significant digits even when |mu_f|^2
-// is 1e4 times the smallest eigenvalue of C.  This is the data-dependent cancellation
-// that rules out FP32 sums here.
+// is 1e4 times the smallest eigenvalue of C.  This data-dependent cancellation rules
+// out FP32 sums here.
 //
-// Per 16 x 16 output tile (256 threads, one per output pixel):
-//   1. stage the (16+2R)^2 halo tile of the reduced cube in LDS (coalesced);
-//   2. for each chunk of up to 16 features: vertical box sums over 2R+1 rows, one
-//      (column, feature) job per thread sliding down the tile; then horizontal sums of
-//      2R+1 columns by each output thread into registers;
-//   3. subtract the inner window (direct, (2RI+1)^2 pixels) to get the annulus sums;
-//      keep the inner mean for DWRX;
-//   4. mu, C, diagonal loading lambda = load_rel tr(C)/L' (floor 1e-30), Cholesky in
-//      registers (FP64), then z = L^-1 d and score = |z|^2 for d = x_p - mu (LRX, eq. 1)
+// Per 16 x 16 output tile (256 threads, one output pixel each):
+//   1. stage the (16+2R)^2 halo tile of the reduced cube in LDS (coalesced).  Pixels
+//      outside the image or with a non-finite component take the reference value, and
+//      the second kind is flagged;
+//   2. for each feature chunk and each window (inner, then outer): vertical box sums,
+//      one job per (column, pair of output rows) with every feature of the chunk in
+//      registers; then horizontal sums of those columns by each output thread.
+//      S = outer - inner gives the annulus sums directly;
+//   3. mu, C, diagonal loading lambda = load_rel tr(C)/L' (floor 1e-30), Cholesky in
+//      registers (FP64), z = L^-1 d and score = |z|^2 for d = x_p - mu (LRX, eq. 1)
 //      and d = m_in - mu (DWRX, eq. 5).
+//   A non-finite sample in the annulus makes the covariance non-finite, and the score
+//   is +inf as in the definition.  A non-finite centre or inner-window value propagates
+//   through d, from the raw values (a rare path that re-reads the inner window).
 // HBM traffic is the reduced cube once (the halo re-reads hit L2) and the score maps.
 #include <hip/hip_runtime.h>
 
@@ -31,47 +36,36 @@ namespace hsad {
 
 namespace {
 constexpr int TX = 16, TY = 16, NT = TX * TY;
+constexpr int RB = 2;                 // output rows per vertical-sum job
+constexpr int NRB = TY / RB;
 
 template <int LP> struct BoxCfg {
     static constexpr int G = LP + LP * (LP + 1) / 2;   // moment features
-    static constexpr int GT = G + 1;                   // + non-finite-sample indicator
-    static constexpr int GC = GT < 16 ? GT : 16;
-    static constexpr int GCP = GC | 1;
+    static constexpr int GT = G + 1;                   // + non-finite indicator
+    static constexpr int GC = GT < 15 ? GT : 15;       // features per LDS chunk
+    static constexpr int GCP = GC | 1;                 // odd stride (bank spread)
     static constexpr int NCH = (GT + GC - 1) / GC;
 };
 
-// quadratic feature r (0-based, row-major over i <= j) -> (i, j)
-template <int LP> __device__ __forceinline__ void quad_ij(int r, int &i, int &j)
+// Feature g of a pixel with centred values f[] and flag b (g is a compile-time constant
+// after unrolling).
+template <int LP> __device__ __forceinline__ double feat(const double *f, double b, int g)
 {
-    i = 0;
-    int len = LP;
-#pragma unroll
-    for (int t = 0; t < LP; ++t) {
-        if (r >= len) {
-            r -= len;
-            len -= 1;
-            i += 1;
-        }
+    if (g < LP) return f[g];
+    if (g >= BoxCfg<LP>::G) return b;
+    int r = g - LP, i = 0, len = LP;
+    while (r >= len) {
+        r -= len;
+        --len;
+        ++i;
     }
-    j = i + r;
-}
-
-// px points at a sanitised tile pixel (non-finite pixels hold the reference value, so
-// their moment features are 0); g == G is the non-finite indicator.
-template <int LP>
-__device__ __forceinline__ double feature(const float *px, float badf, const double *ref, int g)
-{
-    if (g < LP) return (double)px[g] - ref[g];
-    if (g >= BoxCfg<LP>::G) return (double)badf;
-    int i, j;
-    quad_ij<LP>(g - LP, i, j);
-    return ((double)px[i] - ref[i]) * ((double)px[j] - ref[j]);
+    return f[i] * f[i + r];
 }
 
 __device__ __forceinline__ int clip_count(int c, int r, int n)
 {
-    int lo = c - r < 0 ? 0 : c - r;
-    int hi = c + r > n - 1 ? n - 1 : c + r;
+    const int lo = c - r < 0 ? 0 : c - r;
+    const int hi = c + r > n - 1 ? n - 1 : c + r;
     return hi - lo + 1;
 }
 }  // namespace
@@ -86,32 +80,28 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
     using C = BoxCfg<LP>;
     extern __shared__ double smem[];
     const int EX = TX + 2 * R, EY = TY + 2 * R;
-    double *V = smem;                                          // TY * EX * GCP
+    double *V = smem;                                                    // TY*EX*GCP
     float *xs = reinterpret_cast<float *>(smem + (size_t)TY * EX * C::GCP);   // EY*EX*LP
-    float *bad = xs + (size_t)EY * EX * LP;                    // EY*EX (0/1)
+    float *bad = xs + (size_t)EY * EX * LP;                              // EY*EX
 
     const int tid = threadIdx.x;
     const int y0 = blockIdx.y * TY, x0 = blockIdx.x * TX;
 
-    // tile reference pixel (a finite value keeps NaN/Inf confined to their windows)
     double ref[LP];
     {
         const int ry = min(y0 + TY / 2, H - 1), rx = min(x0 + TX / 2, W - 1);
         const float *rp = x + ((size_t)ry * W + rx) * LP;
 #pragma unroll
         for (int i = 0; i < LP; ++i) {
-            float v = rp[i];
+            const float v = rp[i];
             ref[i] = isfinite(v) ? (double)v : 0.0;
         }
     }
 
-    // 1. halo tile.  Pixels outside the image, and pixels with a non-finite component,
-    //    take the reference value (zero features); the latter are flagged in bad[] so that
-    //    a window containing one scores like the definition (see step 4).
+    // 1. halo tile
     for (int t = tid; t < EY * EX; t += NT) {
         const int ey = t / EX, ex = t - ey * EX;
         const int gy = y0 - R + ey, gx = x0 - R + ex;
-        float *dst = xs + (size_t)t * LP;
         float v[LP];
         bool ok = false, fin = true;
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
@@ -123,6 +113,7 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
                 fin = fin && isfinite(v[i]);
             }
         }
+        float *dst = xs + (size_t)t * LP;
 #pragma unroll
         for (int i = 0; i < LP; ++i) dst[i] = (ok && fin) ? v[i] : (float)ref[i];
         bad[t] = (ok && !fin) ? 1.0f : 0.0f;
@@ -132,81 +123,96 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
     const int ty = tid / TX, tx = tid - ty * TX;
     const int py = y0 + ty, px = x0 + tx;
 
-    // 3a. inner window, subtracted up front: S = -sum_inner (sanitised features), and
-    //     the inner mean for DWRX from the raw values (non-finite values propagate)
-    double S[C::GT];
-    double min_sum[LP];
+    double S[C::GT];        // annulus sums (outer minus inner)
+    double sin_lin[LP];     // inner-window linear sums (DWRX mean)
+    double in_bad = 0.0;
 #pragma unroll
     for (int g = 0; g < C::GT; ++g) S[g] = 0.0;
 #pragma unroll
-    for (int i = 0; i < LP; ++i) min_sum[i] = 0.0;
-    if (has_inner) {
-        for (int dy = -RI; dy <= RI; ++dy)
-            for (int dx = -RI; dx <= RI; ++dx) {
-                const size_t t = (size_t)(ty + R + dy) * EX + (tx + R + dx);
-                const float *pp = xs + t * LP;
-                double f[LP];
-#pragma unroll
-                for (int i = 0; i < LP; ++i) f[i] = (double)pp[i] - ref[i];
-                int g = LP;
-#pragma unroll
-                for (int i = 0; i < LP; ++i) {
-                    S[i] -= f[i];
-#pragma unroll
-                    for (int j = i; j < LP; ++j) S[g++] -= f[i] * f[j];
-                }
-                S[C::G] -= (double)bad[t];
-                const int gy = py + dy, gx = px + dx;
-                if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                    const float *raw = x + ((size_t)gy * W + gx) * LP;
-#pragma unroll
-                    for (int i = 0; i < LP; ++i) min_sum[i] += (double)raw[i] - ref[i];
-                }
-            }
-    }
+    for (int i = 0; i < LP; ++i) sin_lin[i] = 0.0;
 
-    // 2. outer box sums, feature chunk by feature chunk
 #pragma unroll
     for (int ch = 0; ch < C::NCH; ++ch) {
         const int g0 = ch * C::GC;
-        const int ng = (C::GT - g0) < C::GC ? (C::GT - g0) : C::GC;
-        for (int job = tid; job < EX * ng; job += NT) {
-            const int gg = job / EX, c = job - gg * EX;
-            const int g = g0 + gg;
-            double s = 0.0;
-            for (int ey = 0; ey <= 2 * R; ++ey) {
-                const size_t t = (size_t)ey * EX + c;
-                s += feature<LP>(xs + t * LP, bad[t], ref, g);
-            }
-            V[((size_t)0 * EX + c) * C::GCP + gg] = s;
-            for (int r = 1; r < TY; ++r) {
-                const size_t ta = (size_t)(r + 2 * R) * EX + c, tb = (size_t)(r - 1) * EX + c;
-                s += feature<LP>(xs + ta * LP, bad[ta], ref, g) - feature<LP>(xs + tb * LP, bad[tb], ref, g);
-                V[((size_t)r * EX + c) * C::GCP + gg] = s;
-            }
-        }
-        __syncthreads();
-        const double *vrow = V + ((size_t)ty * EX + tx) * C::GCP;
+        for (int win = has_inner ? 0 : 1; win < 2; ++win) {
+            // win 0: inner window (half RI), win 1: outer window (half R)
+            const int h = win == 0 ? RI : R;
+            const int eoff = R - h;            // first extended row/col of the window
+            // 2a. vertical sums: job = (column c, row block rb)
+            for (int job = tid; job < EX * NRB; job += NT) {
+                const int rb = job / EX, c = job - rb * EX;
+                const int r0 = rb * RB;
+                double acc[C::GC];
 #pragma unroll
-        for (int gg = 0; gg < C::GC; ++gg) {
-            if (g0 + gg < C::GT) {
-                double s = 0.0;
-                for (int dx = 0; dx <= 2 * R; ++dx) s += vrow[(size_t)dx * C::GCP + gg];
-                S[g0 + gg] += s;
+                for (int gg = 0; gg < C::GC; ++gg) acc[gg] = 0.0;
+                for (int ey = r0 + eoff; ey <= r0 + eoff + 2 * h; ++ey) {
+                    const size_t t = (size_t)ey * EX + c;
+                    double f[LP];
+#pragma unroll
+                    for (int i = 0; i < LP; ++i) f[i] = (double)xs[t * LP + i] - ref[i];
+                    const double b = (double)bad[t];
+#pragma unroll
+                    for (int gg = 0; gg < C::GC; ++gg)
+                        if (g0 + gg < C::GT) acc[gg] += feat<LP>(f, b, g0 + gg);
+                }
+                double *vr = V + ((size_t)r0 * EX + c) * C::GCP;
+#pragma unroll
+                for (int gg = 0; gg < C::GC; ++gg) vr[gg] = acc[gg];
+#pragma unroll
+                for (int r = 1; r < RB; ++r) {
+                    const size_t ta = (size_t)(r0 + r + eoff + 2 * h) * EX + c;
+                    const size_t tb = (size_t)(r0 + r - 1 + eoff) * EX + c;
+                    double fa[LP], fb[LP];
+#pragma unroll
+                    for (int i = 0; i < LP; ++i) {
+                        fa[i] = (double)xs[ta * LP + i] - ref[i];
+                        fb[i] = (double)xs[tb * LP + i] - ref[i];
+                    }
+                    const double ba = (double)bad[ta], bb = (double)bad[tb];
+#pragma unroll
+                    for (int gg = 0; gg < C::GC; ++gg)
+                        if (g0 + gg < C::GT)
+                            acc[gg] += feat<LP>(fa, ba, g0 + gg) - feat<LP>(fb, bb, g0 + gg);
+                    double *vq = V + ((size_t)(r0 + r) * EX + c) * C::GCP;
+#pragma unroll
+                    for (int gg = 0; gg < C::GC; ++gg) vq[gg] = acc[gg];
+                }
             }
+            __syncthreads();
+            // 2b. horizontal sums for this thread's pixel
+            const double *vrow = V + ((size_t)ty * EX + tx + eoff) * C::GCP;
+            double hsum[C::GC];
+#pragma unroll
+            for (int gg = 0; gg < C::GC; ++gg) hsum[gg] = 0.0;
+            for (int dx = 0; dx <= 2 * h; ++dx) {
+                const double *v = vrow + (size_t)dx * C::GCP;
+#pragma unroll
+                for (int gg = 0; gg < C::GC; ++gg) hsum[gg] += v[gg];
+            }
+#pragma unroll
+            for (int gg = 0; gg < C::GC; ++gg) {
+                const int g = g0 + gg;
+                if (g < C::GT) {
+                    if (win == 0) {
+                        S[g] -= hsum[gg];
+                        if (g < LP) sin_lin[g] = hsum[gg];
+                        if (g == C::G) in_bad = hsum[gg];
+                    } else {
+                        S[g] += hsum[gg];
+                    }
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     if (py >= H || px >= W) return;
 
-    // 4. statistics of the annulus, loading, Cholesky, scores
+    // 3. statistics of the annulus, loading, Cholesky, scores
     const int n_o = clip_count(py, R, H) * clip_count(px, R, W);
     const int n_i = has_inner ? clip_count(py, RI, H) * clip_count(px, RI, W) : 0;
     const double inv_na = 1.0 / (double)(n_o - n_i);
-    // a non-finite sample in the annulus makes C non-finite: not positive definite (+inf),
-    // as in the definition; the counts are exact integers held in FP64
-    const bool ann_bad = S[C::G] > 0.5;
+    const bool ann_bad = S[C::G] > 0.5;      // exact small integers in FP64
     double mu[LP];
 #pragma unroll
     for (int i = 0; i < LP; ++i) mu[i] = S[i] * inv_na;
@@ -258,11 +264,25 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
         lrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
     }
     if (dwrx) {
+        if (in_bad > 0.5) {
+            // rare: a non-finite inner sample; take the mean from the raw values so that
+            // NaN / Inf propagate exactly as in the definition
+#pragma unroll
+            for (int i = 0; i < LP; ++i) sin_lin[i] = 0.0;
+            for (int dy = -RI; dy <= RI; ++dy)
+                for (int dx = -RI; dx <= RI; ++dx) {
+                    const int gy = py + dy, gx = px + dx;
+                    if (gy < 0 || gy >= H || gx < 0 || gx >= W) continue;
+                    const float *raw = x + ((size_t)gy * W + gx) * LP;
+#pragma unroll
+                    for (int i = 0; i < LP; ++i) sin_lin[i] += (double)raw[i] - ref[i];
+                }
+        }
         const double inv_ni = 1.0 / (double)n_i;
         double z[LP], s = 0.0;
 #pragma unroll
         for (int i = 0; i < LP; ++i) {
-            double t = min_sum[i] * inv_ni - mu[i];
+            double t = sin_lin[i] * inv_ni - mu[i];
 #pragma unroll
             for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
             z[i] = t / Lm[i][i];

@@ -207,6 +207,101 @@ __global__ __launch_bounds__(256) void dwt_equiv_kernel(const float *__restrict_
 }
 
 // ------------------------------------------------------------------------------------
+// device: equivalent filter with coalesced, LDS-staged band chunks
+// ------------------------------------------------------------------------------------
+// A workgroup owns 256 consecutive pixels (one per thread) and walks the spectrum in
+// chunks of 32 bands.  Each chunk is loaded with whole 128-byte lines per pixel (8
+// lanes x 16 bytes, or 32 lanes x 4 bytes when L is not a multiple of 4) into LDS.
+// There it is transposed to one row per pixel (stride 33 floats, conflict-free).  The
+// next chunk's loads are issued into registers before the current chunk is computed,
+// so HBM streaming overlaps the FP64 FMAs.
+constexpr int kEqCB = 32, kEqTP = 256, kEqLd = kEqCB + 1;
+
+template <int LP, int VEC>
+__global__ __launch_bounds__(kEqTP) void dwt_equiv_lds_kernel(const float *__restrict__ cube,
+                                                              int64_t npix, int L,
+                                                              const double *__restrict__ coef,
+                                                              float *__restrict__ out)
+{
+    __shared__ float tile[kEqTP * kEqLd];
+    constexpr int PER = kEqCB / VEC;             // vectors per pixel segment
+    constexpr int NV = kEqTP * PER / kEqTP;      // vectors per thread per chunk (= PER)
+    using V = typename VecT<VEC>::T;
+    const int t = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * kEqTP;
+    const int np = (int)((npix - p0) < kEqTP ? (npix - p0) : kEqTP);
+    const int nchunk = (L + kEqCB - 1) / kEqCB;
+
+    V buf[NV];
+    auto load_chunk = [&](int c0) {
+        const int cb = (L - c0) < kEqCB ? (L - c0) : kEqCB;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int q = t + kEqTP * i;
+            const int p = q / PER, j = q % PER;
+            if (p < np && j * VEC < cb)
+                buf[i] = *reinterpret_cast<const V *>(cube + (p0 + p) * (int64_t)L + c0 + j * VEC);
+        }
+    };
+    auto store_chunk = [&](int c0) {
+        const int cb = (L - c0) < kEqCB ? (L - c0) : kEqCB;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int q = t + kEqTP * i;
+            const int p = q / PER, j = q % PER;
+            if (p < np && j * VEC < cb) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) tile[p * kEqLd + j * VEC + e] = lane_elem<VEC>(buf[i], e);
+            }
+        }
+    };
+
+    double acc[LP];
+#pragma unroll
+    for (int k = 0; k < LP; ++k) acc[k] = 0.0;
+    load_chunk(0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int c0 = ch * kEqCB;
+        const int cb = (L - c0) < kEqCB ? (L - c0) : kEqCB;
+        store_chunk(c0);
+        __syncthreads();
+        if (ch + 1 < nchunk) load_chunk(c0 + kEqCB);
+        const float *row = tile + t * kEqLd;
+        const double *cf = coef + (size_t)c0 * LP;
+        if (cb == kEqCB) {
+#pragma unroll 8
+            for (int b = 0; b < kEqCB; ++b) {
+                const double xv = (double)row[b];
+#pragma unroll
+                for (int k = 0; k < LP; ++k) acc[k] = fma(cf[b * LP + k], xv, acc[k]);
+            }
+        } else {
+            for (int b = 0; b < cb; ++b) {
+                const double xv = (double)row[b];
+#pragma unroll
+                for (int k = 0; k < LP; ++k) acc[k] = fma(cf[b * LP + k], xv, acc[k]);
+            }
+        }
+        __syncthreads();
+    }
+    if (t >= np) return;
+    float *dst = out + (p0 + t) * LP;
+    if constexpr (LP % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < LP; k += 4)
+            *reinterpret_cast<float4 *>(dst + k) =
+                make_float4((float)acc[k], (float)acc[k + 1], (float)acc[k + 2], (float)acc[k + 3]);
+    } else if constexpr (LP % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < LP; k += 2)
+            *reinterpret_cast<float2 *>(dst + k) = make_float2((float)acc[k], (float)acc[k + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < LP; ++k) dst[k] = (float)acc[k];
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // device: LDS cascade kernel
 // ------------------------------------------------------------------------------------
 struct Taps {
@@ -273,8 +368,16 @@ __global__ __launch_bounds__(256) void dwt_cascade_kernel(const float *__restric
 // ------------------------------------------------------------------------------------
 template <int LP>
 static int launch_equiv(const float *cube, int64_t npix, int64_t L, const double *coef, int vec,
-                        float *out, hipStream_t s)
+                        bool lds, float *out, hipStream_t s)
 {
+    if (lds) {
+        dim3 grid((unsigned)((npix + kEqTP - 1) / kEqTP)), block(kEqTP);
+        if (vec == 4)
+            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+        else
+            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 1>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+        return check_launch("dwt_equiv_lds_kernel");
+    }
     dim3 grid((unsigned)((npix + 255) / 256)), block(256);
     if (vec == 4)
         hipLaunchKernelGGL((dwt_equiv_kernel<LP, 4>), grid, block, 0, s, cube, npix, (int)L, coef, out);
@@ -286,11 +389,11 @@ static int launch_equiv(const float *cube, int64_t npix, int64_t L, const double
 }
 
 static int launch_equiv_lp(int64_t Lp, const float *cube, int64_t npix, int64_t L,
-                           const double *coef, int vec, float *out, hipStream_t s)
+                           const double *coef, int vec, bool lds, float *out, hipStream_t s)
 {
     switch (Lp) {
 #define HSAD_EQ_CASE(n) \
-    case n: return launch_equiv<n>(cube, npix, L, coef, vec, out, s);
+    case n: return launch_equiv<n>(cube, npix, L, coef, vec, lds, out, s);
         HSAD_EQ_CASE(1) HSAD_EQ_CASE(2) HSAD_EQ_CASE(3) HSAD_EQ_CASE(4) HSAD_EQ_CASE(5)
         HSAD_EQ_CASE(6) HSAD_EQ_CASE(7) HSAD_EQ_CASE(8) HSAD_EQ_CASE(9) HSAD_EQ_CASE(10)
         HSAD_EQ_CASE(11) HSAD_EQ_CASE(12) HSAD_EQ_CASE(13) HSAD_EQ_CASE(14) HSAD_EQ_CASE(15)
@@ -300,7 +403,8 @@ static int launch_equiv_lp(int64_t Lp, const float *cube, int64_t npix, int64_t 
     }
 }
 
-static int g_dwt_force = -1;   // -1 auto, 0 cascade, 1 equivalent filter (tests/tuning)
+// -1 auto, 0 cascade, 1 equivalent filter (LDS-staged), 2 equivalent filter (per-lane loads)
+static int g_dwt_force = -1;
 
 int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t Lp,
                float *approx, hipStream_t s)
@@ -314,9 +418,12 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
     }
     const bool equiv_ok = Lp <= 16;
     if (equiv_ok && g_dwt_force != 0) {
-        const int vec = (L % 4 == 0) ? 4 : ((L % 2 == 0) ? 2 : 1);
+        const bool lds = g_dwt_force != 2;
+        // the LDS-staged kernel reads the matrix band-major ([band][k], interleave 1)
+        const int vec = lds ? 1 : ((L % 4 == 0) ? 4 : ((L % 2 == 0) ? 2 : 1));
+        const int ldvec = (L % 4 == 0) ? 4 : 1;
         const double *coef = composite_coefs(L, levels, Lp, vec, s);
-        if (coef) return launch_equiv_lp(Lp, cube, npix, L, coef, vec, approx, s);
+        if (coef) return launch_equiv_lp(Lp, cube, npix, L, coef, lds ? ldvec : vec, lds, approx, s);
     }
     // cascade: size the pixel tile so that both ping-pong buffers fit in 64 KiB of LDS
     const int64_t per_pix = (L + 1) + ((L + 1) / 2 + 1);

@@ -2,8 +2,10 @@
 // its mask (Sec. 5.3.2), and the exact ROC AUC counts (Sec. 5.3.1).
 //
 // Threshold: tau = mu_d + Z sigma_d over the finite scores, with the population standard
-// deviation from two passes (mean, then centred squares).  The reductions are FP64 with
-// a fixed block count, so results are deterministic.  mask = (s > tau).
+// deviation.  Each block takes two passes over its chunk (mean, then centred squares).
+// The block results are combined with Chan's pairwise update of (count, mean, M2) in a
+// fixed tree.  Everything is FP64 and deterministic.  Two launches: block statistics,
+// then merge + mask (s > tau).
 // AUC: the Mann-Whitney counts over pixel pairs (positive p, negative q):
 // greater = #{s_p > s_q}, equal = #{s_p == s_q}.  Positive scores are compacted into the
 // workspace, then each negative pixel is compared with all of them through LDS tiles.
@@ -32,67 +34,107 @@ __device__ __forceinline__ double block_reduce_sum(double v, double *red)
     return s;   // valid in thread 0
 }
 
-// mode 0: (count, sum) of finite scores; mode 1: sum of (s - mu)^2 with mu = stats[1]
-__global__ __launch_bounds__(kRedThreads) void thr_partial_kernel(const float *__restrict__ s,
-                                                                  int64_t n, int mode,
-                                                                  const double *__restrict__ stats,
-                                                                  double *__restrict__ part)
+// Per-block statistics of the finite scores: count, mean (two passes over the block's
+// chunk, so the centred sum of squares M2 is exact up to rounding) -> part[3*b .. 3*b+2].
+__global__ __launch_bounds__(kRedThreads) void thr_block_kernel(const float *__restrict__ s,
+                                                                int64_t n, int64_t chunk,
+                                                                double *__restrict__ part)
 {
     __shared__ double red[8];
-    const double mu = mode ? stats[1] : 0.0;
-    double a = 0.0, b = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    __shared__ double bmean;
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    double c = 0.0, sum = 0.0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
         const float v = s[i];
         if (isfinite(v)) {
-            if (mode == 0) {
-                a += 1.0;
-                b += (double)v;
-            } else {
-                const double d = (double)v - mu;
-                b += d * d;
-            }
+            c += 1.0;
+            sum += (double)v;
         }
     }
-    a = block_reduce_sum(a, red);
-    b = block_reduce_sum(b, red);
+    c = block_reduce_sum(c, red);
+    sum = block_reduce_sum(sum, red);
+    if (threadIdx.x == 0) bmean = c > 0 ? sum / c : 0.0;
+    __syncthreads();
+    const double m = bmean;
+    double m2 = 0.0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        const float v = s[i];
+        if (isfinite(v)) {
+            const double d = (double)v - m;
+            m2 += d * d;
+        }
+    }
+    m2 = block_reduce_sum(m2, red);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = a;
-        part[2 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x] = c;
+        part[3 * blockIdx.x + 1] = m;
+        part[3 * blockIdx.x + 2] = m2;
     }
 }
 
-// stats = {count, mu, sigma, tau}
-__global__ __launch_bounds__(kRedThreads) void thr_final_kernel(const double *__restrict__ part,
-                                                                int nblk, int mode, double z,
-                                                                double *__restrict__ stats)
+// Chan et al.'s pairwise update of (count, mean, M2).
+__device__ __forceinline__ void chan_merge(double &na, double &ma, double &Ma, double nb, double mb,
+                                           double Mb)
 {
-    __shared__ double red[8];
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-        a += part[2 * i];
-        b += part[2 * i + 1];
+    const double nn = na + nb;
+    if (nb == 0.0) return;
+    if (na == 0.0) {
+        na = nb;
+        ma = mb;
+        Ma = Mb;
+        return;
     }
-    a = block_reduce_sum(a, red);
-    b = block_reduce_sum(b, red);
+    const double d = mb - ma;
+    ma += d * (nb / nn);
+    Ma += Mb + d * d * (na * nb / nn);
+    na = nn;
+}
+
+// Every block merges the per-block statistics with the same fixed tree (so they agree
+// bit for bit), block 0 stores stats = {count, mu, sigma, tau}, and all blocks write
+// the mask (s > tau) for their part of the map.
+__global__ __launch_bounds__(kRedThreads) void thr_merge_mask_kernel(const float *__restrict__ s,
+                                                                     int64_t n, int nblk,
+                                                                     const double *__restrict__ part,
+                                                                     double z,
+                                                                     double *__restrict__ stats,
+                                                                     uint8_t *__restrict__ mask)
+{
+    __shared__ double sh[3 * kRedThreads];
+    __shared__ double tau_s;
+    double na = 0.0, ma = 0.0, Ma = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
+        chan_merge(na, ma, Ma, part[3 * i], part[3 * i + 1], part[3 * i + 2]);
+    sh[3 * threadIdx.x] = na;
+    sh[3 * threadIdx.x + 1] = ma;
+    sh[3 * threadIdx.x + 2] = Ma;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double a = sh[3 * threadIdx.x], b = sh[3 * threadIdx.x + 1], c = sh[3 * threadIdx.x + 2];
+            const int o = 3 * (threadIdx.x + w);
+            chan_merge(a, b, c, sh[o], sh[o + 1], sh[o + 2]);
+            sh[3 * threadIdx.x] = a;
+            sh[3 * threadIdx.x + 1] = b;
+            sh[3 * threadIdx.x + 2] = c;
+        }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        if (mode == 0) {
-            stats[0] = a;
-            stats[1] = a > 0 ? b / a : NAN;
-        } else {
-            const double sig = stats[0] > 0 ? sqrt(b / stats[0]) : NAN;
+        const double cnt = sh[0], mu = cnt > 0 ? sh[1] : NAN;
+        const double sig = cnt > 0 ? sqrt(sh[2] / cnt) : NAN;
+        tau_s = mu + z * sig;
+        if (blockIdx.x == 0) {
+            stats[0] = cnt;
+            stats[1] = mu;
             stats[2] = sig;
-            stats[3] = stats[1] + z * sig;
+            stats[3] = tau_s;
         }
     }
-}
-
-__global__ __launch_bounds__(kRedThreads) void thr_mask_kernel(const float *__restrict__ s,
-                                                               int64_t n,
-                                                               const double *__restrict__ stats,
-                                                               uint8_t *__restrict__ mask)
-{
-    const double tau = stats[3];
+    __syncthreads();
+    if (!mask) return;
+    const double tau = tau_s;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         mask[i] = ((double)s[i] > tau) ? 1 : 0;
@@ -195,7 +237,7 @@ extern "C" {
 size_t hsad_threshold_workspace_bytes(int64_t n)
 {
     (void)n;
-    return (size_t)kRedBlocks * 2 * sizeof(double);
+    return (size_t)kRedBlocks * 3 * sizeof(double);
 }
 
 int hsad_threshold(const float *scores, int64_t n, double z_alpha, double *stats, uint8_t *mask,
@@ -207,19 +249,16 @@ int hsad_threshold(const float *scores, int64_t n, double z_alpha, double *stats
     if (!ws || ws_bytes < hsad_threshold_workspace_bytes(n))
         return fail(HSAD_ENOMEM, "hsad_threshold: workspace too small");
     double *part = (double *)ws;
-    int nblk = (int)((n + kRedThreads - 1) / kRedThreads);
+    // ~1024 scores per block, at most kRedBlocks blocks
+    int64_t nblk = (n + 1023) / 1024;
     if (nblk > kRedBlocks) nblk = kRedBlocks;
-    hipLaunchKernelGGL(thr_partial_kernel, dim3(nblk), dim3(kRedThreads), 0, stream, scores, n, 0,
-                       stats, part);
-    hipLaunchKernelGGL(thr_final_kernel, dim3(1), dim3(kRedThreads), 0, stream, part, nblk, 0,
-                       z_alpha, stats);
-    hipLaunchKernelGGL(thr_partial_kernel, dim3(nblk), dim3(kRedThreads), 0, stream, scores, n, 1,
-                       stats, part);
-    hipLaunchKernelGGL(thr_final_kernel, dim3(1), dim3(kRedThreads), 0, stream, part, nblk, 1,
-                       z_alpha, stats);
-    if (mask)
-        hipLaunchKernelGGL(thr_mask_kernel, dim3(nblk), dim3(kRedThreads), 0, stream, scores, n,
-                           stats, mask);
+    const int64_t chunk = (n + nblk - 1) / nblk;
+    hipLaunchKernelGGL(thr_block_kernel, dim3((unsigned)nblk), dim3(kRedThreads), 0, stream, scores, n,
+                       chunk, part);
+    int64_t mblk = (n + kRedThreads * 4 - 1) / (kRedThreads * 4);
+    if (mblk > kRedBlocks) mblk = kRedBlocks;
+    hipLaunchKernelGGL(thr_merge_mask_kernel, dim3((unsigned)mblk), dim3(kRedThreads), 0, stream, scores,
+                       n, (int)nblk, part, z_alpha, stats, mask);
     return check_launch("hsad_threshold");
 }
 

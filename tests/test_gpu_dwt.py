@@ -46,14 +46,17 @@ def test_dwt_equivalent_filter_and_cascade_agree(L, levels):
     ref = oracle.dwt_approx(s.cube, levels)
     L_ = hs.lib()
     try:
-        L_.hsad_internal_dwt_force(ctypes.c_int(0))
+        L_.hsad_internal_dwt_force(0)
         casc = _gpu_dwt(s.cube, levels)
-        L_.hsad_internal_dwt_force(ctypes.c_int(1))
+        L_.hsad_internal_dwt_force(1)
         eq = _gpu_dwt(s.cube, levels)
+        L_.hsad_internal_dwt_force(2)
+        lane = _gpu_dwt(s.cube, levels)
     finally:
-        L_.hsad_internal_dwt_force(ctypes.c_int(-1))
+        L_.hsad_internal_dwt_force(-1)
     assert dwt_rel_err(casc, ref) <= TOL
     assert dwt_rel_err(eq, ref) <= TOL
+    assert dwt_rel_err(lane, ref) <= TOL
 
 
 @pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6])
