@@ -18,9 +18,10 @@
 //      outside the image or with a non-finite component take the reference value, and
 //      the second kind is flagged;
 //   2. for each feature chunk and each window (inner, then outer): vertical box sums,
-//      one job per (column, pair of output rows) with every feature of the chunk in
-//      registers; then horizontal sums of those columns by each output thread.
-//      S = outer - inner gives the annulus sums directly;
+//      one job per (column, block of 4 output rows) with every feature of the chunk in
+//      registers; running sums along each tile row; then each output thread takes its
+//      horizontal box sum as a difference of two running sums.  S = outer - inner gives
+//      the annulus sums directly;
 //   3. mu, C, diagonal loading lambda = load_rel tr(C)/L' (floor 1e-30), Cholesky in
 //      registers (FP64), z = L^-1 d and score = |z|^2 for d = x_p - mu (LRX, eq. 1)
 //      and d = m_in - mu (DWRX, eq. 5).
@@ -36,13 +37,13 @@ namespace hsad {
 
 namespace {
 constexpr int TX = 16, TY = 16, NT = TX * TY;
-constexpr int RB = 2;                 // output rows per vertical-sum job
+constexpr int RB = 4;                 // output rows per vertical-sum job
 constexpr int NRB = TY / RB;
 
-template <int LP> struct BoxCfg {
+template <int LP, int GCMAX = 15> struct BoxCfg {
     static constexpr int G = LP + LP * (LP + 1) / 2;   // moment features
     static constexpr int GT = G + 1;                   // + non-finite indicator
-    static constexpr int GC = GT < 15 ? GT : 15;       // features per LDS chunk
+    static constexpr int GC = GT < GCMAX ? GT : GCMAX; // features per LDS chunk
     static constexpr int GCP = GC | 1;                 // odd stride (bank spread)
     static constexpr int NCH = (GT + GC - 1) / GC;
 };
@@ -62,6 +63,26 @@ template <int LP> __device__ __forceinline__ double feat(const double *f, double
     return f[i] * f[i + r];
 }
 
+// Centred values of tile pixel t (FP64, exact).
+template <int LP>
+__device__ __forceinline__ void centred(const float *xs, size_t t, const double *ref, double *f)
+{
+    if constexpr (LP % 4 == 0) {
+        const float4 *q = reinterpret_cast<const float4 *>(xs + t * LP);
+#pragma unroll
+        for (int k = 0; k < LP / 4; ++k) {
+            const float4 v = q[k];
+            f[4 * k] = (double)v.x - ref[4 * k];
+            f[4 * k + 1] = (double)v.y - ref[4 * k + 1];
+            f[4 * k + 2] = (double)v.z - ref[4 * k + 2];
+            f[4 * k + 3] = (double)v.w - ref[4 * k + 3];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < LP; ++i) f[i] = (double)xs[t * LP + i] - ref[i];
+    }
+}
+
 __device__ __forceinline__ int clip_count(int c, int r, int n)
 {
     const int lo = c - r < 0 ? 0 : c - r;
@@ -70,14 +91,14 @@ __device__ __forceinline__ int clip_count(int c, int r, int n)
 }
 }  // namespace
 
-template <int LP>
+template <int LP, int GCMAX>
 __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restrict__ x, int H,
                                                           int W, int R, int RI, int has_inner,
                                                           double load_rel,
                                                           float *__restrict__ lrx,
                                                           float *__restrict__ dwrx)
 {
-    using C = BoxCfg<LP>;
+    using C = BoxCfg<LP, GCMAX>;
     extern __shared__ double smem[];
     const int EX = TX + 2 * R, EY = TY + 2 * R;
     double *V = smem;                                                    // TY*EX*GCP
@@ -148,8 +169,7 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
                 for (int ey = r0 + eoff; ey <= r0 + eoff + 2 * h; ++ey) {
                     const size_t t = (size_t)ey * EX + c;
                     double f[LP];
-#pragma unroll
-                    for (int i = 0; i < LP; ++i) f[i] = (double)xs[t * LP + i] - ref[i];
+                    centred<LP>(xs, t, ref, f);
                     const double b = (double)bad[t];
 #pragma unroll
                     for (int gg = 0; gg < C::GC; ++gg)
@@ -163,11 +183,8 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
                     const size_t ta = (size_t)(r0 + r + eoff + 2 * h) * EX + c;
                     const size_t tb = (size_t)(r0 + r - 1 + eoff) * EX + c;
                     double fa[LP], fb[LP];
-#pragma unroll
-                    for (int i = 0; i < LP; ++i) {
-                        fa[i] = (double)xs[ta * LP + i] - ref[i];
-                        fb[i] = (double)xs[tb * LP + i] - ref[i];
-                    }
+                    centred<LP>(xs, ta, ref, fa);
+                    centred<LP>(xs, tb, ref, fb);
                     const double ba = (double)bad[ta], bb = (double)bad[tb];
 #pragma unroll
                     for (int gg = 0; gg < C::GC; ++gg)
@@ -179,16 +196,25 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
                 }
             }
             __syncthreads();
-            // 2b. horizontal sums for this thread's pixel
-            const double *vrow = V + ((size_t)ty * EX + tx + eoff) * C::GCP;
+            // 2b. running (prefix) sums along each tile row, in place: V[ty][c] becomes
+            //     sum_{c' <= c} V[ty][c'], one thread per (row, feature)
+            for (int job = tid; job < TY * C::GC; job += NT) {
+                const int r = job / C::GC, gg = job - r * C::GC;
+                double run = 0.0;
+                double *v = V + (size_t)r * EX * C::GCP + gg;
+                for (int c = 0; c < EX; ++c) {
+                    run += v[(size_t)c * C::GCP];
+                    v[(size_t)c * C::GCP] = run;
+                }
+            }
+            __syncthreads();
+            // 2c. horizontal box sum of this thread's pixel = difference of two prefixes
+            const int c_hi = tx + eoff + 2 * h, c_lo = tx + eoff - 1;
+            const double *vhi = V + ((size_t)ty * EX + c_hi) * C::GCP;
+            const double *vlo = V + ((size_t)ty * EX + (c_lo < 0 ? 0 : c_lo)) * C::GCP;
             double hsum[C::GC];
 #pragma unroll
-            for (int gg = 0; gg < C::GC; ++gg) hsum[gg] = 0.0;
-            for (int dx = 0; dx <= 2 * h; ++dx) {
-                const double *v = vrow + (size_t)dx * C::GCP;
-#pragma unroll
-                for (int gg = 0; gg < C::GC; ++gg) hsum[gg] += v[gg];
-            }
+            for (int gg = 0; gg < C::GC; ++gg) hsum[gg] = vhi[gg] - (c_lo < 0 ? 0.0 : vlo[gg]);
 #pragma unroll
             for (int gg = 0; gg < C::GC; ++gg) {
                 const int g = g0 + gg;
@@ -231,6 +257,7 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
     }
     double lam = load_rel * tr / (double)LP;
     lam = lam < 1e-30 ? 1e-30 : lam;
+    // Cholesky with reciprocal pivots: Lm[j][j] holds 1/L_jj
     bool pd = true;
 #pragma unroll
     for (int j = 0; j < LP; ++j) {
@@ -238,9 +265,8 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
         pd = pd && (d > 0.0);
-        const double ljj = sqrt(d);
-        Lm[j][j] = ljj;
-        const double inv = 1.0 / ljj;
+        const double inv = rsqrt(d);
+        Lm[j][j] = inv;
 #pragma unroll
         for (int i = j + 1; i < LP; ++i) {
             double t = Lm[i][j];
@@ -258,7 +284,7 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
             double t = ((double)pc[i] - ref[i]) - mu[i];
 #pragma unroll
             for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
-            z[i] = t / Lm[i][i];
+            z[i] = t * Lm[i][i];
             s += z[i] * z[i];
         }
         lrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
@@ -285,16 +311,16 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
             double t = sin_lin[i] * inv_ni - mu[i];
 #pragma unroll
             for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
-            z[i] = t / Lm[i][i];
+            z[i] = t * Lm[i][i];
             s += z[i] * z[i];
         }
         dwrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
     }
 }
 
-template <int LP> static size_t box_smem(int R)
+template <int LP, int GCMAX = 15> static size_t box_smem(int R)
 {
-    using C = BoxCfg<LP>;
+    using C = BoxCfg<LP, GCMAX>;
     const size_t EX = TX + 2 * R, EY = TY + 2 * R;
     return (size_t)TY * EX * C::GCP * sizeof(double) + EY * EX * (LP + 1) * sizeof(float);
 }
@@ -316,27 +342,53 @@ static size_t box_smem_lp(int64_t Lp, int R)
 
 static constexpr size_t kBoxMaxSmem = 144 * 1024;
 
+// LDS use of the default variant is at most that of the 15-feature chunk
 bool box_supported(int64_t Lp, const Windows &w)
 {
     return Lp >= 1 && Lp <= 8 && box_smem_lp(Lp, w.ro) <= kBoxMaxSmem;
+}
+
+static int g_box_gc = 0;   // 0: default feature chunk; 15 / 8 / 5 forced (tuning, tests)
+
+template <int LP, int GCMAX>
+static int box_launch_gc(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
+                         float *lrx, float *dwrx, hipStream_t s)
+{
+    const size_t sh = box_smem<LP, GCMAX>(w.ro);
+    if (int rc = allow_lds((const void *)box_lrx_dwrx_kernel<LP, GCMAX>, sh, "box_lrx_dwrx_kernel"))
+        return rc;
+    dim3 grid((unsigned)((W + TX - 1) / TX), (unsigned)((H + TY - 1) / TY)), block(NT);
+    hipLaunchKernelGGL((box_lrx_dwrx_kernel<LP, GCMAX>), grid, block, sh, s, x, (int)H, (int)W, w.ro,
+                       w.ri, w.inner > 0 ? 1 : 0, load_rel, lrx, dwrx);
+    return check_launch("box_lrx_dwrx_kernel");
 }
 
 template <int LP>
 static int box_launch(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
                       float *lrx, float *dwrx, hipStream_t s)
 {
-    const size_t sh = box_smem<LP>(w.ro);
-    if (int rc = allow_lds((const void *)box_lrx_dwrx_kernel<LP>, sh, "box_lrx_dwrx_kernel")) return rc;
-    dim3 grid((unsigned)((W + TX - 1) / TX), (unsigned)((H + TY - 1) / TY)), block(NT);
-    hipLaunchKernelGGL(box_lrx_dwrx_kernel<LP>, grid, block, sh, s, x, (int)H, (int)W, w.ro, w.ri,
-                       w.inner > 0 ? 1 : 0, load_rel, lrx, dwrx);
-    return check_launch("box_lrx_dwrx_kernel");
+    // default chunk width: measured fastest on gfx950 at 512 x 512 (5 features keep four
+    // workgroups resident per CU; 8 for L' = 5..7, where 5 spills registers)
+    const int gc = g_box_gc ? g_box_gc : ((LP >= 5 && LP <= 7) ? 8 : 5);
+    switch (gc) {
+    case 8: return box_launch_gc<LP, 8>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 15: return box_launch_gc<LP, 15>(x, H, W, w, load_rel, lrx, dwrx, s);
+    default: return box_launch_gc<LP, 5>(x, H, W, w, load_rel, lrx, dwrx, s);
+    }
 }
+
+int wave_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                         double load_rel, float *lrx, float *dwrx, hipStream_t s);
+bool wave_supported(int64_t Lp, const Windows &w);
+int box_variant();
 
 int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                         double load_rel, float *lrx, float *dwrx, hipStream_t s)
 {
     if (H > (1 << 24) || W > (1 << 24)) return fail(HSAD_EUNSUPPORTED, "box path: image too large");
+    const int v = box_variant();
+    if (v == 2 && wave_supported(Lp, w))
+        return wave_lrx_dwrx_launch(x, H, W, Lp, w, load_rel, lrx, dwrx, s);
     switch (Lp) {
     case 1: return box_launch<1>(x, H, W, w, load_rel, lrx, dwrx, s);
     case 2: return box_launch<2>(x, H, W, w, load_rel, lrx, dwrx, s);
@@ -351,3 +403,303 @@ int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const 
 }
 
 }  // namespace hsad
+
+extern "C" int hsad_internal_box_chunk(int gc)
+{
+    hsad::g_box_gc = gc;
+    return 0;
+}
+
+// =====================================================================================
+// Wave-row variant: no LDS tile, no workgroup barriers.
+//
+// One wavefront owns `rpw` consecutive output rows and 64 - 2R consecutive output
+// columns.  Lane l holds image column x0 - R + l.  It reads the 2R+1 pixels of its
+// column window directly from global memory (one coalesced vector load per row; the
+// reduced cube stays in L2), keeps the vertical box sums of every feature in registers
+// and slides them down the rows.  The horizontal window sums come from cross-lane
+// doubling: B1 = V, B2 = B1 + B1(l+1), B4, B8, ..., combined over the binary digits of the
+// window width.  Output lane l then holds the sums of lanes l .. l+2R, which is the outer
+// window of image column x0 + l.  Same features, exact FP64 sums and scoring as the tile
+// kernel above.
+// =====================================================================================
+namespace hsad {
+namespace {
+
+// sum over lanes l .. l+w-1 of v (lanes past 63 contribute their own value, never read
+// by an output lane because l + w - 1 <= 63 there)
+__device__ __forceinline__ double lane_window_sum(double v, int w)
+{
+    double blk = v;      // block of 2^k lanes starting at l
+    double acc = 0.0;
+    int off = 0;
+    for (int k = 0; (1 << k) <= w; ++k) {
+        if (w & (1 << k)) {
+            // take block of size 2^k starting at l + off
+            acc += __shfl_down(blk, off, 64);
+            off += 1 << k;
+        }
+        const int step = 1 << k;
+        if ((2 << k) <= w) blk += __shfl_down(blk, step, 64);
+    }
+    return acc;
+}
+
+template <int LP>
+__device__ __forceinline__ void load_pixel(const float *__restrict__ x, int H, int W, int gy,
+                                           int gx, const double *ref, double *f, double &b)
+{
+    b = 0.0;
+#pragma unroll
+    for (int i = 0; i < LP; ++i) f[i] = 0.0;
+    if (gy < 0 || gy >= H || gx < 0 || gx >= W) return;
+    const float *src = x + ((size_t)gy * W + gx) * LP;
+    float v[LP];
+    if constexpr (LP % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < LP / 4; ++k) {
+            const float4 q = reinterpret_cast<const float4 *>(src)[k];
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < LP; ++i) v[i] = src[i];
+    }
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < LP; ++i) fin = fin && isfinite(v[i]);
+    if (!fin) {
+        b = 1.0;
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < LP; ++i) f[i] = (double)v[i] - ref[i];
+}
+}  // namespace
+
+template <int LP, int RPW>
+__global__ __launch_bounds__(256) void wave_lrx_dwrx_kernel(const float *__restrict__ x, int H,
+                                                           int W, int R, int RI, int has_inner,
+                                                           double load_rel, int ncb, int nrb,
+                                                           float *__restrict__ lrx,
+                                                           float *__restrict__ dwrx)
+{
+    using C = BoxCfg<LP, 64>;   // one chunk: every feature in registers
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (wave >= ncb * nrb) return;
+    const int cb = wave % ncb, rbk = wave / ncb;
+    const int OUTW = 64 - 2 * R;
+    const int x0 = cb * OUTW, r0 = rbk * RPW;
+    const int gx = x0 - R + lane;
+
+    // wave-uniform reference pixel
+    double ref[LP];
+    {
+        const int ry = min(r0, H - 1), rx = min(x0 + OUTW / 2, W - 1);
+        const float *rp = x + ((size_t)ry * W + rx) * LP;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            const float v = rp[i];
+            ref[i] = isfinite(v) ? (double)v : 0.0;
+        }
+    }
+
+    double Vo[C::GT], Vi[C::GT];
+#pragma unroll
+    for (int g = 0; g < C::GT; ++g) {
+        Vo[g] = 0.0;
+        Vi[g] = 0.0;
+    }
+    for (int dy = -R; dy <= R; ++dy) {
+        double f[LP], b;
+        load_pixel<LP>(x, H, W, r0 + dy, gx, ref, f, b);
+        const bool inn = has_inner && dy >= -RI && dy <= RI;
+#pragma unroll
+        for (int g = 0; g < C::GT; ++g) {
+            const double v = feat<LP>(f, b, g);
+            Vo[g] += v;
+            if (inn) Vi[g] += v;
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int r = r0 + i;
+        if (i > 0) {
+            if (r >= H) break;
+            double fa[LP], ba, fb[LP], bb;
+            load_pixel<LP>(x, H, W, r + R, gx, ref, fa, ba);
+            load_pixel<LP>(x, H, W, r - R - 1, gx, ref, fb, bb);
+#pragma unroll
+            for (int g = 0; g < C::GT; ++g) Vo[g] += feat<LP>(fa, ba, g) - feat<LP>(fb, bb, g);
+            if (has_inner) {
+                load_pixel<LP>(x, H, W, r + RI, gx, ref, fa, ba);
+                load_pixel<LP>(x, H, W, r - RI - 1, gx, ref, fb, bb);
+#pragma unroll
+                for (int g = 0; g < C::GT; ++g) Vi[g] += feat<LP>(fa, ba, g) - feat<LP>(fb, bb, g);
+            }
+        }
+        // horizontal sums: outer over lanes l..l+2R, inner over lanes l+R-RI..l+R+RI
+        double S[C::GT];
+        double sin_lin[LP];
+        double in_bad = 0.0;
+#pragma unroll
+        for (int g = 0; g < C::GT; ++g) {
+            double so = lane_window_sum(Vo[g], 2 * R + 1);
+            if (has_inner) {
+                const double si = __shfl_down(lane_window_sum(Vi[g], 2 * RI + 1), R - RI, 64);
+                so -= si;
+                if (g < LP) sin_lin[g] = si;
+                if (g == C::G) in_bad = si;
+            }
+            S[g] = so;
+        }
+        if (!has_inner) {
+#pragma unroll
+            for (int k = 0; k < LP; ++k) sin_lin[k] = 0.0;
+        }
+        const int px = x0 + lane;
+        if (lane >= OUTW || px >= W || r >= H) continue;
+
+        const int n_o = clip_count(r, R, H) * clip_count(px, R, W);
+        const int n_i = has_inner ? clip_count(r, RI, H) * clip_count(px, RI, W) : 0;
+        const double inv_na = 1.0 / (double)(n_o - n_i);
+        const bool ann_bad = S[C::G] > 0.5;
+        double mu[LP];
+#pragma unroll
+        for (int k = 0; k < LP; ++k) mu[k] = S[k] * inv_na;
+        double Lm[LP][LP];
+        double tr = 0.0;
+        {
+            int g = LP;
+#pragma unroll
+            for (int a = 0; a < LP; ++a)
+#pragma unroll
+                for (int c = a; c < LP; ++c) {
+                    const double cv = S[g++] * inv_na - mu[a] * mu[c];
+                    Lm[c][a] = cv;
+                    if (a == c) tr += cv;
+                }
+        }
+        double lam = load_rel * tr / (double)LP;
+        lam = lam < 1e-30 ? 1e-30 : lam;
+        bool pd = true;
+#pragma unroll
+        for (int j = 0; j < LP; ++j) {
+            double d = Lm[j][j] + lam;
+#pragma unroll
+            for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
+            pd = pd && (d > 0.0);
+            const double inv = rsqrt(d);
+            Lm[j][j] = inv;
+#pragma unroll
+            for (int a = j + 1; a < LP; ++a) {
+                double t = Lm[a][j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) t -= Lm[a][k] * Lm[j][k];
+                Lm[a][j] = t * inv;
+            }
+        }
+        const size_t o = (size_t)r * W + px;
+        if (lrx) {
+            const float *pc = x + o * LP;
+            double z[LP], s = 0.0;
+#pragma unroll
+            for (int a = 0; a < LP; ++a) {
+                double t = ((double)pc[a] - ref[a]) - mu[a];
+#pragma unroll
+                for (int k = 0; k < a; ++k) t -= Lm[a][k] * z[k];
+                z[a] = t * Lm[a][a];
+                s += z[a] * z[a];
+            }
+            lrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
+        }
+        if (dwrx) {
+            if (in_bad > 0.5) {
+#pragma unroll
+                for (int k = 0; k < LP; ++k) sin_lin[k] = 0.0;
+                for (int dy = -RI; dy <= RI; ++dy)
+                    for (int dx = -RI; dx <= RI; ++dx) {
+                        const int yy = r + dy, xx = px + dx;
+                        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                        const float *raw = x + ((size_t)yy * W + xx) * LP;
+#pragma unroll
+                        for (int k = 0; k < LP; ++k) sin_lin[k] += (double)raw[k] - ref[k];
+                    }
+            }
+            const double inv_ni = 1.0 / (double)n_i;
+            double z[LP], s = 0.0;
+#pragma unroll
+            for (int a = 0; a < LP; ++a) {
+                double t = sin_lin[a] * inv_ni - mu[a];
+#pragma unroll
+                for (int k = 0; k < a; ++k) t -= Lm[a][k] * z[k];
+                z[a] = t * Lm[a][a];
+                s += z[a] * z[a];
+            }
+            dwrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
+        }
+    }
+}
+
+static int g_box_variant = 0;   // 0 auto, 1 tile kernel, 2 wave-row kernel
+
+static int g_wave_rpw = 2;
+
+template <int LP, int RPW>
+static int wave_launch_rpw(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
+                           float *lrx, float *dwrx, hipStream_t s)
+{
+    const int outw = 64 - 2 * w.ro;
+    const int ncb = (int)((W + outw - 1) / outw);
+    const int nrb = (int)((H + RPW - 1) / RPW);
+    const int64_t waves = (int64_t)ncb * nrb;
+    dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+    hipLaunchKernelGGL((wave_lrx_dwrx_kernel<LP, RPW>), grid, block, 0, s, x, (int)H, (int)W, w.ro,
+                       w.ri, w.inner > 0 ? 1 : 0, load_rel, ncb, nrb, lrx, dwrx);
+    return check_launch("wave_lrx_dwrx_kernel");
+}
+
+template <int LP>
+static int wave_launch(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
+                       float *lrx, float *dwrx, hipStream_t s)
+{
+    switch (g_wave_rpw) {
+    case 1: return wave_launch_rpw<LP, 1>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 4: return wave_launch_rpw<LP, 4>(x, H, W, w, load_rel, lrx, dwrx, s);
+    default: return wave_launch_rpw<LP, 2>(x, H, W, w, load_rel, lrx, dwrx, s);
+    }
+}
+
+bool wave_supported(int64_t Lp, const Windows &w) { return Lp >= 1 && Lp <= 8 && 2 * w.ro <= 40; }
+
+int box_variant() { return g_box_variant; }
+
+int wave_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                         double load_rel, float *lrx, float *dwrx, hipStream_t s)
+{
+    switch (Lp) {
+    case 1: return wave_launch<1>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 2: return wave_launch<2>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 3: return wave_launch<3>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 4: return wave_launch<4>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 5: return wave_launch<5>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 6: return wave_launch<6>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 7: return wave_launch<7>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 8: return wave_launch<8>(x, H, W, w, load_rel, lrx, dwrx, s);
+    default: return fail(HSAD_EUNSUPPORTED, "wave path: L' > 8");
+    }
+}
+
+}  // namespace hsad
+
+extern "C" int hsad_internal_box_variant(int variant, int rpw)
+{
+    hsad::g_box_variant = variant;
+    if (rpw == 1 || rpw == 2 || rpw == 4) hsad::g_wave_rpw = rpw;
+    return 0;
+}
