@@ -22,9 +22,17 @@ size_t generic_ws_per_pixel(int64_t Lp, GramMode)
     return (size_t)((Lp + 2) * Lp) * sizeof(double);
 }
 
+// Pixels per chunk.  A chunk's workspace is written by the Gram kernel and read back by
+// the factorisation right after.  Up to 192 MiB it stays in the 256 MB Infinity Cache,
+// but a chunk also needs about 8192 pixels (one wavefront each) to fill the 256 CUs.
+// The cap is the larger of the two.
 static int64_t chunk_pixels(int64_t total, int64_t Lp, size_t ws_bytes)
 {
-    int64_t P = (int64_t)(ws_bytes / generic_ws_per_pixel(Lp, GRAM_LRX));
+    const int64_t per = (int64_t)generic_ws_per_pixel(Lp, GRAM_LRX);
+    int64_t P = (int64_t)(ws_bytes / per);
+    int64_t cap = ((int64_t)192 << 20) / per;
+    if (cap < 8192) cap = 8192;
+    if (P > cap) P = cap;
     if (P > total) P = total;
     if (P > (1 << 30)) P = 1 << 30;
     return P;

@@ -22,6 +22,8 @@
 //   DWEST mode: rows 0..L'-1 = C_diff, row L' = m_in - mu_a (eq. 3)
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace hsad {
@@ -42,7 +44,6 @@ struct GramArgs {
     uint32_t outer_magic;  // ceil(2^32 / outer) for k / outer
 };
 
-static constexpr int kMaxTilesPerPass = 16;
 
 __device__ __forceinline__ bool sample_pos(const GramArgs &a, int py, int px, int k, int &sy,
                                            int &sx, bool &in_inner)
@@ -63,7 +64,7 @@ __device__ __forceinline__ int clipn(int c, int r, int n)
 }
 
 // Layout of one wave's LDS region (doubles): stage[T][64] then mu[Lpad], mi[Lpad].
-template <int PREC>
+template <int PREC, int kMaxTilesPerPass>
 __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_block)
 {
     extern __shared__ double lds[];
@@ -133,29 +134,35 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_blo
     // inner samples only feed DWEST; annulus samples feed both modes
     const int nsets = a.mode == GRAM_DWEST ? 2 : 1;
 
+    using Acc = typename std::conditional<PREC == 0, f64x4, f32x4>::type;
     for (int t0 = 0; t0 < ntiles; t0 += kMaxTilesPerPass) {
         const int nt = ntiles - t0 < kMaxTilesPerPass ? ntiles - t0 : kMaxTilesPerPass;
         // tile t of this pass -> (bi, bj), row-major over the upper triangle
         int tbi[kMaxTilesPerPass], tbj[kMaxTilesPerPass];
-#pragma unroll
-        for (int t = 0; t < kMaxTilesPerPass; ++t) {
-            int rem = t0 + t, bi = 0;
+        {
+            int rem = t0, bi = 0;
             while (bi < T && rem >= T - bi) {
                 rem -= T - bi;
                 ++bi;
             }
-            tbi[t] = bi;
-            tbj[t] = bi + rem;
-        }
-        f32x4 accf[kMaxTilesPerPass];
-        f64x4 accd[kMaxTilesPerPass];
+            int bj = bi + rem;
 #pragma unroll
-        for (int t = 0; t < kMaxTilesPerPass; ++t) {
-            accf[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            accd[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int t = 0; t < kMaxTilesPerPass; ++t) {
+                tbi[t] = bi;
+                tbj[t] = bj;
+                if (++bj >= T) {
+                    ++bi;
+                    bj = bi;
+                }
+            }
         }
+        Acc acc[kMaxTilesPerPass];
+#pragma unroll
+        for (int t = 0; t < kMaxTilesPerPass; ++t)
+            for (int e = 0; e < 4; ++e) acc[t][e] = 0;
         for (int set = 0; set < nsets; ++set) {
             // set 0: annulus (weight wa), set 1: inner window (weight wi)
+            const double w = set == 0 ? wa : wi;
             for (int k0 = 0; k0 < K; k0 += KG) {
                 // stage this lane's centred values for every block
                 for (int b = 0; b < T; ++b) {
@@ -193,26 +200,26 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_blo
                         }
                     }
                 }
-                const double w = set == 0 ? wa : wi;
 #pragma unroll
                 for (int t = 0; t < kMaxTilesPerPass; ++t) {
-                    if (t >= nt) break;
-                    const int bi = tbi[t], bj = tbj[t];
-                    if constexpr (PREC == 0) {
-                        const double av = stage[bi * 64 + lane] * w, bv = stage[bj * 64 + lane];
-                        accd[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accd[t], 0, 0, 0);
-                    } else if constexpr (PREC == 1) {
-                        const float *sf = reinterpret_cast<const float *>(stage);
-                        accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sf[bi * 64 + lane], sf[bj * 64 + lane],
-                                                                       accf[t], 0, 0, 0);
-                    } else if constexpr (PREC == 2) {
-                        const bf16x8 *s8 = reinterpret_cast<const bf16x8 *>(stage);
-                        accf[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s8[bi * 64 + lane], s8[bj * 64 + lane],
-                                                                          accf[t], 0, 0, 0);
-                    } else {
-                        const f16x8 *s8 = reinterpret_cast<const f16x8 *>(stage);
-                        accf[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(s8[bi * 64 + lane], s8[bj * 64 + lane],
-                                                                         accf[t], 0, 0, 0);
+                    if (t < nt) {
+                        const int bi = tbi[t], bj = tbj[t];
+                        if constexpr (PREC == 0) {
+                            const double av = stage[bi * 64 + lane] * w, bv = stage[bj * 64 + lane];
+                            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                        } else if constexpr (PREC == 1) {
+                            const float *sf = reinterpret_cast<const float *>(stage);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sf[bi * 64 + lane], sf[bj * 64 + lane],
+                                                                          acc[t], 0, 0, 0);
+                        } else if constexpr (PREC == 2) {
+                            const bf16x8 *s8 = reinterpret_cast<const bf16x8 *>(stage);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s8[bi * 64 + lane], s8[bj * 64 + lane],
+                                                                             acc[t], 0, 0, 0);
+                        } else {
+                            const f16x8 *s8 = reinterpret_cast<const f16x8 *>(stage);
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(s8[bi * 64 + lane], s8[bj * 64 + lane],
+                                                                            acc[t], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -220,18 +227,19 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_blo
         // write the tiles (and their mirror images) scaled to covariances
 #pragma unroll
         for (int t = 0; t < kMaxTilesPerPass; ++t) {
-            if (t >= nt) break;
-            const int bi = tbi[t], bj = tbj[t];
+            if (t < nt) {
+                const int bi = tbi[t], bj = tbj[t];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                // output element e of lane l: FP64 16x16x4 puts it at row 4e + (l>>4),
-                // the FP32/BF16/FP16 16x16 variants at row 4(l>>4) + e; column l&15
-                const int r = 16 * bi + (PREC == 0 ? 4 * e + g4 : 4 * g4 + e), c = 16 * bj + c16;
-                const double v = (PREC == 0 ? accd[t][e] : (double)accf[t][e]) * scale_out;
-                // one writer per symmetric pair keeps the result deterministic
-                if (r < a.Lp && c < a.Lp && (bi < bj || r <= c)) {
-                    out[(size_t)r * a.Lp + c] = v;
-                    out[(size_t)c * a.Lp + r] = v;
+                for (int e = 0; e < 4; ++e) {
+                    // output element e of lane l: FP64 16x16x4 puts it at row 4e + (l>>4),
+                    // the FP32/BF16/FP16 16x16 variants at row 4(l>>4) + e; column l&15
+                    const int r = 16 * bi + (PREC == 0 ? 4 * e + g4 : 4 * g4 + e), c = 16 * bj + c16;
+                    const double v = (double)acc[t][e] * scale_out;
+                    // one writer per symmetric pair keeps the result deterministic
+                    if (r < a.Lp && c < a.Lp && (bi < bj || r <= c)) {
+                        out[(size_t)r * a.Lp + c] = v;
+                        out[(size_t)c * a.Lp + r] = v;
+                    }
                 }
             }
         }
@@ -268,24 +276,31 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
     const size_t sh = per_wave * wpb;
     if (sh > 160 * 1024) return fail(HSAD_EUNSUPPORTED, "gram: L' too large for LDS staging");
     dim3 grid((unsigned)((npix + wpb - 1) / wpb)), block(64 * wpb);
-    switch (prec) {
-    case GP_FP64:
-        if (int rc = allow_lds((const void *)gram_kernel<0>, sh, "gram_kernel")) return rc;
-        hipLaunchKernelGGL(gram_kernel<0>, grid, block, sh, s, a, wpb);
-        break;
-    case GP_FP32:
-        if (int rc = allow_lds((const void *)gram_kernel<1>, sh, "gram_kernel")) return rc;
-        hipLaunchKernelGGL(gram_kernel<1>, grid, block, sh, s, a, wpb);
-        break;
-    case GP_BF16:
-        if (int rc = allow_lds((const void *)gram_kernel<2>, sh, "gram_kernel")) return rc;
-        hipLaunchKernelGGL(gram_kernel<2>, grid, block, sh, s, a, wpb);
-        break;
-    default:
-        if (int rc = allow_lds((const void *)gram_kernel<3>, sh, "gram_kernel")) return rc;
-        hipLaunchKernelGGL(gram_kernel<3>, grid, block, sh, s, a, wpb);
-        break;
+    const int T = (int)((Lp + 15) / 16);
+    const int ntiles = T * (T + 1) / 2;
+    const int mt = ntiles <= 1 ? 1 : ntiles <= 3 ? 3 : ntiles <= 6 ? 6 : ntiles <= 10 ? 10 : 16;
+    int rc = HSAD_OK;
+#define HSAD_GRAM_LAUNCH(P, M)                                                                   \
+    do {                                                                                         \
+        if ((rc = allow_lds((const void *)gram_kernel<P, M>, sh, "gram_kernel"))) return rc;     \
+        hipLaunchKernelGGL((gram_kernel<P, M>), grid, block, sh, s, a, wpb);                     \
+    } while (0)
+#define HSAD_GRAM_MT(P)                                                                          \
+    switch (mt) {                                                                                \
+    case 1: HSAD_GRAM_LAUNCH(P, 1); break;                                                       \
+    case 3: HSAD_GRAM_LAUNCH(P, 3); break;                                                       \
+    case 6: HSAD_GRAM_LAUNCH(P, 6); break;                                                       \
+    case 10: HSAD_GRAM_LAUNCH(P, 10); break;                                                     \
+    default: HSAD_GRAM_LAUNCH(P, 16); break;                                                     \
     }
+    switch (prec) {
+    case GP_FP64: HSAD_GRAM_MT(0); break;
+    case GP_FP32: HSAD_GRAM_MT(1); break;
+    case GP_BF16: HSAD_GRAM_MT(2); break;
+    default: HSAD_GRAM_MT(3); break;
+    }
+#undef HSAD_GRAM_MT
+#undef HSAD_GRAM_LAUNCH
     return check_launch("gram_kernel");
 }
 
