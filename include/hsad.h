@@ -169,6 +169,74 @@ size_t hsad_auc_workspace_bytes(int64_t n);
 int hsad_auc(const float *scores, const uint8_t *truth, int64_t n, uint64_t *counts, void *ws,
              size_t ws_bytes, hipStream_t stream);
 
+
+/* ---------------------------------------------------------------------------------------
+ * Uneven batches of scenes (persistent work-queue kernels, graph-capturable runs)
+ * -------------------------------------------------------------------------------------*/
+typedef struct hsad_scene {
+    const float *cube;  /* device, H*W*L float32 [y][x][band] */
+    float *approx;      /* device, H*W*L' float32, written (reduced cube) */
+    float *lrx;         /* device, H*W float32, written, or NULL */
+    float *dwrx;        /* device, H*W float32, written, or NULL (needs params.inner >= 1) */
+    int64_t H, W, L;    /* L <= 4096, H*W <= 2^30 */
+    int32_t levels;     /* DWT depth (Sec. 3); the reduced length L' must be <= 128 */
+    int32_t reserved;   /* must be 0 */
+    hsad_window_params params; /* precision must be AUTO or FP64 */
+} hsad_scene;
+
+typedef struct hsad_batch_options {
+    int32_t wgs_per_cu;   /* persistent workgroups per CU (1..16) */
+    int32_t dwt_pixels;   /* pixels per DWT work item, 0 = as many as fit 48 KiB of LDS */
+    int64_t chunk_bytes;  /* Gram/Cholesky scratch per chunk (>= 1 MiB) */
+    int32_t reserved;     /* must be 0 */
+    int32_t pad;
+} hsad_batch_options;
+
+typedef struct hsad_batch_plan hsad_batch_plan;   /* opaque, host memory */
+
+/* Default options (what hsad_batch_plan_create uses when opt is NULL). */
+void hsad_batch_default_options(hsad_batch_options *opt);
+
+/* Host-only: validates every scene and builds the work lists.  The detectors are the same
+ * as hsad_dwt + hsad_lrx_dwrx per scene (same definitions and tolerances): scenes with
+ * L' <= 8 go through the box-sum bucket, the others through the matrix-core Gram and FP64
+ * Cholesky.  The work is ordered by estimated cost (largest first) and cut into items.
+ * Errors: HSAD_EINVAL (NULL, sizes, windows, options), HSAD_EUNSUPPORTED (L' > 128). */
+int hsad_batch_plan_create(const hsad_scene *scenes, int n, const hsad_batch_options *opt,
+                           hsad_batch_plan **plan);
+
+/* Device workspace the plan needs (queue counters, tables, Gram scratch). */
+size_t hsad_batch_workspace_bytes(const hsad_batch_plan *plan);
+
+/* Copies the plan's tables into ws and synchronises `stream` (one time, not capturable). */
+int hsad_batch_upload(hsad_batch_plan *plan, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Enqueues the whole batch on `stream`: a counter reset (fill kernel), one persistent DWT
+ * kernel, one persistent kernel per box bucket, and per Gram chunk the persistent Gram
+ * kernels and one persistent Cholesky kernel.  No allocation, copy, memset or host
+ * synchronisation, so it may be captured into a HIP graph and replayed.  ws must be the
+ * workspace passed to hsad_batch_upload; runs on one workspace must not overlap. */
+int hsad_batch_run(const hsad_batch_plan *plan, void *ws, hipStream_t stream);
+
+/* Frees the host plan. */
+int hsad_batch_plan_destroy(hsad_batch_plan *plan);
+
+/* Autotuner: times every candidate schedule on this batch with HIP events, one warm-up
+ * and one timed run each, and stores the fastest in *best.  The candidates cover
+ * persistent workgroups per CU {1,2,4}, DWT item size {max, 8} and Gram chunk bytes
+ * {1 GiB, 4 GiB}; those whose workspace exceeds ws_bytes are skipped.  If cache_path
+ * is not NULL, the result is cached there as JSON keyed by GPU architecture and batch
+ * signature, and a cached entry is returned without timing (*best_ms = -1).  ws is
+ * overwritten.  Synchronises `stream`.
+ * Errors: HSAD_EINVAL, HSAD_ENOMEM (no candidate fits), HSAD_EHIP. */
+int hsad_batch_autotune(const hsad_scene *scenes, int n, void *ws, size_t ws_bytes,
+                        hipStream_t stream, const char *cache_path, hsad_batch_options *best,
+                        double *best_ms);
+
+/* info[0..7] = {scenes, pixels, DWT items, box items, Gram items, Gram chunks,
+ * box-bucket pixels, Gram-bucket pixels}; n >= 8. */
+int hsad_batch_plan_info(const hsad_batch_plan *plan, int64_t *info, int n);
+
 #ifdef __cplusplus
 }
 #endif

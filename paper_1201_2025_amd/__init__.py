@@ -17,5 +17,6 @@ from ._binding import (  # noqa: F401
     hsad_dwest, hsad_dwrx, hsad_dwt, hsad_dwt_out_len, hsad_last_error, hsad_levels_for,
     hsad_lrx, hsad_lrx_dwrx, hsad_version, hsad_workspace_bytes, lib, lib_path,
     hsad_threshold, hsad_threshold_workspace_bytes, hsad_auc, hsad_auc_workspace_bytes,
-    auc_from_counts,
+    auc_from_counts, BatchPlan, BatchOptions, Scene, batch_default_options,
+    hsad_batch_autotune,
 )

@@ -31,6 +31,18 @@ class WindowParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class Scene(ctypes.Structure):
+    _fields_ = [("cube", ctypes.c_void_p), ("approx", ctypes.c_void_p), ("lrx", ctypes.c_void_p),
+                ("dwrx", ctypes.c_void_p), ("H", ctypes.c_int64), ("W", ctypes.c_int64),
+                ("L", ctypes.c_int64), ("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("params", WindowParams)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("wgs_per_cu", ctypes.c_int32), ("dwt_pixels", ctypes.c_int32),
+                ("chunk_bytes", ctypes.c_int64), ("reserved", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -54,6 +66,17 @@ SIGNATURES = [
     ("hsad_threshold", ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_auc_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("hsad_auc", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_batch_default_options", None, [ctypes.POINTER(BatchOptions)]),
+    ("hsad_batch_plan_create", ctypes.c_int, [ctypes.POINTER(Scene), ctypes.c_int,
+                                              ctypes.POINTER(BatchOptions), ctypes.POINTER(_vp)]),
+    ("hsad_batch_workspace_bytes", ctypes.c_size_t, [_vp]),
+    ("hsad_batch_upload", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_batch_run", ctypes.c_int, [_vp, _vp, _vp]),
+    ("hsad_batch_plan_destroy", ctypes.c_int, [_vp]),
+    ("hsad_batch_plan_info", ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.c_int]),
+    ("hsad_batch_autotune", ctypes.c_int, [ctypes.POINTER(Scene), ctypes.c_int, _vp, ctypes.c_size_t,
+                                           _vp, ctypes.c_char_p, ctypes.POINTER(BatchOptions),
+                                           ctypes.POINTER(ctypes.c_double)]),
 ]
 
 
@@ -297,3 +320,90 @@ def hsad_auc(scores, truth, counts=None, ws=None, stream=None):
 def auc_from_counts(counts) -> float:
     g, e, npos, nneg = [int(v) for v in counts.tolist()]
     return (g + 0.5 * e) / (npos * nneg) if npos and nneg else float("nan")
+
+
+def batch_default_options() -> BatchOptions:
+    o = BatchOptions()
+    lib().hsad_batch_default_options(ctypes.byref(o))
+    return o
+
+
+def batch_scene_array(scenes):
+    """(ctypes Scene array, outputs) for a list of scene dicts (see BatchPlan)."""
+    torch = _torch()
+    arr = (Scene * len(scenes))()
+    outs = []
+    for i, sc in enumerate(scenes):
+        cube = sc["cube"]
+        _dev(cube, "cube", torch.float32, 3)
+        H, W, L = cube.shape
+        Lp = hsad_dwt_out_len(L, sc["levels"])
+        a = torch.empty((H, W, Lp), dtype=torch.float32, device=cube.device)
+        lr = torch.empty((H, W), dtype=torch.float32, device=cube.device) if sc.get("lrx", True) else None
+        dw = torch.empty((H, W), dtype=torch.float32, device=cube.device) if sc.get("dwrx", True) else None
+        arr[i] = Scene(cube.data_ptr(), a.data_ptr(), lr.data_ptr() if lr is not None else None,
+                       dw.data_ptr() if dw is not None else None, H, W, L, int(sc["levels"]), 0,
+                       _params(sc["inner"], sc["outer"], sc.get("load_rel", 1e-6), HSAD_PREC_AUTO))
+        outs.append((a, lr, dw))
+    return arr, outs
+
+
+def hsad_batch_autotune(scenes, ws, cache_path=None, stream=None):
+    """Autotunes the batch schedule; returns (BatchOptions, measured ms or -1 if cached)."""
+    arr, keep = batch_scene_array(scenes)
+    best = BatchOptions()
+    ms = ctypes.c_double(0.0)
+    rc = lib().hsad_batch_autotune(arr, len(scenes), ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel() * ws.element_size(), _stream(stream),
+                                   cache_path.encode() if cache_path else None, ctypes.byref(best),
+                                   ctypes.byref(ms))
+    _check("hsad_batch_autotune", rc)
+    return best, ms.value
+
+
+class BatchPlan:
+    """An uneven batch of scenes run by the persistent batch kernels.
+
+    scenes: list of dicts with keys cube (GPU float32 tensor H x W x L), levels, inner, outer,
+    load_rel (default 1e-6), lrx / dwrx (bool, default True).  Outputs are allocated here:
+    self.approx[i], self.lrx[i], self.dwrx[i].  run() enqueues the batch on the current
+    stream and can be captured in a CUDA/HIP graph."""
+
+    def __init__(self, scenes, options: BatchOptions | None = None, stream=None):
+        torch = _torch()
+        arr, outs = batch_scene_array(scenes)
+        self.approx = [o[0] for o in outs]
+        self.lrx = [o[1] for o in outs]
+        self.dwrx = [o[2] for o in outs]
+        self._keep = [sc["cube"] for sc in scenes]
+        self._arr = arr
+        self.plan = ctypes.c_void_p()
+        opt = ctypes.byref(options) if options is not None else None
+        _check("hsad_batch_plan_create",
+               lib().hsad_batch_plan_create(arr, len(scenes), opt, ctypes.byref(self.plan)))
+        nbytes = int(lib().hsad_batch_workspace_bytes(self.plan))
+        self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=scenes[0]["cube"].device)
+        _check("hsad_batch_upload", lib().hsad_batch_upload(self.plan, ctypes.c_void_p(self.ws.data_ptr()),
+                                                            nbytes, _stream(stream)))
+
+    def run(self, stream=None):
+        _check("hsad_batch_run", lib().hsad_batch_run(self.plan, ctypes.c_void_p(self.ws.data_ptr()),
+                                                      _stream(stream)))
+
+    def info(self) -> dict:
+        a = (_i64 * 8)()
+        _check("hsad_batch_plan_info", lib().hsad_batch_plan_info(self.plan, a, 8))
+        keys = ["scenes", "pixels", "dwt_items", "box_items", "gram_items", "gram_chunks",
+                "box_pixels", "gram_pixels"]
+        return dict(zip(keys, [int(v) for v in a]))
+
+    def close(self):
+        if self.plan:
+            lib().hsad_batch_plan_destroy(self.plan)
+            self.plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

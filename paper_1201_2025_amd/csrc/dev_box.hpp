@@ -1,0 +1,295 @@
+// dev_box.hpp -- device body of the fused box-sum LRX/DWRX tile (window statistics,
+// loading, Cholesky and scores for L' <= 8), shared by the per-cube kernel and the
+// persistent batch kernel.  See box.hip for the method notes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hsad {
+
+constexpr int TX = 16, TY = 16, NT = TX * TY;
+constexpr int RB = 4;                 // output rows per vertical-sum job
+constexpr int NRB = TY / RB;
+
+template <int LP, int GCMAX = 15> struct BoxCfg {
+    static constexpr int G = LP + LP * (LP + 1) / 2;   // moment features
+    static constexpr int GT = G + 1;                   // + non-finite indicator
+    static constexpr int GC = GT < GCMAX ? GT : GCMAX; // features per LDS chunk
+    static constexpr int GCP = GC | 1;                 // odd stride (bank spread)
+    static constexpr int NCH = (GT + GC - 1) / GC;
+};
+
+// Feature g of a pixel with centred values f[] and flag b (g is a compile-time constant
+// after unrolling).
+template <int LP> __device__ __forceinline__ double feat(const double *f, double b, int g)
+{
+    if (g < LP) return f[g];
+    if (g >= BoxCfg<LP>::G) return b;
+    int r = g - LP, i = 0, len = LP;
+    while (r >= len) {
+        r -= len;
+        --len;
+        ++i;
+    }
+    return f[i] * f[i + r];
+}
+
+// Centred values of tile pixel t (FP64, exact).
+template <int LP>
+__device__ __forceinline__ void centred(const float *xs, size_t t, const double *ref, double *f)
+{
+    if constexpr (LP % 4 == 0) {
+        const float4 *q = reinterpret_cast<const float4 *>(xs + t * LP);
+#pragma unroll
+        for (int k = 0; k < LP / 4; ++k) {
+            const float4 v = q[k];
+            f[4 * k] = (double)v.x - ref[4 * k];
+            f[4 * k + 1] = (double)v.y - ref[4 * k + 1];
+            f[4 * k + 2] = (double)v.z - ref[4 * k + 2];
+            f[4 * k + 3] = (double)v.w - ref[4 * k + 3];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < LP; ++i) f[i] = (double)xs[t * LP + i] - ref[i];
+    }
+}
+
+__device__ __forceinline__ int clip_count(int c, int r, int n)
+{
+    const int lo = c - r < 0 ? 0 : c - r;
+    const int hi = c + r > n - 1 ? n - 1 : c + r;
+    return hi - lo + 1;
+}
+
+template <int LP, int GCMAX>
+__device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R, int RI,
+                                int has_inner, double load_rel, float *__restrict__ lrx,
+                                float *__restrict__ dwrx, int by, int bx, double *smem)
+{
+    using C = BoxCfg<LP, GCMAX>;
+    const int EX = TX + 2 * R, EY = TY + 2 * R;
+    double *V = smem;                                                    // TY*EX*GCP
+    float *xs = reinterpret_cast<float *>(smem + (size_t)TY * EX * C::GCP);   // EY*EX*LP
+    float *bad = xs + (size_t)EY * EX * LP;                              // EY*EX
+
+    const int tid = threadIdx.x;
+    const int y0 = by * TY, x0 = bx * TX;
+
+    double ref[LP];
+    {
+        const int ry = min(y0 + TY / 2, H - 1), rx = min(x0 + TX / 2, W - 1);
+        const float *rp = x + ((size_t)ry * W + rx) * LP;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            const float v = rp[i];
+            ref[i] = isfinite(v) ? (double)v : 0.0;
+        }
+    }
+
+    // 1. halo tile
+    for (int t = tid; t < EY * EX; t += NT) {
+        const int ey = t / EX, ex = t - ey * EX;
+        const int gy = y0 - R + ey, gx = x0 - R + ex;
+        float v[LP];
+        bool ok = false, fin = true;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            const float *src = x + ((size_t)gy * W + gx) * LP;
+            ok = true;
+#pragma unroll
+            for (int i = 0; i < LP; ++i) {
+                v[i] = src[i];
+                fin = fin && isfinite(v[i]);
+            }
+        }
+        float *dst = xs + (size_t)t * LP;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) dst[i] = (ok && fin) ? v[i] : (float)ref[i];
+        bad[t] = (ok && !fin) ? 1.0f : 0.0f;
+    }
+    __syncthreads();
+
+    const int ty = tid / TX, tx = tid - ty * TX;
+    const int py = y0 + ty, px = x0 + tx;
+
+    double S[C::GT];        // annulus sums (outer minus inner)
+    double sin_lin[LP];     // inner-window linear sums (DWRX mean)
+    double in_bad = 0.0;
+#pragma unroll
+    for (int g = 0; g < C::GT; ++g) S[g] = 0.0;
+#pragma unroll
+    for (int i = 0; i < LP; ++i) sin_lin[i] = 0.0;
+
+#pragma unroll
+    for (int ch = 0; ch < C::NCH; ++ch) {
+        const int g0 = ch * C::GC;
+        for (int win = has_inner ? 0 : 1; win < 2; ++win) {
+            // win 0: inner window (half RI), win 1: outer window (half R)
+            const int h = win == 0 ? RI : R;
+            const int eoff = R - h;            // first extended row/col of the window
+            // 2a. vertical sums: job = (column c, row block rb)
+            for (int job = tid; job < EX * NRB; job += NT) {
+                const int rb = job / EX, c = job - rb * EX;
+                const int r0 = rb * RB;
+                double acc[C::GC];
+#pragma unroll
+                for (int gg = 0; gg < C::GC; ++gg) acc[gg] = 0.0;
+                for (int ey = r0 + eoff; ey <= r0 + eoff + 2 * h; ++ey) {
+                    const size_t t = (size_t)ey * EX + c;
+                    double f[LP];
+                    centred<LP>(xs, t, ref, f);
+                    const double b = (double)bad[t];
+#pragma unroll
+                    for (int gg = 0; gg < C::GC; ++gg)
+                        if (g0 + gg < C::GT) acc[gg] += feat<LP>(f, b, g0 + gg);
+                }
+                double *vr = V + ((size_t)r0 * EX + c) * C::GCP;
+#pragma unroll
+                for (int gg = 0; gg < C::GC; ++gg) vr[gg] = acc[gg];
+#pragma unroll
+                for (int r = 1; r < RB; ++r) {
+                    const size_t ta = (size_t)(r0 + r + eoff + 2 * h) * EX + c;
+                    const size_t tb = (size_t)(r0 + r - 1 + eoff) * EX + c;
+                    double fa[LP], fb[LP];
+                    centred<LP>(xs, ta, ref, fa);
+                    centred<LP>(xs, tb, ref, fb);
+                    const double ba = (double)bad[ta], bb = (double)bad[tb];
+#pragma unroll
+                    for (int gg = 0; gg < C::GC; ++gg)
+                        if (g0 + gg < C::GT)
+                            acc[gg] += feat<LP>(fa, ba, g0 + gg) - feat<LP>(fb, bb, g0 + gg);
+                    double *vq = V + ((size_t)(r0 + r) * EX + c) * C::GCP;
+#pragma unroll
+                    for (int gg = 0; gg < C::GC; ++gg) vq[gg] = acc[gg];
+                }
+            }
+            __syncthreads();
+            // 2b. running (prefix) sums along each tile row, in place: V[ty][c] becomes
+            //     sum_{c' <= c} V[ty][c'], one thread per (row, feature)
+            for (int job = tid; job < TY * C::GC; job += NT) {
+                const int r = job / C::GC, gg = job - r * C::GC;
+                double run = 0.0;
+                double *v = V + (size_t)r * EX * C::GCP + gg;
+                for (int c = 0; c < EX; ++c) {
+                    run += v[(size_t)c * C::GCP];
+                    v[(size_t)c * C::GCP] = run;
+                }
+            }
+            __syncthreads();
+            // 2c. horizontal box sum of this thread's pixel = difference of two prefixes
+            const int c_hi = tx + eoff + 2 * h, c_lo = tx + eoff - 1;
+            const double *vhi = V + ((size_t)ty * EX + c_hi) * C::GCP;
+            const double *vlo = V + ((size_t)ty * EX + (c_lo < 0 ? 0 : c_lo)) * C::GCP;
+            double hsum[C::GC];
+#pragma unroll
+            for (int gg = 0; gg < C::GC; ++gg) hsum[gg] = vhi[gg] - (c_lo < 0 ? 0.0 : vlo[gg]);
+#pragma unroll
+            for (int gg = 0; gg < C::GC; ++gg) {
+                const int g = g0 + gg;
+                if (g < C::GT) {
+                    if (win == 0) {
+                        S[g] -= hsum[gg];
+                        if (g < LP) sin_lin[g] = hsum[gg];
+                        if (g == C::G) in_bad = hsum[gg];
+                    } else {
+                        S[g] += hsum[gg];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    if (py >= H || px >= W) return;
+
+    // 3. statistics of the annulus, loading, Cholesky, scores
+    const int n_o = clip_count(py, R, H) * clip_count(px, R, W);
+    const int n_i = has_inner ? clip_count(py, RI, H) * clip_count(px, RI, W) : 0;
+    const double inv_na = 1.0 / (double)(n_o - n_i);
+    const bool ann_bad = S[C::G] > 0.5;      // exact small integers in FP64
+    double mu[LP];
+#pragma unroll
+    for (int i = 0; i < LP; ++i) mu[i] = S[i] * inv_na;
+    double Lm[LP][LP];
+    double tr = 0.0;
+    {
+        int g = LP;
+#pragma unroll
+        for (int i = 0; i < LP; ++i)
+#pragma unroll
+            for (int j = i; j < LP; ++j) {
+                const double c = S[g++] * inv_na - mu[i] * mu[j];
+                Lm[j][i] = c;
+                if (i == j) tr += c;
+            }
+    }
+    double lam = load_rel * tr / (double)LP;
+    lam = lam < 1e-30 ? 1e-30 : lam;
+    // Cholesky with reciprocal pivots: Lm[j][j] holds 1/L_jj
+    bool pd = true;
+#pragma unroll
+    for (int j = 0; j < LP; ++j) {
+        double d = Lm[j][j] + lam;
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
+        pd = pd && (d > 0.0);
+        const double inv = rsqrt(d);
+        Lm[j][j] = inv;
+#pragma unroll
+        for (int i = j + 1; i < LP; ++i) {
+            double t = Lm[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= Lm[i][k] * Lm[j][k];
+            Lm[i][j] = t * inv;
+        }
+    }
+    const size_t o = (size_t)py * W + px;
+    if (lrx) {
+        const float *pc = x + o * LP;            // raw centre pixel
+        double z[LP], s = 0.0;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            double t = ((double)pc[i] - ref[i]) - mu[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
+            z[i] = t * Lm[i][i];
+            s += z[i] * z[i];
+        }
+        lrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
+    }
+    if (dwrx) {
+        if (in_bad > 0.5) {
+            // rare: a non-finite inner sample; take the mean from the raw values so that
+            // NaN / Inf propagate exactly as in the definition
+#pragma unroll
+            for (int i = 0; i < LP; ++i) sin_lin[i] = 0.0;
+            for (int dy = -RI; dy <= RI; ++dy)
+                for (int dx = -RI; dx <= RI; ++dx) {
+                    const int gy = py + dy, gx = px + dx;
+                    if (gy < 0 || gy >= H || gx < 0 || gx >= W) continue;
+                    const float *raw = x + ((size_t)gy * W + gx) * LP;
+#pragma unroll
+                    for (int i = 0; i < LP; ++i) sin_lin[i] += (double)raw[i] - ref[i];
+                }
+        }
+        const double inv_ni = 1.0 / (double)n_i;
+        double z[LP], s = 0.0;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            double t = sin_lin[i] * inv_ni - mu[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
+            z[i] = t * Lm[i][i];
+            s += z[i] * z[i];
+        }
+        dwrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
+    }
+}
+
+
+template <int LP, int GCMAX = 15> __host__ __device__ inline size_t box_smem(int R)
+{
+    using C = BoxCfg<LP, GCMAX>;
+    const size_t EX = TX + 2 * R, EY = TY + 2 * R;
+    return (size_t)TY * EX * C::GCP * sizeof(double) + EY * EX * (LP + 1) * sizeof(float);
+}
+
+}  // namespace hsad

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "dev_dwt.hpp"
 
 namespace hsad {
 
@@ -302,65 +303,17 @@ __global__ __launch_bounds__(kEqTP) void dwt_equiv_lds_kernel(const float *__res
 }
 
 // ------------------------------------------------------------------------------------
-// device: LDS cascade kernel
+// device: LDS cascade kernel (body in dev_dwt.hpp)
 // ------------------------------------------------------------------------------------
-struct Taps {
-    double h[8];
-};
-
 __global__ __launch_bounds__(256) void dwt_cascade_kernel(const float *__restrict__ cube,
                                                           int64_t npix, int L, int levels,
                                                           int Lp, int P, Taps taps,
                                                           float *__restrict__ out)
 {
     extern __shared__ double ldsd[];
-    const int S0 = L + 1;                 // odd stride of the level-0 buffer
-    const int S1 = (L + 1) / 2 + 1;       // stride of the level-1 buffer
-    double *buf0 = ldsd;                  // P * S0, FP64 levels (see dwt_equiv_kernel)
-    double *buf1 = ldsd + (size_t)P * S0; // P * S1
     const int64_t p0 = (int64_t)blockIdx.x * P;
     const int np = (int)((npix - p0) < P ? (npix - p0) : P);
-    const int tid = threadIdx.x;
-
-    // coalesced load of np contiguous spectra
-    const float *src = cube + p0 * (int64_t)L;
-    const int total = np * L;
-    for (int t = tid; t < total; t += 256) {
-        const int p = t / L, i = t - p * L;
-        buf0[p * S0 + i] = (double)src[t];
-    }
-    __syncthreads();
-
-    double *cur = buf0, *nxt = buf1;
-    int scur = S0, snxt = S1;
-    int n = L;
-    for (int j = 0; j < levels; ++j) {
-        const int ne = n + (n & 1), m = ne / 2;
-        // lanes over k (64 per pixel row), 4 pixel rows per pass of 256 threads
-        for (int p = tid >> 6; p < np; p += 4) {
-            const double *x = cur + p * scur;
-            for (int k = tid & 63; k < m; k += 64) {
-                double s = 0.0;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    int i = 2 * k - t;       // >= -7; short levels (ne < 8) wrap twice
-                    while (i < 0) i += ne;
-                    s = fma(taps.h[t], x[i < n ? i : n - 1], s);
-                }
-                nxt[p * snxt + k] = s;
-            }
-        }
-        __syncthreads();
-        double *tp = cur; cur = nxt; nxt = tp;
-        int ts = scur; scur = snxt; snxt = ts;
-        n = m;
-    }
-    // coalesced store of np * Lp outputs
-    float *dst = out + p0 * (int64_t)Lp;
-    for (int t = tid; t < np * Lp; t += 256) {
-        const int p = t / Lp, k = t - p * Lp;
-        dst[t] = (float)cur[p * scur + k];
-    }
+    dwt_cascade_tile(cube, p0, np, L, levels, Lp, taps, out, ldsd, P);
 }
 
 // ------------------------------------------------------------------------------------
@@ -426,7 +379,7 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
         if (coef) return launch_equiv_lp(Lp, cube, npix, L, coef, lds ? ldvec : vec, lds, approx, s);
     }
     // cascade: size the pixel tile so that both ping-pong buffers fit in 64 KiB of LDS
-    const int64_t per_pix = (L + 1) + ((L + 1) / 2 + 1);
+    const int64_t per_pix = dwt_cascade_lds_doubles(L, 1);
     int64_t P = (64 * 1024 / 8) / per_pix;
     if (P > 64) P = 64;
     if (P < 1) return fail(HSAD_EUNSUPPORTED, "hsad_dwt: L too large for the LDS cascade");

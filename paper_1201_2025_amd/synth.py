@@ -27,8 +27,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Scene", "make_spectra", "make_scene", "CONFIGS", "batch_scene_specs",
-           "random_cube"]
+__all__ = ["Scene", "make_spectra", "make_scene", "make_scene_torch", "CONFIGS",
+           "batch_scene_specs", "random_cube"]
 
 
 @dataclass
@@ -107,6 +107,50 @@ def make_scene(seed: int, H: int, W: int, L: int, K: int = 8, n_single: int = 12
         cube[y:y + sz, x:x + sz] = (f * target + (1.0 - f) * blk).astype(np.float32)
         truth[y:y + sz, x:x + sz] = 1
     return Scene(cube=cube, truth=truth, spectra=spectra, fractions=fr, objects=objs)
+
+
+def make_scene_torch(seed: int, H: int, W: int, L: int, K: int = 8, n_single: int = 12,
+                     n_blob: int = 0, noise: float = 0.01, f_range=(0.3, 0.7),
+                     device="cuda", chunk_rows: int = 256):
+    """The same recipe as make_scene with the per-pixel arrays built by torch on `device`,
+    for workloads of many gigabytes.  Spectra, endmember centres and widths, object
+    positions and fractions come from the same numpy stream as make_scene, so for a given
+    seed they are identical.  Only the noise differs: it comes from torch's generator
+    seeded with `seed`.  Returns (cube tensor H x W x L float32, truth uint8 numpy, spectra)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    spectra = make_spectra(rng, K + 1, L)
+    m = min(H, W)
+    centres = np.stack([rng.uniform(0, H, K), rng.uniform(0, W, K)], 1)
+    widths = rng.uniform(0.15, 0.5, K) * m
+    objs = _place_objects(rng, H, W, n_single, n_blob)
+    fr = rng.uniform(f_range[0], f_range[1], len(objs))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    bg_spec = torch.from_numpy(spectra[:K]).to(device)
+    target = torch.from_numpy(spectra[K]).to(device)
+    cen = torch.from_numpy(centres).to(device)
+    wid = torch.from_numpy(widths).to(device)
+    cube = torch.empty((H, W, L), dtype=torch.float32, device=device)
+    xs = torch.arange(W, dtype=torch.float64, device=device)
+    for r0 in range(0, H, chunk_rows):
+        r1 = min(H, r0 + chunk_rows)
+        ys = torch.arange(r0, r1, dtype=torch.float64, device=device)
+        d2 = (ys[:, None, None] - cen[None, None, :, 0]) ** 2 + (xs[None, :, None] - cen[None, None, :, 1]) ** 2
+        logw = -d2 / (2.0 * wid[None, None, :] ** 2)
+        logw = logw - logw.max(dim=2, keepdim=True).values
+        w = torch.exp(logw)
+        a = w / w.sum(dim=2, keepdim=True)
+        bg = a @ bg_spec
+        if noise > 0:
+            bg += torch.randn(bg.shape, generator=gen, dtype=torch.float64, device=device) * noise
+        cube[r0:r1] = bg.to(torch.float32)
+    truth = np.zeros((H, W), dtype=np.uint8)
+    for (y, x, sz), f in zip(objs, fr):
+        blk = cube[y:y + sz, x:x + sz].to(torch.float64)
+        cube[y:y + sz, x:x + sz] = (f * target + (1.0 - f) * blk).to(torch.float32)
+        truth[y:y + sz, x:x + sz] = 1
+    return cube, truth, spectra
 
 
 def random_cube(seed: int, H: int, W: int, L: int, scale: float = 1.0) -> np.ndarray:
