@@ -237,6 +237,157 @@ int hsad_batch_autotune(const hsad_scene *scenes, int n, void *ws, size_t ws_byt
  * box-bucket pixels, Gram-bucket pixels}; n >= 8. */
 int hsad_batch_plan_info(const hsad_batch_plan *plan, int64_t *info, int n);
 
+/* ---------------------------------------------------------------------------------------
+ * Exact LRX/DWRX at a list of pixels
+ * -------------------------------------------------------------------------------------*/
+/* LRX (eq. 1) and DWRX (eq. 5) of the pixels idx[0..nidx) of the reduced cube x (same
+ * definitions, windows and loading as hsad_lrx_dwrx), computed by the FP64 matrix-core
+ * Gram and the FP64 Cholesky.  Only lrx[idx[j]] / dwrx[idx[j]] are written; the rest of
+ * the maps is left as it was.  Duplicates are allowed.  ws needs at least (L'+2) L' doubles; larger
+ * workspaces process more pixels per chunk (up to 192 MiB worth).  precision must be
+ * AUTO or FP64.  For L' > 8 the scores are bitwise those of hsad_lrx_dwrx.  Entries of
+ * idx outside [0, H*W) are skipped.
+ * Errors: HSAD_EINVAL, HSAD_ENOMEM, HSAD_EHIP. */
+int hsad_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                     const int32_t *idx, int64_t nidx, float *lrx, float *dwrx, void *ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned surrogate of the LRX score
+ *
+ * Not part of the paper: a per-pixel MLP that predicts log1p(LRX) (eq. 1) from local
+ * features, so that the exact detector only runs where the prediction is close to the
+ * eq. (12) threshold, plus a seeded audit sample that measures the prediction error and
+ * triggers an exact fallback.
+ *   Features (D = 3 L'), for each band i of the reduced cube, over the annulus
+ *   (outer minus inner window): z_i = (x_i - mu_i)/sqrt(v_i + 1e-12), log(v_i + 1e-12)
+ *   and mu_i, where mu_i and v_i are the annulus mean and 1/n variance.
+ *   Network: D inputs (normalised per column, zero padded to Dp = 32 ceil(D/32) <= 256)
+ *   -> 128 ReLU -> 128 ReLU -> 1.  BF16 matrix-core products with FP32 accumulation.
+ *   Parameters (FP32, nparams values): W1 [Dp][128], b1 [128], W2 [128][128], b2 [128],
+ *   w3 [128], b3, 3 padding values.  h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2),
+ *   y = h2 . w3 + b3.  The BF16 copy (nbf16 values) holds W1 transposed [128][Dp],
+ *   W2 transposed [128][128] and W2 [128][128]; hsad_mlp_sync and every training step
+ *   keep it equal to the rounded FP32 weights.
+ * -------------------------------------------------------------------------------------*/
+typedef struct hsad_mlp_model {
+    const float *params;   /* device, nparams FP32 */
+    const uint16_t *wbf;   /* device, nbf16 BF16 bit patterns */
+    const float *norm;     /* device, 2 D floats: {shift, scale} per input column */
+    int64_t Lp;            /* reduced band count the model was trained for */
+    int32_t Dp;            /* padded input width */
+    int32_t reserved;      /* must be 0 */
+    double rmse_val;       /* validation RMSE of log1p(score) */
+} hsad_mlp_model;
+
+typedef struct hsad_surrogate_options {
+    double z_alpha;         /* eq. (12) */
+    double band_k;          /* band half-width = band_k * rmse_val around log1p(tau) */
+    double audit_frac;      /* fraction of pixels audited (seeded, uniform), 0..1 */
+    double fallback_factor; /* exact fallback when the audit RMSE > fallback_factor * rmse_val */
+    uint64_t seed;          /* audit stream seed */
+} hsad_surrogate_options;
+
+typedef struct hsad_surrogate_report {
+    int64_t pixels;      /* H * W */
+    int64_t selected;    /* pixels scored exactly (H * W after a fallback) */
+    int64_t band;        /* pixels inside the near-threshold band */
+    int64_t audit;       /* audited pixels */
+    double audit_rmse;   /* RMSE of the prediction on the audit, log1p space */
+    double audit_max;    /* largest |error| on the audit, log1p space */
+    double tau_pred;     /* eq. (12) threshold of the predicted map */
+    double tau;          /* eq. (12) threshold of the final map */
+    int32_t fallback;    /* 1 when the whole map was recomputed exactly */
+    int32_t reserved;
+} hsad_surrogate_report;
+
+/* Sizes for a reduced band count: D = 3 L', Dp, nparams (FP32) and nbf16 (BF16) counts.
+ * Errors: HSAD_EINVAL (L' outside 1..85). */
+int hsad_mlp_dims(int64_t Lp, int32_t *D, int32_t *Dp, int64_t *nparams, int64_t *nbf16);
+
+/* Features of every pixel of the reduced cube x.  With norm == NULL, writes FP32 rows
+ * feat [H*W][3 L'] (z, log-variance, mean blocks); otherwise writes the normalised BF16
+ * rows packed [H*W][Dp], (f - norm[2k]) * norm[2k+1], zero padded.  Windows as for LRX.
+ * Errors: HSAD_EINVAL, HSAD_EHIP. */
+int hsad_surrogate_features(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                            const float *norm, int32_t Dp, float *feat, uint16_t *packed, hipStream_t stream);
+
+/* Column normalisation of an n x D FP32 matrix: norm[2c] = mean, norm[2c+1] = 1 / population
+ * standard deviation (1 for a constant column).  Errors: HSAD_EINVAL, HSAD_EHIP. */
+int hsad_mlp_norm_stats(const float *feat, int64_t n, int32_t D, float *norm, hipStream_t stream);
+
+/* BF16 rows [n][Dp] = (feat - norm[2k]) * norm[2k+1], zero padded.  Errors: HSAD_EINVAL, HSAD_EHIP. */
+int hsad_mlp_pack(const float *feat, int64_t n, int32_t D, int32_t Dp, const float *norm, uint16_t *out,
+                  hipStream_t stream);
+
+/* Training targets tgt = log1p(scores); non-finite scores give NaN, which training skips. */
+int hsad_surrogate_targets(const float *scores, int64_t n, float *tgt, hipStream_t stream);
+
+/* Refreshes the BF16 copy wbf from the FP32 parameters. */
+int hsad_mlp_sync(const float *params, int32_t Dp, uint16_t *wbf, hipStream_t stream);
+
+/* Predictions yhat[r] (log1p space) for n packed BF16 rows X [n][Dp].
+ * Errors: HSAD_EINVAL, HSAD_EHIP. */
+int hsad_mlp_infer(const uint16_t *X, int64_t n, int32_t Dp, const float *params, const uint16_t *wbf,
+                   float *yhat, hipStream_t stream);
+
+/* Workspace of hsad_mlp_gradient / hsad_mlp_train_step: one FP32 gradient partial per
+ * 64 rows of the batch. */
+size_t hsad_mlp_train_workspace_bytes(int64_t batch, int32_t Dp);
+
+/* Gradient of the mean squared error (1/batch) sum_j (y(X[rows[j]]) - tgt[rows[j]])^2
+ * with respect to the parameters: grad[0..nparams) and grad[nparams] = the loss.
+ * X holds nX packed rows [nX][Dp] and tgt nX targets; rows[0..batch) selects the batch.
+ * Entries of rows outside [0, nX) and rows whose target is NaN contribute nothing (the
+ * mean still divides by batch).  The
+ * forward pass uses the BF16 weights and rounds h1, h2 and the back-propagated errors to
+ * BF16; sums of partials run in a fixed order, so repeated calls agree bitwise.
+ * Errors: HSAD_EINVAL, HSAD_ENOMEM, HSAD_EHIP. */
+int hsad_mlp_gradient(const uint16_t *X, int64_t nX, const float *tgt, const int32_t *rows, int64_t batch,
+                      int32_t Dp, const float *params, const uint16_t *wbf, float *grad, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* One Adam step (Kingma and Ba 2015: beta1 0.9, beta2 0.999, eps 1e-8, bias correction
+ * with `step` >= 1) on the FP32 parameters from the gradient of hsad_mlp_gradient;
+ * updates adam_m, adam_v (nparams FP32 each, zero before step 1) and the BF16 copy.
+ * loss (device, 1 float, may be NULL) receives the batch loss before the update. */
+int hsad_mlp_train_step(const uint16_t *X, int64_t nX, const float *tgt, const int32_t *rows, int64_t batch,
+                        int32_t Dp, float *params, uint16_t *wbf, float *adam_m, float *adam_v, int64_t step,
+                        float lr, float *loss, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace of hsad_error_stats (bytes). */
+size_t hsad_error_stats_workspace_bytes(int64_t n);
+
+/* Error of predictions against references, e = yhat - r with r = log1p(ref) when
+ * ref_is_score, else ref.  Over rows with (flags[i] & flag_mask) != 0 (all rows when flags
+ * is NULL) and finite e: out (device, 3 doubles) = {count, RMSE, max |e|}.  Fixed-order
+ * reduction.  Errors: HSAD_EINVAL, HSAD_ENOMEM, HSAD_EHIP. */
+int hsad_error_stats(const float *yhat, const float *ref, int32_t ref_is_score, const uint8_t *flags,
+                     int32_t flag_mask, int64_t n, double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Pixels sent to the exact detector.  flags[i] = 1 when |yhat[i] - log1p(stats[3])| <= band
+ * (NaN predictions included), plus 2 when the upper 32 bits of SplitMix64 output i of the
+ * stream seeded with `seed` (state seed + (i+1) 0x9E3779B97F4A7C15, then the standard
+ * finaliser) are below audit_frac * 2^32.  The indices of the flagged pixels are written to
+ * idx in unspecified order; counts (device, 3 uint32) = {flagged, band, audit}.  stats is
+ * the device output of hsad_threshold.  Errors: HSAD_EINVAL, HSAD_EHIP. */
+int hsad_surrogate_select(const float *yhat, int64_t n, const double *stats, double band, uint64_t seed,
+                          double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, hipStream_t stream);
+
+/* Workspace of hsad_surrogate_run (bytes). */
+size_t hsad_surrogate_workspace_bytes(int64_t H, int64_t W, int64_t Lp, int32_t Dp, const hsad_window_params *p);
+
+/* Hybrid LRX map of the reduced cube x: features, predictions, eq. (12) on the predicted
+ * scores expm1(yhat), selection (hsad_surrogate_select with band = band_k * rmse_val),
+ * exact LRX at the selected pixels, audit statistics, and, when the audit RMSE exceeds
+ * fallback_factor * rmse_val, exact LRX of the whole map.  Then eq. (12) and the mask
+ * (if mask != NULL) of the final map.  scores: device, H*W float32 (exact at the selected
+ * pixels, expm1(prediction) elsewhere).  rep: host.  Synchronises `stream` three times.
+ * Errors: HSAD_EINVAL (arguments, model/cube mismatch), HSAD_ENOMEM, HSAD_EHIP. */
+int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                       const hsad_mlp_model *model, const hsad_surrogate_options *opt, float *scores,
+                       uint8_t *mask, hsad_surrogate_report *rep, void *ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

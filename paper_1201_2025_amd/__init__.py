@@ -18,5 +18,10 @@ from ._binding import (  # noqa: F401
     hsad_lrx, hsad_lrx_dwrx, hsad_version, hsad_workspace_bytes, lib, lib_path,
     hsad_threshold, hsad_threshold_workspace_bytes, hsad_auc, hsad_auc_workspace_bytes,
     auc_from_counts, BatchPlan, BatchOptions, Scene, batch_default_options,
-    hsad_batch_autotune,
+    hsad_batch_autotune, hsad_lrx_dwrx_at, hsad_mlp_dims, hsad_surrogate_features,
+    hsad_mlp_norm_stats, hsad_mlp_pack, hsad_surrogate_targets, hsad_mlp_sync, hsad_mlp_infer,
+    hsad_mlp_train_workspace_bytes, hsad_mlp_gradient, hsad_mlp_train_step, hsad_error_stats,
+    hsad_surrogate_select, hsad_surrogate_workspace_bytes, hsad_surrogate_run, MlpModel,
+    SurrogateOptions, SurrogateReport,
 )
+from .surrogate import Surrogate  # noqa: F401

@@ -43,6 +43,28 @@ class BatchOptions(ctypes.Structure):
                 ("chunk_bytes", ctypes.c_int64), ("reserved", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+class MlpModel(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("wbf", ctypes.c_void_p), ("norm", ctypes.c_void_p),
+                ("Lp", ctypes.c_int64), ("Dp", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rmse_val", ctypes.c_double)]
+
+
+class SurrogateOptions(ctypes.Structure):
+    _fields_ = [("z_alpha", ctypes.c_double), ("band_k", ctypes.c_double),
+                ("audit_frac", ctypes.c_double), ("fallback_factor", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class SurrogateReport(ctypes.Structure):
+    _fields_ = [("pixels", ctypes.c_int64), ("selected", ctypes.c_int64), ("band", ctypes.c_int64),
+                ("audit", ctypes.c_int64), ("audit_rmse", ctypes.c_double),
+                ("audit_max", ctypes.c_double), ("tau_pred", ctypes.c_double), ("tau", ctypes.c_double),
+                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -77,6 +99,31 @@ SIGNATURES = [
     ("hsad_batch_autotune", ctypes.c_int, [ctypes.POINTER(Scene), ctypes.c_int, _vp, ctypes.c_size_t,
                                            _vp, ctypes.c_char_p, ctypes.POINTER(BatchOptions),
                                            ctypes.POINTER(ctypes.c_double)]),
+    ("hsad_lrx_dwrx_at", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _i64, _vp, _vp, _vp,
+                                        ctypes.c_size_t, _vp]),
+    ("hsad_mlp_dims", ctypes.c_int, [_i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    ("hsad_surrogate_features", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, ctypes.c_int32, _vp, _vp,
+                                               _vp]),
+    ("hsad_mlp_norm_stats", ctypes.c_int, [_vp, _i64, ctypes.c_int32, _vp, _vp]),
+    ("hsad_mlp_pack", ctypes.c_int, [_vp, _i64, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
+    ("hsad_surrogate_targets", ctypes.c_int, [_vp, _i64, _vp, _vp]),
+    ("hsad_mlp_sync", ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp]),
+    ("hsad_mlp_infer", ctypes.c_int, [_vp, _i64, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    ("hsad_mlp_train_workspace_bytes", ctypes.c_size_t, [_i64, ctypes.c_int32]),
+    ("hsad_mlp_gradient", ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                         ctypes.c_size_t, _vp]),
+    ("hsad_mlp_train_step", ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, ctypes.c_int32, _vp, _vp, _vp, _vp, _i64,
+                                           ctypes.c_float, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_error_stats_workspace_bytes", ctypes.c_size_t, [_i64]),
+    ("hsad_error_stats", ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _i64, _vp, _vp,
+                                        ctypes.c_size_t, _vp]),
+    ("hsad_surrogate_select", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_double, ctypes.c_uint64,
+                                             ctypes.c_double, _vp, _vp, _vp, _vp]),
+    ("hsad_surrogate_workspace_bytes", ctypes.c_size_t, [_i64, _i64, _i64, ctypes.c_int32, _P]),
+    ("hsad_surrogate_run", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.POINTER(MlpModel),
+                                          ctypes.POINTER(SurrogateOptions), _vp, _vp,
+                                          ctypes.POINTER(SurrogateReport), _vp, ctypes.c_size_t, _vp]),
 ]
 
 
@@ -407,3 +454,205 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---- exact LRX at listed pixels, surrogate ---------------------------------------------
+def hsad_lrx_dwrx_at(x, idx, inner: int, outer: int, load_rel: float = 1e-6, lrx=None, dwrx=None,
+                     ws=None, ws_bytes: int | None = None, stream=None):
+    """Exact LRX / DWRX of the reduced cube x at the flat pixel indices idx (int32 GPU tensor),
+    written into lrx / dwrx (H x W float32 GPU tensors; pass None to skip one)."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    pi = _dev(idx, "idx", torch.int32)
+    p = _params(inner, outer, load_rel, HSAD_PREC_AUTO)
+    if ws is None:
+        per = (Lp + 2) * Lp * 8
+        nb = per * max(1, min(idx.numel(), max(8192, (192 << 20) // per))) if ws_bytes is None else ws_bytes
+        ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+    rc = lib().hsad_lrx_dwrx_at(px, H, W, Lp, ctypes.byref(p), pi, idx.numel(),
+                                _ptr_or_null(lrx, "lrx", torch.float32), _ptr_or_null(dwrx, "dwrx", torch.float32),
+                                _dev(ws, "ws"), ws.numel() * ws.element_size(), _stream(stream))
+    _check("hsad_lrx_dwrx_at", rc)
+    return lrx, dwrx
+
+
+def hsad_mlp_dims(Lp: int):
+    """(D, Dp, nparams, nbf16) of the surrogate network for L' reduced bands."""
+    D, Dp, npar, nbf = ctypes.c_int32(), ctypes.c_int32(), _i64(), _i64()
+    _check("hsad_mlp_dims", lib().hsad_mlp_dims(int(Lp), ctypes.byref(D), ctypes.byref(Dp), ctypes.byref(npar),
+                                                ctypes.byref(nbf)))
+    return D.value, Dp.value, npar.value, nbf.value
+
+
+def hsad_surrogate_features(x, inner: int, outer: int, norm=None, Dp: int = 0, out=None, stream=None):
+    """Features of every pixel of x (H, W, L'): FP32 (H*W, 3L') when norm is None, else the
+    normalised BF16 rows (H*W, Dp) as an int16 tensor of bit patterns."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    p = _params(inner, outer, 0.0, HSAD_PREC_AUTO)
+    if norm is None:
+        out = torch.empty((H * W, 3 * Lp), dtype=torch.float32, device=x.device) if out is None else out
+        rc = lib().hsad_surrogate_features(px, H, W, Lp, ctypes.byref(p), None, 0, _dev(out, "feat", torch.float32),
+                                           None, _stream(stream))
+    else:
+        out = torch.empty((H * W, Dp), dtype=torch.int16, device=x.device) if out is None else out
+        rc = lib().hsad_surrogate_features(px, H, W, Lp, ctypes.byref(p), _dev(norm, "norm", torch.float32),
+                                           int(Dp), None, _dev(out, "packed", torch.int16), _stream(stream))
+    _check("hsad_surrogate_features", rc)
+    return out
+
+
+def hsad_mlp_norm_stats(feat, norm=None, stream=None):
+    torch = _torch()
+    n, D = feat.shape
+    norm = torch.empty(2 * D, dtype=torch.float32, device=feat.device) if norm is None else norm
+    _check("hsad_mlp_norm_stats", lib().hsad_mlp_norm_stats(_dev(feat, "feat", torch.float32), n, D,
+                                                            _dev(norm, "norm", torch.float32), _stream(stream)))
+    return norm
+
+
+def hsad_mlp_pack(feat, norm, Dp: int, out=None, stream=None):
+    torch = _torch()
+    n, D = feat.shape
+    out = torch.empty((n, Dp), dtype=torch.int16, device=feat.device) if out is None else out
+    _check("hsad_mlp_pack", lib().hsad_mlp_pack(_dev(feat, "feat", torch.float32), n, D, int(Dp),
+                                                _dev(norm, "norm", torch.float32), _dev(out, "out", torch.int16),
+                                                _stream(stream)))
+    return out
+
+
+def hsad_surrogate_targets(scores, out=None, stream=None):
+    torch = _torch()
+    n = scores.numel()
+    out = torch.empty(n, dtype=torch.float32, device=scores.device) if out is None else out
+    _check("hsad_surrogate_targets", lib().hsad_surrogate_targets(_dev(scores, "scores", torch.float32), n,
+                                                                  _dev(out, "tgt", torch.float32), _stream(stream)))
+    return out
+
+
+def hsad_mlp_sync(params, Dp: int, wbf, stream=None):
+    torch = _torch()
+    _check("hsad_mlp_sync", lib().hsad_mlp_sync(_dev(params, "params", torch.float32), int(Dp),
+                                                _dev(wbf, "wbf", torch.int16), _stream(stream)))
+    return wbf
+
+
+def hsad_mlp_infer(X, params, wbf, out=None, stream=None):
+    torch = _torch()
+    n, Dp = X.shape
+    out = torch.empty(n, dtype=torch.float32, device=X.device) if out is None else out
+    _check("hsad_mlp_infer", lib().hsad_mlp_infer(_dev(X, "X", torch.int16), n, Dp,
+                                                  _dev(params, "params", torch.float32), _dev(wbf, "wbf", torch.int16),
+                                                  _dev(out, "yhat", torch.float32), _stream(stream)))
+    return out
+
+
+def hsad_mlp_train_workspace_bytes(batch: int, Dp: int) -> int:
+    return int(lib().hsad_mlp_train_workspace_bytes(int(batch), int(Dp)))
+
+
+def hsad_mlp_gradient(X, tgt, rows, params, wbf, grad=None, ws=None, stream=None):
+    """Gradient vector (nparams + 1 floats, the last being the batch loss)."""
+    torch = _torch()
+    Dp = X.shape[1]
+    batch = rows.numel()
+    grad = torch.empty(params.numel() + 1, dtype=torch.float32, device=X.device) if grad is None else grad
+    if ws is None:
+        ws = torch.empty(hsad_mlp_train_workspace_bytes(batch, Dp), dtype=torch.uint8, device=X.device)
+    if tgt.numel() != X.shape[0]:
+        raise ValueError("tgt must have one entry per row of X")
+    rc = lib().hsad_mlp_gradient(_dev(X, "X", torch.int16), X.shape[0], _dev(tgt, "tgt", torch.float32),
+                                 _dev(rows, "rows", torch.int32), batch, Dp, _dev(params, "params", torch.float32),
+                                 _dev(wbf, "wbf", torch.int16), _dev(grad, "grad", torch.float32), _dev(ws, "ws"),
+                                 ws.numel() * ws.element_size(), _stream(stream))
+    _check("hsad_mlp_gradient", rc)
+    return grad
+
+
+def hsad_mlp_train_step(X, tgt, rows, params, wbf, m, v, step: int, lr: float, loss=None, ws=None, stream=None):
+    torch = _torch()
+    Dp = X.shape[1]
+    batch = rows.numel()
+    if ws is None:
+        ws = torch.empty(hsad_mlp_train_workspace_bytes(batch, Dp), dtype=torch.uint8, device=X.device)
+    if tgt.numel() != X.shape[0]:
+        raise ValueError("tgt must have one entry per row of X")
+    rc = lib().hsad_mlp_train_step(_dev(X, "X", torch.int16), X.shape[0], _dev(tgt, "tgt", torch.float32),
+                                   _dev(rows, "rows", torch.int32), batch, Dp,
+                                   _dev(params, "params", torch.float32), _dev(wbf, "wbf", torch.int16),
+                                   _dev(m, "adam_m", torch.float32), _dev(v, "adam_v", torch.float32), int(step),
+                                   float(lr), _ptr_or_null(loss, "loss", torch.float32), _dev(ws, "ws"),
+                                   ws.numel() * ws.element_size(), _stream(stream))
+    _check("hsad_mlp_train_step", rc)
+
+
+def hsad_error_stats(yhat, ref, ref_is_score: bool, flags=None, flag_mask: int = 0, out=None, ws=None,
+                     stream=None):
+    torch = _torch()
+    n = yhat.numel()
+    out = torch.empty(3, dtype=torch.float64, device=yhat.device) if out is None else out
+    if ws is None:
+        ws = torch.empty(int(lib().hsad_error_stats_workspace_bytes(n)), dtype=torch.uint8, device=yhat.device)
+    rc = lib().hsad_error_stats(_dev(yhat, "yhat", torch.float32), _dev(ref, "ref", torch.float32),
+                                1 if ref_is_score else 0, _ptr_or_null(flags, "flags", torch.uint8), int(flag_mask),
+                                n, _dev(out, "out", torch.float64), _dev(ws, "ws"), ws.numel() * ws.element_size(),
+                                _stream(stream))
+    _check("hsad_error_stats", rc)
+    return out
+
+
+def hsad_surrogate_select(yhat, stats, band: float, seed: int, audit_frac: float, flags=None, idx=None,
+                          counts=None, stream=None):
+    """Returns (flags uint8, idx int32 (first counts[0] valid), counts int32[3])."""
+    torch = _torch()
+    n = yhat.numel()
+    flags = torch.empty(n, dtype=torch.uint8, device=yhat.device) if flags is None else flags
+    idx = torch.empty(n, dtype=torch.int32, device=yhat.device) if idx is None else idx
+    counts = torch.empty(3, dtype=torch.int32, device=yhat.device) if counts is None else counts
+    rc = lib().hsad_surrogate_select(_dev(yhat, "yhat", torch.float32), n, _dev(stats, "stats", torch.float64),
+                                     float(band), int(seed) & ((1 << 64) - 1), float(audit_frac),
+                                     _dev(flags, "flags", torch.uint8), _dev(idx, "idx", torch.int32),
+                                     _dev(counts, "counts", torch.int32), _stream(stream))
+    _check("hsad_surrogate_select", rc)
+    return flags, idx, counts
+
+
+def hsad_surrogate_workspace_bytes(H: int, W: int, Lp: int, Dp: int, inner: int, outer: int,
+                                   load_rel: float = 1e-6) -> int:
+    p = _params(inner, outer, load_rel, HSAD_PREC_AUTO)
+    return int(lib().hsad_surrogate_workspace_bytes(int(H), int(W), int(Lp), int(Dp), ctypes.byref(p)))
+
+
+def hsad_surrogate_run(x, inner: int, outer: int, load_rel: float, params, wbf, norm, rmse_val: float,
+                       z_alpha: float = 3.0, band_k: float = 3.0, audit_frac: float = 0.01,
+                       fallback_factor: float = 2.0, seed: int = 0, scores=None, mask=True, ws=None,
+                       stream=None):
+    """Hybrid LRX map of the reduced cube x; returns (scores, mask or None, report dict)."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    Dp = wbf.numel() // 128 - 256
+    p = _params(inner, outer, load_rel, HSAD_PREC_AUTO)
+    model = MlpModel(params.data_ptr(), wbf.data_ptr(), norm.data_ptr(), Lp, Dp, 0, float(rmse_val))
+    _dev(params, "params", torch.float32)
+    _dev(wbf, "wbf", torch.int16)
+    _dev(norm, "norm", torch.float32)
+    opt = SurrogateOptions(float(z_alpha), float(band_k), float(audit_frac), float(fallback_factor),
+                           int(seed) & ((1 << 64) - 1))
+    scores = torch.empty((H, W), dtype=torch.float32, device=x.device) if scores is None else scores
+    if mask is True:
+        mask = torch.empty((H, W), dtype=torch.uint8, device=x.device)
+    elif mask is False:
+        mask = None
+    need = int(lib().hsad_surrogate_workspace_bytes(H, W, Lp, Dp, ctypes.byref(p)))
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    rep = SurrogateReport()
+    rc = lib().hsad_surrogate_run(px, H, W, Lp, ctypes.byref(p), ctypes.byref(model), ctypes.byref(opt),
+                                  _dev(scores, "scores", torch.float32), _ptr_or_null(mask, "mask", torch.uint8),
+                                  ctypes.byref(rep), _dev(ws, "ws"), ws.numel() * ws.element_size(),
+                                  _stream(stream))
+    _check("hsad_surrogate_run", rc)
+    return scores, mask, rep.as_dict()

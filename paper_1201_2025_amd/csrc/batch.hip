@@ -178,6 +178,7 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const SceneDev *__restr
             a.npix = m.b;
             a.ws = chunk_ws + m.ws_off;
             a.outer_magic = s.outer_magic;
+            a.idx = nullptr;
             gram_pixel<0, MT>(a, wv, lds + (size_t)wv * wave_doubles);
         }
         __syncthreads();

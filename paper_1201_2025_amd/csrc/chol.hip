@@ -23,12 +23,14 @@ namespace hsad {
 __global__ __launch_bounds__(256) void chol_rx_kernel(double *__restrict__ ws, int Lp, int npix,
                                                       int64_t pix0, double load_rel,
                                                       float *__restrict__ lrx,
-                                                      float *__restrict__ dwrx)
+                                                      float *__restrict__ dwrx,
+                                                      const int32_t *__restrict__ idx, int64_t npix_img)
 {
     extern __shared__ double sm[];
     const int local = blockIdx.x;
     if (local >= npix) return;
-    const int64_t p = pix0 + local;
+    const int64_t p = idx ? (int64_t)idx[pix0 + local] : pix0 + local;
+    if (p < 0 || p >= npix_img) return;   // listed index outside the image: skipped
     chol_pixel(ws + (size_t)local * (Lp + 2) * Lp, Lp, load_rel, lrx ? lrx + p : nullptr,
                dwrx ? dwrx + p : nullptr, sm);
 }
@@ -36,13 +38,13 @@ __global__ __launch_bounds__(256) void chol_rx_kernel(double *__restrict__ ws, i
 size_t chol_smem(int64_t Lp) { return chol_smem_doubles((int)Lp) * sizeof(double); }
 
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
-                float *dwrx, hipStream_t s)
+                float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img)
 {
     const size_t sh = chol_smem(Lp);
     const int nt = Lp <= 32 ? 64 : 256;
     if (int rc = allow_lds((const void *)chol_rx_kernel, sh, "chol_rx_kernel")) return rc;
     hipLaunchKernelGGL(chol_rx_kernel, dim3((unsigned)npix), dim3(nt), sh, s, ws, (int)Lp, npix,
-                       pix0, load_rel, lrx, dwrx);
+                       pix0, load_rel, lrx, dwrx, idx, npix_img);
     return check_launch("chol_rx_kernel");
 }
 

@@ -24,6 +24,7 @@ struct GramArgs {
     int npix;            // pixels in the chunk
     double *ws;          // chunk workspace, (Lp+2)*Lp doubles per pixel
     uint32_t outer_magic;  // ceil(2^32 / outer) for k / outer
+    const int32_t *idx;  // optional pixel list: pixel = idx[pix0 + local] (NULL: pix0 + local)
 };
 
 
@@ -54,7 +55,8 @@ __device__ inline void gram_pixel(const GramArgs &a, int local, double *stage)
     const int Lpad = T * 16;
     double *mu = stage + (size_t)T * 64 * (PREC == 2 || PREC == 3 ? 2 : 1);
     double *mi = mu + Lpad;
-    const int64_t pix = a.pix0 + local;
+    const int64_t pix = a.idx ? (int64_t)a.idx[a.pix0 + local] : a.pix0 + local;
+    if (pix < 0 || pix >= (int64_t)a.H * a.W) return;   // listed index outside the image: skipped
     const int py = (int)(pix / a.W), px = (int)(pix - (int64_t)py * a.W);
     const int c16 = lane & 15, g4 = lane >> 4;
     const int K = (2 * a.R + 1) * (2 * a.R + 1);

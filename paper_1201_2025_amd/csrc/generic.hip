@@ -9,10 +9,11 @@ namespace hsad {
 
 size_t gram_lds_per_wave(int64_t Lp, int prec);
 int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, int mode,
-                int prec, int64_t pix0, int npix, double *ws, hipStream_t s);
+                int prec, int64_t pix0, int npix, double *ws, hipStream_t s,
+                const int32_t *idx = nullptr);
 size_t chol_smem(int64_t Lp);
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
-                float *dwrx, hipStream_t s);
+                float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img);
 size_t jacobi_smem(int64_t n);
 int jacobi_launch(const double *ws, int64_t n, int npix, int64_t pix0, float *score,
                   float *literal, int32_t *npos, hipStream_t s);
@@ -51,7 +52,26 @@ int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Win
         const int n = (int)((total - p0) < P ? (total - p0) : P);
         int rc = gram_launch(x, H, W, Lp, w, GRAM_LRX, prec, p0, n, (double *)ws, s);
         if (rc) return rc;
-        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s);
+        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s, nullptr, H * W);
+        if (rc) return rc;
+    }
+    return HSAD_OK;
+}
+
+// LRX / DWRX at a list of pixels (flat y * W + x); outputs written only there.
+int generic_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                        double load_rel, GramPrec prec, const int32_t *idx, int64_t nidx, float *lrx,
+                        float *dwrx, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (gram_lds_per_wave(Lp, prec) > 160 * 1024 || chol_smem(Lp) > 160 * 1024)
+        return fail(HSAD_EUNSUPPORTED, "generic path: L' too large");
+    const int64_t P = chunk_pixels(nidx, Lp, ws_bytes);
+    if (P < 1) return fail(HSAD_ENOMEM, "generic path: workspace below one pixel");
+    for (int64_t p0 = 0; p0 < nidx; p0 += P) {
+        const int n = (int)((nidx - p0) < P ? (nidx - p0) : P);
+        int rc = gram_launch(x, H, W, Lp, w, GRAM_LRX, prec, p0, n, (double *)ws, s, idx);
+        if (rc) return rc;
+        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s, idx, H * W);
         if (rc) return rc;
     }
     return HSAD_OK;

@@ -44,9 +44,10 @@ size_t gram_lds_per_wave(int64_t Lp, int prec)
 }
 
 int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, int mode,
-                int prec, int64_t pix0, int npix, double *ws, hipStream_t s)
+                int prec, int64_t pix0, int npix, double *ws, hipStream_t s, const int32_t *idx)
 {
     GramArgs a;
+    a.idx = idx;
     a.x = x;
     a.H = (int)H;
     a.W = (int)W;

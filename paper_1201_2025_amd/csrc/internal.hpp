@@ -50,6 +50,9 @@ size_t generic_ws_per_pixel(int64_t Lp, GramMode mode);
 int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                      double load_rel, GramPrec prec, float *lrx, float *dwrx, void *ws,
                      size_t ws_bytes, hipStream_t s);
+int generic_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
+                        double load_rel, GramPrec prec, const int32_t *idx, int64_t nidx, float *lrx,
+                        float *dwrx, void *ws, size_t ws_bytes, hipStream_t s);
 int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                   float *score, float *literal, int32_t *npos, void *ws, size_t ws_bytes,
                   hipStream_t s);

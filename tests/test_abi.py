@@ -115,3 +115,57 @@ def test_workspace_sizes():
     pb = _p(5, 15, prec=hs.HSAD_PREC_GRAM_BF16)
     assert L.hsad_workspace_bytes(hs.HSAD_OP_LRX, 64, 64, 4, ctypes.byref(pb)) > 0
     assert L.hsad_workspace_bytes(hs.HSAD_OP_DWEST, 64, 64, 4, ctypes.byref(p)) > 0
+
+
+def test_surrogate_dims_match_oracle():
+    from oracle import mlp
+    for Lp in (1, 4, 7, 14, 28, 56, 85):
+        D, Dp, npar, nbf = hs.hsad_mlp_dims(Lp)
+        assert (D, Dp, npar) == mlp.dims(Lp)
+        assert nbf == 128 * Dp + 2 * 128 * 128
+    for bad in (0, 86, 224):
+        with pytest.raises(hs.HsadError):
+            hs.hsad_mlp_dims(bad)
+    assert hs.hsad_mlp_train_workspace_bytes(16384, 64) == 256 * (mlp.dims(14)[2] + 4) * 4
+    assert hs.hsad_mlp_train_workspace_bytes(0, 64) == 0
+    assert hs.hsad_mlp_train_workspace_bytes(64, 48) == 0
+
+
+def test_surrogate_argument_errors():
+    L = hs.lib()
+    p = _p(5, 15)
+    idx = FAKE
+    # lrx at indices: windows, precision, workspace
+    assert L.hsad_lrx_dwrx_at(FAKE, 8, 8, 14, ctypes.byref(_p(5, 4)), idx, 3, FAKE, None, FAKE, 1 << 20,
+                              None) == hs.HSAD_EINVAL
+    assert L.hsad_lrx_dwrx_at(FAKE, 8, 8, 14, ctypes.byref(_p(0, 15)), idx, 3, None, FAKE, FAKE, 1 << 20,
+                              None) == hs.HSAD_EINVAL
+    assert L.hsad_lrx_dwrx_at(FAKE, 8, 8, 14, ctypes.byref(_p(5, 15, prec=hs.HSAD_PREC_GRAM_BF16)), idx, 3,
+                              FAKE, None, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    assert L.hsad_lrx_dwrx_at(FAKE, 8, 8, 14, ctypes.byref(p), idx, 3, FAKE, None, FAKE, 100,
+                              None) == hs.HSAD_ENOMEM
+    assert L.hsad_lrx_dwrx_at(FAKE, 8, 8, 14, ctypes.byref(p), idx, 0, FAKE, None, None, 0, None) == hs.HSAD_OK
+    # selection
+    assert L.hsad_surrogate_select(FAKE, 10, FAKE, -1.0, 0, 0.01, FAKE, FAKE, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_surrogate_select(FAKE, 10, FAKE, 1.0, 0, 1.5, FAKE, FAKE, FAKE, None) == hs.HSAD_EINVAL
+    # network entry points: Dp must be a multiple of 32 in 32..256
+    assert L.hsad_mlp_infer(FAKE, 10, 48, FAKE, FAKE, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_mlp_gradient(FAKE, 100, FAKE, FAKE, 64, 64, FAKE, FAKE, FAKE, FAKE, 10, None) == hs.HSAD_ENOMEM
+    assert L.hsad_mlp_gradient(FAKE, 0, FAKE, FAKE, 64, 64, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == hs.HSAD_EINVAL
+    assert L.hsad_mlp_train_step(FAKE, 100, FAKE, FAKE, 64, 64, FAKE, FAKE, FAKE, FAKE, 0, 1e-3, None, FAKE,
+                                 1 << 30, None) == hs.HSAD_EINVAL
+    # hybrid run: model / cube mismatch, options, workspace
+    m = hs.MlpModel(0x1000, 0x1000, 0x1000, 14, 64, 0, 0.1)
+    o = hs.SurrogateOptions(3.0, 3.0, 0.01, 2.0, 1)
+    rep = hs.SurrogateReport()
+    run = L.hsad_surrogate_run
+    assert run(FAKE, 64, 64, 13, ctypes.byref(p), ctypes.byref(m), ctypes.byref(o), FAKE, FAKE,
+               ctypes.byref(rep), FAKE, 1 << 40, None) == hs.HSAD_EINVAL
+    assert "model" in hs.hsad_last_error()
+    bad = hs.SurrogateOptions(3.0, 3.0, 2.0, 2.0, 1)
+    assert run(FAKE, 64, 64, 14, ctypes.byref(p), ctypes.byref(m), ctypes.byref(bad), FAKE, FAKE,
+               ctypes.byref(rep), FAKE, 1 << 40, None) == hs.HSAD_EINVAL
+    need = L.hsad_surrogate_workspace_bytes(64, 64, 14, 64, ctypes.byref(p))
+    assert need >= 64 * 64 * (64 * 2 + 4 + 1 + 4)
+    assert run(FAKE, 64, 64, 14, ctypes.byref(p), ctypes.byref(m), ctypes.byref(o), FAKE, FAKE,
+               ctypes.byref(rep), FAKE, need - 1, None) == hs.HSAD_ENOMEM

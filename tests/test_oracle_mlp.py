@@ -1,0 +1,175 @@
+"""Pins of the FP64 surrogate oracle (oracle/mlp.py) against independent facts:
+central finite differences, closed forms of special cases, the textbook Adam first step,
+brute-force annulus moments, and the sequential form of SplitMix64."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1201_2025_amd import synth
+
+
+def _net(seed, Dp, scale=0.2):
+    r = np.random.default_rng(seed)
+    W1 = r.standard_normal((Dp, 128)) * scale
+    b1 = r.standard_normal(128) * 0.1
+    W2 = r.standard_normal((128, 128)) * scale / 4
+    b2 = r.standard_normal(128) * 0.1
+    w3 = r.standard_normal(128) * 0.2
+    return mlp.pack(W1, b1, W2, b2, w3, 0.3)
+
+
+def test_dims():
+    assert mlp.dims(14) == (42, 64, 64 * 128 + 128 + 128 * 128 + 128 + 128 + 4)
+    assert mlp.dims(56)[:2] == (168, 192)
+    assert mlp.dims(4)[:2] == (12, 32)
+
+
+def test_gradient_matches_central_differences():
+    Dp = 32
+    p = _net(1, Dp)
+    r = np.random.default_rng(2)
+    X = r.standard_normal((9, Dp))
+    t = r.standard_normal(9)
+    t[4] = np.nan
+    loss, g = mlp.loss_and_grad(X, t, p, Dp)
+    assert g.shape == p.shape
+    idx = np.concatenate([r.choice(Dp * 128, 40, replace=False),                  # W1
+                          Dp * 128 + np.arange(0, 128, 17),                        # b1
+                          Dp * 128 + 128 + r.choice(128 * 128, 40, replace=False),  # W2
+                          Dp * 128 + 128 + 128 * 128 + np.arange(0, 128, 13),      # b2
+                          Dp * 128 + 2 * 128 + 128 * 128 + np.arange(0, 128, 11),  # w3
+                          [Dp * 128 + 3 * 128 + 128 * 128]])                       # b3
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (mlp.loss_and_grad(X, t, pp, Dp)[0] - mlp.loss_and_grad(X, t, pm, Dp)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), i
+    # padding entries carry no gradient
+    assert np.all(g[-3:] == 0)
+
+
+def test_zero_weights_closed_form():
+    Dp = 32
+    r = np.random.default_rng(3)
+    b1, b2, w3 = r.standard_normal(128), r.standard_normal(128), r.standard_normal(128)
+    p = mlp.pack(np.zeros((Dp, 128)), b1, np.zeros((128, 128)), b2, w3, 0.7)
+    X = r.standard_normal((5, Dp))
+    t = r.standard_normal(5)
+    y_expected = np.maximum(b2, 0) @ w3 + 0.7
+    assert np.allclose(mlp.forward(X, p, Dp), y_expected, rtol=0, atol=1e-12)
+    loss, g = mlp.loss_and_grad(X, t, p, Dp)
+    W1, gb1, W2, gb2, gw3, gb3 = mlp.unpack(g, Dp)
+    res = y_expected - t
+    assert np.isclose(loss, np.mean(res ** 2), rtol=1e-14)
+    assert np.isclose(gb3, 2 * np.mean(res), rtol=1e-12)
+    assert np.allclose(gw3, 2 * np.mean(res) * np.maximum(b2, 0), rtol=1e-12, atol=1e-15)
+    assert np.all(W1 == 0)      # a1 = b1 does not depend on X; dL/dW1 = X^T d1, d1 = 0 (W2 = 0)
+    assert np.all(gb1 == 0)
+
+
+def test_positive_regime_is_affine():
+    # with every pre-activation positive the network is x W1 W2 w3 + const
+    Dp = 32
+    r = np.random.default_rng(4)
+    W1 = np.abs(r.standard_normal((Dp, 128))) * 0.1
+    W2 = np.abs(r.standard_normal((128, 128))) * 0.1
+    b1, b2 = np.full(128, 5.0), np.full(128, 5.0)
+    w3 = r.standard_normal(128)
+    p = mlp.pack(W1, b1, W2, b2, w3, -1.0)
+    X = np.abs(r.standard_normal((7, Dp)))
+    direct = X @ (W1 @ (W2 @ w3)) + (b1 @ (W2 @ w3) + b2 @ w3 - 1.0)
+    assert np.allclose(mlp.forward(X, p, Dp), direct, rtol=1e-12)
+
+
+def test_adam_first_step_is_lr_sign():
+    g = np.array([3.0, -2e-3, 0.5, -40.0])
+    p, m, v = mlp.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
+    assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-5)
+    # second step with the same gradient moves by lr again
+    p2, _, _ = mlp.adam_step(p, g, m, v, 2, 0.01)
+    assert np.allclose(p2 - p, -0.01 * np.sign(g), rtol=1e-5)
+
+
+def test_features_brute_force():
+    x = synth.random_cube(5, 7, 6, 3).astype(np.float64)
+    for inner, outer in [(3, 5), (0, 3), (1, 5)]:
+        f = mlp.features(x, inner, outer)
+        H, W, Lp = x.shape
+        R, RI = outer // 2, inner // 2
+        for p in range(H * W):
+            py, px = divmod(p, W)
+            pts = [(yy, xx) for yy in range(H) for xx in range(W)
+                   if abs(yy - py) <= R and abs(xx - px) <= R
+                   and not (inner and abs(yy - py) <= RI and abs(xx - px) <= RI)]
+            a = np.array([x[yy, xx] for yy, xx in pts])
+            mu, var = a.mean(0), a.var(0)
+            ve = var + 1e-12
+            ref = np.concatenate([(x[py, px] - mu) / np.sqrt(ve), np.log(ve), mu])
+            assert np.allclose(f[p], ref, rtol=1e-9, atol=1e-12)
+
+
+def test_splitmix64_counter_form_equals_sequential():
+    for seed in (0, 1, 12345, 2 ** 64 - 1):
+        a = mlp.splitmix64(seed, np.arange(50))
+        b = mlp.splitmix64_sequential(seed, 50)
+        assert np.array_equal(a, b)
+    # distinct outputs (the finaliser is a bijection of the distinct states)
+    assert np.unique(mlp.splitmix64(7, np.arange(100000))).size == 100000
+
+
+def test_select_band_and_audit():
+    n = 200000
+    y = np.linspace(-2, 6, n).astype(np.float32)
+    y[17] = np.nan
+    tau = 10.0
+    f = mlp.select(y, tau, 0.25, 99, 0.01)
+    lt = np.log1p(tau)
+    band = (f & 1) == 1
+    assert band[17]
+    yy = y.astype(np.float64)
+    ok = ~np.isnan(yy)
+    assert np.array_equal(band[ok], np.abs(yy[ok] - lt) <= 0.25)
+    k = int(((f & 2) == 2).sum())
+    # binomial(n, 0.01): mean 2000, sd ~44.5; 6 sd
+    assert abs(k - 2000) < 270
+    assert mlp.select(y, tau, 0.25, 99, 0.0).max() <= 1
+    # audit is a function of the index, not of the values
+    g = mlp.select(y[::-1].copy(), tau, 0.25, 99, 0.01)
+    assert np.array_equal(f & 2, g & 2)
+
+
+def test_nan_rows_are_skipped():
+    Dp = 32
+    p = _net(5, Dp)
+    r = np.random.default_rng(6)
+    X = r.standard_normal((6, Dp))
+    t = r.standard_normal(6)
+    l_all, g_all = mlp.loss_and_grad(X[:4], t[:4], p, Dp)
+    t2 = t.copy()
+    t2[4:] = np.nan
+    l_nan, g_nan = mlp.loss_and_grad(X, t2, p, Dp)
+    # same sums, divided by 6 instead of 4
+    assert np.isclose(l_nan * 6, l_all * 4, rtol=1e-12)
+    assert np.allclose(g_nan * 6, g_all * 4, rtol=1e-10, atol=1e-14)
+
+
+def test_masks_equal_to_the_signs_change_nothing():
+    Dp = 32
+    p = _net(8, Dp)
+    r = np.random.default_rng(9)
+    X = r.standard_normal((7, Dp))
+    t = r.standard_normal(7)
+    W1, b1, W2, b2, _, _ = mlp.unpack(p, Dp)
+    a1 = X @ W1 + b1
+    a2 = np.maximum(a1, 0) @ W2 + b2
+    l0, g0 = mlp.loss_and_grad(X, t, p, Dp)
+    l1, g1 = mlp.loss_and_grad(X, t, p, Dp, masks=(a1 > 0, a2 > 0))
+    assert l0 == l1 and np.array_equal(g0, g1)
+    # a flipped decision of a unit changes the gradient only through that unit
+    m2 = a2 > 0
+    m2[0, 5] = ~m2[0, 5]
+    _, g2 = mlp.loss_and_grad(X, t, p, Dp, masks=(a1 > 0, m2))
+    assert not np.array_equal(g0, g2)
