@@ -15,7 +15,10 @@ printed.  Beside the timed step, the script also measures:
   * the same detector at full band (no DWT, L' = 224, exact FP64 Gram) on the same cube;
   * the DWT levels 1..5 sweep;
   * ROC AUC of the GPU scores minus that of the FP64 oracle scores (truth mask known);
-  * the FP64 CPU oracle on the host cores, for the same workload (cpu_baseline).
+  * the FP64 CPU oracle on the host cores, for the same workload (cpu_baseline);
+  * the 64-scene uneven batch through the persistent batch engine;
+  * the learned surrogate: exact vs hybrid LRX on a 2048 x 2048 x 224 scene at L' = 14
+    and 56, with the change of ROC AUC.
 """
 from __future__ import annotations
 
@@ -46,6 +49,11 @@ def parse():
     ap.add_argument("--no-fullband", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batch measurement")
     ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
+    ap.add_argument("--surrogate-scenes", type=int, default=200,
+                    help="training scenes of 256x256x224 for the surrogate (200 in the full workload)")
+    ap.add_argument("--surrogate-levels", type=str, default="4,2",
+                    help="DWT depths of the surrogate measurement (4 -> L'=14, 2 -> L'=56)")
     ap.add_argument("--profile", action="store_true",
                     help="timed steps only, then 3 plain 256 MiB device copies (counter calibration)")
     return ap.parse_args()
@@ -133,6 +141,111 @@ def bench_batch(args, dev):
             "plan": info}
 
 
+def bench_surrogate(args, dev, log):
+    """Learned surrogate: trained on exact LRX of generated 256x256x224 scenes, then used on
+    one 2048x2048x224 scene (same recipe).  For each DWT depth, the exact path (DWT + LRX +
+    eq. 12 mask) and the hybrid path (DWT + hsad_surrogate_run: features, network, band +
+    1% audit, exact recompute, fallback check, eq. 12 mask) are timed on the same cube, and
+    the ROC AUC of both maps against the truth mask is computed by hsad_auc."""
+    import torch
+    import paper_1201_2025_amd as hs
+    from paper_1201_2025_amd import synth
+    ct, ci = synth.CONFIGS["C5_train"], synth.CONFIGS["C5_infer"]
+    inner, outer, load = ct["inner"], ct["outer"], ct["load_rel"]
+    t0 = time.perf_counter()
+    cube, truth, _ = synth.make_scene_torch(ci["seed"], ci["H"], ci["W"], 224, K=ci["K"],
+                                            n_single=ci["n_single"], n_blob=ci["n_blob"], device=dev)
+    truth_t = torch.from_numpy(truth.ravel()).to(dev)
+    H, W = ci["H"], ci["W"]
+    npix = H * W
+    gen_s = time.perf_counter() - t0
+    out = {"workload": "train: %d scenes 256x256x224 (seeds %d+i); use: 2048x2048x224 seed %d; "
+                       "inner %d outer %d; band 3 x validation RMSE, 1%% audit, fallback at 2 x"
+                       % (args.surrogate_scenes, ct["seed"], ci["seed"], inner, outer),
+           "scene_gen_s": gen_s, "levels": []}
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(reps):
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    for lv in [int(v) for v in args.surrogate_levels.split(",") if v]:
+        Lp = hs.hsad_dwt_out_len(224, lv)
+        t0 = time.perf_counter()
+        sur = hs.Surrogate(Lp, inner, outer, load, seed=lv)
+        n_val = max(1, args.surrogate_scenes // 20)
+        for i in range(args.surrogate_scenes):
+            c, _, _ = synth.make_scene_torch(ct["seed"] + i, ct["H"], ct["W"], 224, K=ct["K"],
+                                             n_single=ct["n_single"], n_blob=ct["n_blob"], device=dev)
+            sur.add_scene(c, lv)
+            del c
+        torch.cuda.synchronize()
+        label_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hist = sur.fit(epochs=8, batch=16384, lr=2e-3, lr_final=1e-4, val_scenes=n_val, seed=lv)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        train_rows = int(sur.X_train.shape[0])
+        sur.release()
+        torch.cuda.empty_cache()
+
+        approx = torch.empty((H, W, Lp), dtype=torch.float32, device=dev)
+        exact = torch.empty((H, W), dtype=torch.float32, device=dev)
+        emask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        ws_b = hs.hsad_workspace_bytes(hs.HSAD_OP_LRX, H, W, Lp, inner, outer, load)
+        ws = torch.empty(max(ws_b, 1), dtype=torch.uint8, device=dev)
+        th_ws = torch.empty(hs.hsad_threshold_workspace_bytes(npix), dtype=torch.uint8, device=dev)
+        th = torch.empty(4, dtype=torch.float64, device=dev)
+
+        def run_exact():
+            hs.hsad_dwt(cube, lv, out=approx)
+            hs.hsad_lrx(approx, inner, outer, load, out=exact, ws=ws if ws_b else None)
+            hs.hsad_threshold(exact, 3.0, stats=th, mask=emask, ws=th_ws)
+
+        exact_ms = timed(run_exact)
+        del ws
+        sws = torch.empty(sur.workspace_bytes(H, W), dtype=torch.uint8, device=dev)
+        hyb = torch.empty((H, W), dtype=torch.float32, device=dev)
+        hmask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        rep = {}
+
+        def run_hybrid():
+            hs.hsad_dwt(cube, lv, out=approx)
+            _, _, r = sur.run(approx, z_alpha=3.0, band_k=3.0, audit_frac=0.01, fallback_factor=2.0,
+                              seed=12345, ws=sws, scores=hyb, mask=hmask)
+            rep.update(r)
+
+        hybrid_ms = timed(run_hybrid)
+        hs.hsad_dwt(cube, lv, out=approx)
+        pred_ms = timed(lambda: sur.predict(approx))
+        a_e = hs.auc_from_counts(hs.hsad_auc(exact, truth_t))
+        a_h = hs.auc_from_counts(hs.hsad_auc(hyb, truth_t))
+        mm = int((emask != hmask).sum().item())
+        del sws
+        entry = {"levels": lv, "Lp": Lp, "train_rows": train_rows, "label_gen_s": label_s,
+                 "train_s": train_s, "epochs": len(hist), "val_rmse": sur.rmse_val,
+                 "history": [[round(a, 5), round(b, 5)] for a, b in hist],
+                 "exact_ms": exact_ms, "hybrid_ms": hybrid_ms, "features_and_network_ms": pred_ms,
+                 "gain": exact_ms / hybrid_ms,
+                 "exact_pixels_per_s": npix / (exact_ms * 1e-3), "hybrid_pixels_per_s": npix / (hybrid_ms * 1e-3),
+                 "auc_exact": a_e, "auc_hybrid": a_h, "auc_delta": a_h - a_e,
+                 "mask_mismatch": mm, "report": rep}
+        log("surrogate L'=%d: exact %.2f ms, hybrid %.2f ms (gain %.2fx), dAUC %.2e, selected %.4f, fallback %d"
+            % (Lp, exact_ms, hybrid_ms, exact_ms / hybrid_ms, a_h - a_e, rep["selected"] / npix, rep["fallback"]))
+        out["levels"].append(entry)
+        del sur, approx, exact, hyb
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -214,8 +327,8 @@ def main():
     # once (H W L 4) and write the approximation matrix (H W L' 4).
     dwt_bytes = npix * L * 4 + npix * Lp * 4
     achieved = dwt_bytes / (dwt_ms * 1e-3)
-    dwt_kernel = "dwt_equiv_kernel" if Lp <= 16 else "dwt_cascade_kernel"
-    src_hash = kernel_source_hash(["dwt.hip"])
+    dwt_kernel = "dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_cascade_kernel"
+    src_hash = kernel_source_hash(["dwt.hip", "dev_dwt.hpp"])
     traffic = load_traffic(dwt_kernel, "C2_L%d_J%d" % (L, J), src_hash)
 
     # ROC AUC of the GPU scores vs the FP64 oracle scores on the same cube
@@ -242,17 +355,19 @@ def main():
                                "lrx_rel_err_median": float(np.median(rel)),
                                "mask_mismatch": int((mask.cpu().numpy().ravel() != ref_mask).sum())}
         if not args.no_cpu:
-            # the whole workload once (the oracle takes about a second on 16 cores)
-            reps = []
-            for _ in range(3):
+            # whole-cube passes of the oracle until about 10 s of CPU work have been timed
+            reps, spent = [], 0.0
+            while spent < 10.0 and len(reps) < 200:
                 t = time.perf_counter()
                 ra = oracle.dwt_approx(scene.cube, J)
-                oracle.lrx_dwrx(ra, inner, outer, load)
-                oracle.threshold(rl, 3.0)
+                r_l, _ = oracle.lrx_dwrx(ra, inner, outer, load)
+                oracle.mask(r_l, oracle.threshold(r_l, 3.0))
                 reps.append(time.perf_counter() - t)
-            cpu = {"value": npix / float(np.median(reps)), "unit": "pixels/s", "cores": threads,
+                spent += reps[-1]
+            cpu = {"value": npix * len(reps) / spent, "unit": "pixels/s", "cores": threads,
                    "kind": "oracle",
-                   "sample": "whole 512x512x224 cube, DWT J=%d + LRX/DWRX + eq. 12; median of 3" % J}
+                   "sample": "%d passes over the whole 512x512x224 cube (DWT J=%d + LRX/DWRX + eq. 12 "
+                             "mask), %.1f s" % (len(reps), J, spent)}
     except Exception as e:       # the oracle is test infrastructure; report, don't fail
         result_extra["oracle_error"] = repr(e)
 
@@ -316,6 +431,16 @@ def main():
                           "dwt_hbm_frac": (npix * (L + lpj) * 4) / (dm * 1e-3) / HBM_PEAK})
             del wsj
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    surrogate = None
+    if not args.no_surrogate:
+        try:
+            surrogate = bench_surrogate(args, dev, log)
+        except Exception as e:     # report, keep the headline line
+            surrogate = {"error": repr(e)}
+
     batch = None
     if not args.no_batch:
         try:
@@ -350,6 +475,7 @@ def main():
         "full_band_gpu": full,
         "sweep": sweep,
         "batch": batch,
+        "surrogate": surrogate,
     }
     out.update(result_extra)
     print(json.dumps(out))

@@ -24,13 +24,16 @@ template <int LP> __device__ __forceinline__ double feat(const double *f, double
 {
     if (g < LP) return f[g];
     if (g >= BoxCfg<LP>::G) return b;
-    int r = g - LP, i = 0, len = LP;
-    while (r >= len) {
-        r -= len;
-        --len;
-        ++i;
-    }
-    return f[i] * f[i + r];
+    // product feature r = g - LP enumerates the upper triangle row by row; row k starts at
+    // k LP - k (k - 1) / 2.  A fixed-trip-count search keeps every index a compile-time
+    // constant once g is (a data-dependent loop here sends f[] to scratch memory).
+    const int r = g - LP;
+    int i = 0;
+#pragma unroll
+    for (int k = 1; k < LP; ++k)
+        if (r >= k * LP - k * (k - 1) / 2) i = k;
+    const int j = i + (r - (i * LP - i * (i - 1) / 2));
+    return f[i] * f[j];
 }
 
 // Centred values of tile pixel t (FP64, exact).
