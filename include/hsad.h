@@ -365,14 +365,19 @@ size_t hsad_error_stats_workspace_bytes(int64_t n);
 int hsad_error_stats(const float *yhat, const float *ref, int32_t ref_is_score, const uint8_t *flags,
                      int32_t flag_mask, int64_t n, double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace of hsad_surrogate_select (bytes). */
+size_t hsad_surrogate_select_workspace_bytes(int64_t n);
+
 /* Pixels sent to the exact detector.  flags[i] = 1 when |yhat[i] - log1p(stats[3])| <= band
  * (NaN predictions included), plus 2 when the upper 32 bits of SplitMix64 output i of the
  * stream seeded with `seed` (state seed + (i+1) 0x9E3779B97F4A7C15, then the standard
  * finaliser) are below audit_frac * 2^32.  The indices of the flagged pixels are written to
- * idx in unspecified order; counts (device, 3 uint32) = {flagged, band, audit}.  stats is
- * the device output of hsad_threshold.  Errors: HSAD_EINVAL, HSAD_EHIP. */
+ * idx in ascending order; counts (device, 3 uint32) = {flagged, band, audit}.  stats is
+ * the device output of hsad_threshold.  Three launches, no atomics (deterministic).
+ * Errors: HSAD_EINVAL, HSAD_ENOMEM, HSAD_EHIP. */
 int hsad_surrogate_select(const float *yhat, int64_t n, const double *stats, double band, uint64_t seed,
-                          double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, hipStream_t stream);
+                          double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
 
 /* Workspace of hsad_surrogate_run (bytes). */
 size_t hsad_surrogate_workspace_bytes(int64_t H, int64_t W, int64_t Lp, int32_t Dp, const hsad_window_params *p);

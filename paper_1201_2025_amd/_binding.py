@@ -118,8 +118,9 @@ SIGNATURES = [
     ("hsad_error_stats_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("hsad_error_stats", ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _i64, _vp, _vp,
                                         ctypes.c_size_t, _vp]),
+    ("hsad_surrogate_select_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("hsad_surrogate_select", ctypes.c_int, [_vp, _i64, _vp, ctypes.c_double, ctypes.c_uint64,
-                                             ctypes.c_double, _vp, _vp, _vp, _vp]),
+                                             ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_surrogate_workspace_bytes", ctypes.c_size_t, [_i64, _i64, _i64, ctypes.c_int32, _P]),
     ("hsad_surrogate_run", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.POINTER(MlpModel),
                                           ctypes.POINTER(SurrogateOptions), _vp, _vp,
@@ -605,16 +606,18 @@ def hsad_error_stats(yhat, ref, ref_is_score: bool, flags=None, flag_mask: int =
 
 def hsad_surrogate_select(yhat, stats, band: float, seed: int, audit_frac: float, flags=None, idx=None,
                           counts=None, stream=None):
-    """Returns (flags uint8, idx int32 (first counts[0] valid), counts int32[3])."""
+    """Returns (flags uint8, idx int32 (first counts[0] valid, ascending), counts int32[3])."""
     torch = _torch()
     n = yhat.numel()
     flags = torch.empty(n, dtype=torch.uint8, device=yhat.device) if flags is None else flags
     idx = torch.empty(n, dtype=torch.int32, device=yhat.device) if idx is None else idx
     counts = torch.empty(3, dtype=torch.int32, device=yhat.device) if counts is None else counts
+    ws = torch.empty(int(lib().hsad_surrogate_select_workspace_bytes(n)), dtype=torch.uint8, device=yhat.device)
     rc = lib().hsad_surrogate_select(_dev(yhat, "yhat", torch.float32), n, _dev(stats, "stats", torch.float64),
                                      float(band), int(seed) & ((1 << 64) - 1), float(audit_frac),
                                      _dev(flags, "flags", torch.uint8), _dev(idx, "idx", torch.int32),
-                                     _dev(counts, "counts", torch.int32), _stream(stream))
+                                     _dev(counts, "counts", torch.int32), _dev(ws, "ws"),
+                                     ws.numel(), _stream(stream))
     _check("hsad_surrogate_select", rc)
     return flags, idx, counts
 

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace hsad {
 
 struct Taps {
@@ -66,6 +68,110 @@ __device__ inline void dwt_cascade_tile(const float *__restrict__ cube, int64_t 
     for (int t = tid; t < np * Lp; t += 256) {
         const int p = t / Lp, k = t - p * Lp;
         dst[t] = (float)cur[p * scur + k];
+    }
+}
+
+
+// ------------------------------------------------------------------------------------
+// Banded equivalent filter.  After J levels, output k depends only on a circular window of
+// the input: at most 7 (2^J - 1) + 1 samples, because each level reads 8 taps at stride 2
+// (the odd-length extension only repeats a neighbouring sample).  coef holds, for every
+// output k, W coefficients of that window ([L'][W], FP64, zero past the row's own width),
+// and start[k] its first input index.  The cascade's composite map is the same linear map,
+// so this gives the cascade's result with W FMAs per output instead of 8 per level, in one
+// pass over the input.
+// ------------------------------------------------------------------------------------
+// LDS floats of a tile of P spectra: input rows of L + W - 1 samples (the first W - 1 samples
+// repeated after the last, so that a window never wraps), odd stride; output rows of stride L'|1.
+__host__ __device__ inline int64_t dwt_banded_lds_floats(int64_t L, int64_t Lp, int64_t W, int64_t P)
+{
+    return P * ((L + W - 1) | 1) + P * (Lp | 1);
+}
+
+// np (<= P <= 64) contiguous spectra starting at pixel p0; a workgroup of 256 threads.
+// Stage: the np*L contiguous input floats are copied into padded LDS rows (float4 loads
+// when L % 4 == 0), with the circular extension.  Compute: lane = pixel, wavefront w takes
+// outputs k = w, w + 4, ..., so k (and every coefficient address) is uniform across the
+// wavefront, and a lane reads W consecutive samples of its own row (odd stride: no bank
+// conflicts; constant offsets).  FP64 accumulation.  Write-out: the np*L' outputs leave
+// through padded LDS rows as one contiguous store.
+// magic_L = ceil(2^32 / L), magic_Lp = ceil(2^32 / L'): exact quotients for t < 64 L.
+template <int VEC>
+__device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p0, int np, int L, int Lp,
+                                       int W, const double *__restrict__ coef,
+                                       const int32_t *__restrict__ start, uint32_t magic_L,
+                                       uint32_t magic_Lp, float *__restrict__ out, float *lds, int P)
+{
+    const int LDP = (L + W - 1) | 1, LDO = Lp | 1;
+    const uint32_t ext = (uint32_t)(W - 1);
+    float *xs = lds;                          // P * LDP
+    float *os = lds + (size_t)P * LDP;        // P * LDO
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+
+    const float *src = cube + p0 * (int64_t)L;
+    const int total = np * L;
+    if constexpr (VEC == 4) {
+        const int nv = total >> 2;
+        const float4 *s4 = reinterpret_cast<const float4 *>(src);
+#pragma unroll 4
+        for (int v = tid; v < nv; v += 256) {
+            const float4 q = s4[v];
+            const uint32_t e = 4u * (uint32_t)v;
+            const uint32_t r = __umulhi(e, magic_L);
+            const uint32_t col = e - r * (uint32_t)L;
+            float *d = xs + r * LDP + col;
+            d[0] = q.x;
+            d[1] = q.y;
+            d[2] = q.z;
+            d[3] = q.w;
+            if (col < ext) {
+                float *dd = d + L;
+                const float qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (col + j < ext) dd[j] = qq[j];
+            }
+        }
+    } else {
+#pragma unroll 4
+        for (int t = tid; t < total; t += 256) {
+            const uint32_t r = __umulhi((uint32_t)t, magic_L);
+            const uint32_t col = (uint32_t)t - r * (uint32_t)L;
+            const float v = src[t];
+            xs[r * LDP + col] = v;
+            if (col < ext) xs[r * LDP + col + L] = v;
+        }
+    }
+    __syncthreads();
+
+    if (lane < np) {
+        const float *xp = xs + lane * LDP;
+        for (int k = wave; k < Lp; k += 4) {
+            const double *c = coef + (size_t)k * W;
+            const float *xk = xp + start[k];
+            double a0 = 0.0, a1 = 0.0;
+            int t = 0;
+            for (; t + 8 <= W; t += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    a0 = fma(c[t + u], (double)xk[t + u], a0);
+                    a1 = fma(c[t + u + 1], (double)xk[t + u + 1], a1);
+                }
+            }
+            for (; t < W; ++t) a0 = fma(c[t], (double)xk[t], a0);
+            os[lane * LDO + k] = (float)(a0 + a1);
+        }
+    }
+    __syncthreads();
+
+    float *dst = out + p0 * (int64_t)Lp;
+    const int ototal = np * Lp;
+#pragma unroll 4
+    for (int t = tid; t < ototal; t += 256) {
+        const uint32_t r = __umulhi((uint32_t)t, magic_Lp);
+        dst[t] = os[r * LDO + ((uint32_t)t - r * (uint32_t)Lp)];
     }
 }
 

@@ -126,6 +126,81 @@ static const double *composite_coefs(int64_t L, int levels, int64_t Lp, int vec,
     return base + res.first->second.offset;
 }
 
+// Banded form of the composite matrix: per row k the smallest circular window of input
+// indices that holds all its nonzeros (start s_k, width w_k); W = max_k w_k.  Returns
+// false when the arena is full or W exceeds max_w.  Layout in the arena: coef [L'][W]
+// doubles, then L' int32 starts (rounded up to whole doubles).
+struct BandedCoefs {
+    const double *coef;
+    const int32_t *start;
+    int W;
+};
+
+static bool banded_coefs(int64_t L, int levels, int64_t Lp, int max_w, hipStream_t s, BandedCoefs *out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(g_coef_mu);
+    double *base = nullptr;
+    if (hipGetSymbolAddress((void **)&base, HIP_SYMBOL(g_coef_arena)) != hipSuccess) return false;
+    CoefKey key{dev, L, levels, -1};
+    auto it = g_coef.find(key);
+    if (it == g_coef.end()) {
+        std::vector<double> A((size_t)(Lp * L));
+        dwt_composite_matrix(L, levels, A.data());
+        std::vector<int32_t> st((size_t)Lp);
+        std::vector<int> wd((size_t)Lp);
+        int W = 0;
+        for (int64_t k = 0; k < Lp; ++k) {
+            const double *row = A.data() + k * L;
+            std::vector<int64_t> nz;
+            for (int64_t i = 0; i < L; ++i)
+                if (row[i] != 0.0) nz.push_back(i);
+            if (nz.empty()) {
+                st[k] = 0;
+                wd[k] = 0;
+                continue;
+            }
+            // largest circular gap between consecutive nonzeros; the window is its complement
+            int64_t best_gap = -1, best_next = 0;
+            for (size_t q = 0; q < nz.size(); ++q) {
+                const int64_t a = nz[q], b = q + 1 < nz.size() ? nz[q + 1] : nz[0] + L;
+                if (b - a - 1 > best_gap) {
+                    best_gap = b - a - 1;
+                    best_next = (q + 1 < nz.size() ? nz[q + 1] : nz[0]);
+                }
+            }
+            st[k] = (int32_t)best_next;
+            wd[k] = (int)(L - best_gap);
+            if (wd[k] > W) W = wd[k];
+        }
+        const size_t ncoef = (size_t)(Lp * W), nst = (size_t)((Lp + 1) / 2);
+        CoefEntry e;
+        e.host.assign(ncoef + nst, 0.0);
+        for (int64_t k = 0; k < Lp; ++k)
+            for (int t = 0; t < wd[k]; ++t) e.host[(size_t)(k * W + t)] = A[(size_t)(k * L + (st[k] + t) % L)];
+        std::memcpy(e.host.data() + ncoef, st.data(), st.size() * sizeof(int32_t));
+        size_t &used = g_coef_used[dev];
+        const size_t off = (used + 31) & ~(size_t)31;
+        if (off + ncoef + nst + 1 > kCoefArenaDoubles) return false;
+        e.host.push_back((double)W);   // width kept after the table
+        e.offset = off;
+        if (hipMemcpyAsync(base + off, e.host.data(), e.host.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return false;
+        used = off + e.host.size();
+        it = g_coef.emplace(key, std::move(e)).first;
+    }
+    const std::vector<double> &h = it->second.host;
+    const int W = (int)h.back();
+    if (W < 1 || W > max_w) return false;
+    out->coef = base + it->second.offset;
+    out->start = reinterpret_cast<const int32_t *>(base + it->second.offset + (size_t)(Lp * W));
+    out->W = W;
+    return true;
+}
+
 // ------------------------------------------------------------------------------------
 // device: equivalent-filter kernel
 // ------------------------------------------------------------------------------------
@@ -317,6 +392,35 @@ __global__ __launch_bounds__(256) void dwt_cascade_kernel(const float *__restric
 }
 
 // ------------------------------------------------------------------------------------
+// device: banded equivalent-filter kernel (body in dev_dwt.hpp)
+// ------------------------------------------------------------------------------------
+template <int VEC>
+__global__ __launch_bounds__(256) void dwt_banded_kernel(const float *__restrict__ cube, int64_t npix, int L,
+                                                         int Lp, int W, const double *__restrict__ coef,
+                                                         const int32_t *__restrict__ start, uint32_t magic_L,
+                                                         uint32_t magic_Lp, int P, float *__restrict__ out)
+{
+    extern __shared__ float ldsf[];
+    const int64_t p0 = (int64_t)blockIdx.x * P;
+    const int np = (int)((npix - p0) < P ? (npix - p0) : P);
+    dwt_banded_tile<VEC>(cube, p0, np, L, Lp, W, coef, start, magic_L, magic_Lp, out, ldsf, P);
+}
+
+static uint32_t magic_u32(int64_t d) { return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d); }
+
+// Pixels per banded tile: at most 32 and as many as fit 40 KiB of LDS, so that four
+// workgroups share a CU and one workgroup's staging overlaps another's FP64 loop (measured
+// at 2048 x 2048 x 224: 32-pixel tiles beat 64-pixel tiles by 10-30 %); a multiple of 4 so
+// float4 staging stays aligned.
+static int banded_pixels(int64_t L, int64_t Lp, int64_t W)
+{
+    int64_t P = (40 * 1024 / 4) / (((L + W - 1) | 1) + (Lp | 1));
+    if (P > 32) P = 32;
+    P &= ~(int64_t)3;
+    return (int)P;
+}
+
+// ------------------------------------------------------------------------------------
 // dispatch
 // ------------------------------------------------------------------------------------
 template <int LP>
@@ -356,7 +460,8 @@ static int launch_equiv_lp(int64_t Lp, const float *cube, int64_t npix, int64_t 
     }
 }
 
-// -1 auto, 0 cascade, 1 equivalent filter (LDS-staged), 2 equivalent filter (per-lane loads)
+// -1 auto, 0 cascade, 1 equivalent filter (LDS-staged), 2 equivalent filter (per-lane loads),
+// 3 banded equivalent filter (where it applies; otherwise as auto)
 static int g_dwt_force = -1;
 
 int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t Lp,
@@ -370,13 +475,31 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
         return HSAD_OK;
     }
     const bool equiv_ok = Lp <= 16;
-    if (equiv_ok && g_dwt_force != 0) {
+    if (equiv_ok && g_dwt_force != 0 && g_dwt_force != 3) {
         const bool lds = g_dwt_force != 2;
         // the LDS-staged kernel reads the matrix band-major ([band][k], interleave 1)
         const int vec = lds ? 1 : ((L % 4 == 0) ? 4 : ((L % 2 == 0) ? 2 : 1));
         const int ldvec = (L % 4 == 0) ? 4 : 1;
         const double *coef = composite_coefs(L, levels, Lp, vec, s);
         if (coef) return launch_equiv_lp(Lp, cube, npix, L, coef, lds ? ldvec : vec, lds, approx, s);
+    }
+    // banded equivalent filter for longer outputs (each output reads <= 7 (2^J - 1) + 1
+    // samples); the cascade remains for very long spectra and as a fallback
+    BandedCoefs bc;
+    int bP = 0;
+    if (g_dwt_force != 0 && g_dwt_force != 1 && g_dwt_force != 2 && L < 8192 &&
+        banded_coefs(L, levels, Lp, 128, s, &bc) && (bP = banded_pixels(L, Lp, bc.W)) >= 4) {
+        const size_t sh = (size_t)dwt_banded_lds_floats(L, Lp, bc.W, bP) * sizeof(float);
+        const void *kern = (L % 4 == 0) ? (const void *)dwt_banded_kernel<4> : (const void *)dwt_banded_kernel<1>;
+        if (int rc = allow_lds(kern, sh, "dwt_banded_kernel")) return rc;
+        dim3 grid((unsigned)((npix + bP - 1) / bP)), block(256);
+        if (L % 4 == 0)
+            hipLaunchKernelGGL(dwt_banded_kernel<4>, grid, block, sh, s, cube, npix, (int)L, (int)Lp, bc.W, bc.coef,
+                               bc.start, magic_u32(L), magic_u32(Lp), bP, approx);
+        else
+            hipLaunchKernelGGL(dwt_banded_kernel<1>, grid, block, sh, s, cube, npix, (int)L, (int)Lp, bc.W, bc.coef,
+                               bc.start, magic_u32(L), magic_u32(Lp), bP, approx);
+        return check_launch("dwt_banded_kernel");
     }
     // cascade: size the pixel tile so that both ping-pong buffers fit in 64 KiB of LDS
     const int64_t per_pix = dwt_cascade_lds_doubles(L, 1);

@@ -533,16 +533,37 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const uint16_t *__restric
     }
 }
 
-// fixed-order sum of the partials: grad[i] for i < nparams, grad[nparams] = mean loss
+// Total over the nwg gradient partials of element i = 64 blockIdx.x + (threadIdx.x & 63),
+// in a fixed order: wavefront g sums the partials w = g, g + 4, ... in sequence, then the
+// four sums are combined as (s0 + s1) + (s2 + s3).  Blocks of 256 threads; the result is
+// returned to the first wavefront (false elsewhere and past np).
+__device__ inline bool partial_total(const float *__restrict__ part, int nwg, int64_t np, float *red, float *total,
+                                     int64_t *index)
+{
+    const int g = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 64 + j, stride = np + 4;
+    float s = 0.f;
+    if (i <= np) {
+#pragma unroll 8
+        for (int w = g; w < nwg; w += 4) s += part[(size_t)w * stride + i];
+    }
+    red[g * 64 + j] = s;
+    __syncthreads();
+    if (g != 0 || i > np) return false;
+    *total = (red[j] + red[64 + j]) + (red[128 + j] + red[192 + j]);
+    *index = i;
+    return true;
+}
+
+// grad[i] for i < nparams, grad[nparams] = mean loss
 __global__ __launch_bounds__(256) void grad_sum_kernel(const float *__restrict__ part, int nwg, int Dp,
                                                        float inv_batch, float *__restrict__ grad)
 {
-    const int64_t np = mlp_nparams(Dp), stride = np + 4;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= np; i += (int64_t)gridDim.x * blockDim.x) {
-        float acc = 0.f;
-        for (int w = 0; w < nwg; ++w) acc += part[(size_t)w * stride + i];
-        grad[i] = i == np ? acc * inv_batch : acc;
-    }
+    __shared__ float red[256];
+    const int64_t np = mlp_nparams(Dp);
+    float gs;
+    int64_t i;
+    if (partial_total(part, nwg, np, red, &gs, &i)) grad[i] = i == np ? gs * inv_batch : gs;
 }
 
 __device__ __forceinline__ void store_bf16_copy(int64_t i, float w, int Dp, uint16_t *wbf)
@@ -558,29 +579,29 @@ __device__ __forceinline__ void store_bf16_copy(int64_t i, float w, int Dp, uint
 }
 
 // Adam (Kingma and Ba 2015, Algorithm 1: beta1 0.9, beta2 0.999, eps 1e-8) on the FP32
-// master weights from the fixed-order sum of the partials; refreshes the BF16 copies.
+// master weights from the fixed-order total of the partials; refreshes the BF16 copies.
 __global__ __launch_bounds__(256) void mlp_adam_kernel(const float *__restrict__ part, int nwg, int Dp,
                                                        float *__restrict__ params, float *__restrict__ m,
                                                        float *__restrict__ v, uint16_t *__restrict__ wbf,
                                                        float lr, float b1c, float b2c, float inv_batch,
                                                        float *__restrict__ loss_out)
 {
-    const int64_t np = mlp_nparams(Dp), stride = np + 4;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= np; i += (int64_t)gridDim.x * blockDim.x) {
-        float gs = 0.f;
-        for (int w = 0; w < nwg; ++w) gs += part[(size_t)w * stride + i];
-        if (i == np) {
-            if (loss_out) loss_out[0] = gs * inv_batch;
-            continue;
-        }
-        const float mi = 0.9f * m[i] + 0.1f * gs;
-        const float vi = 0.999f * v[i] + 0.001f * gs * gs;
-        m[i] = mi;
-        v[i] = vi;
-        const float w = params[i] - lr * (mi / b1c) / (sqrtf(vi / b2c) + 1e-8f);
-        params[i] = w;
-        store_bf16_copy(i, w, Dp, wbf);
+    __shared__ float red[256];
+    const int64_t np = mlp_nparams(Dp);
+    float gs;
+    int64_t i;
+    if (!partial_total(part, nwg, np, red, &gs, &i)) return;
+    if (i == np) {
+        if (loss_out) loss_out[0] = gs * inv_batch;
+        return;
     }
+    const float mi = 0.9f * m[i] + 0.1f * gs;
+    const float vi = 0.999f * v[i] + 0.001f * gs * gs;
+    m[i] = mi;
+    v[i] = vi;
+    const float w = params[i] - lr * (mi / b1c) / (sqrtf(vi / b2c) + 1e-8f);
+    params[i] = w;
+    store_bf16_copy(i, w, Dp, wbf);
 }
 
 __global__ __launch_bounds__(256) void mlp_sync_kernel(const float *__restrict__ params, int Dp, uint16_t *__restrict__ wbf)
@@ -603,36 +624,109 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
     return z ^ (z >> 31);
 }
 
-// flags[i] = 1 when |yhat_i - log1p(tau)| <= band (NaN predictions count as inside),
-// | 2 when the top 32 bits of SplitMix64(seed, i) fall below audit_cut.  Flagged indices
-// are appended to idx (one atomic per wavefront; the order within idx is unspecified).
-// counts = {flagged, band, audit}, cleared by the caller's fill kernel.
-__global__ __launch_bounds__(256) void surr_select_kernel(const float *__restrict__ yhat, int64_t n,
-                                                          const double *__restrict__ stats, double band,
-                                                          uint64_t seed, uint32_t audit_cut, uint8_t *__restrict__ flags,
-                                                          int32_t *__restrict__ idx, unsigned *__restrict__ counts)
+// Selection in three passes, so that the list is deterministic and sorted:
+//  1. flags[i] = 1 when |yhat_i - log1p(tau)| <= band (NaN predictions count as inside)
+//     | 2 when the top 32 bits of SplitMix64(seed, i) fall below audit_cut; block b covers
+//     the contiguous range [b seg, (b + 1) seg) and stores its {flagged, band, audit} counts;
+//  2. one block scans the per-block counts (exclusive offsets, totals into counts);
+//  3. every block writes the indices of its flagged pixels in ascending order.
+constexpr int kSelMaxBlocks = 4096;
+
+__device__ inline unsigned block_sum_u32(unsigned v, unsigned *red)
 {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void select_flags_kernel(const float *__restrict__ yhat, int64_t n,
+                                                           const double *__restrict__ stats, double band,
+                                                           uint64_t seed, uint32_t audit_cut, int64_t seg,
+                                                           uint8_t *__restrict__ flags, unsigned *__restrict__ bcnt)
+{
+    __shared__ unsigned red[4];
     const double tl = log1p(stats[3]);
-    const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        unsigned f = 0;
-        if (i < n) {
-            const double d = fabs((double)yhat[i] - tl);
-            const bool in_band = !(d > band);
-            const bool audit = (uint32_t)(splitmix64_at(seed, (uint64_t)i) >> 32) < audit_cut;
-            f = (in_band ? 1u : 0u) | (audit ? 2u : 0u);
-            flags[i] = (uint8_t)f;
+    const int64_t b0 = (int64_t)blockIdx.x * seg, b1 = b0 + seg < n ? b0 + seg : n;
+    unsigned cs = 0, cb = 0, ca = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+        const bool in_band = !(fabs((double)yhat[i] - tl) > band);
+        const bool audit = (uint32_t)(splitmix64_at(seed, (uint64_t)i) >> 32) < audit_cut;
+        const unsigned f = (in_band ? 1u : 0u) | (audit ? 2u : 0u);
+        flags[i] = (uint8_t)f;
+        cs += f != 0u;
+        cb += f & 1u;
+        ca += f >> 1;
+    }
+    cs = block_sum_u32(cs, red);
+    cb = block_sum_u32(cb, red);
+    ca = block_sum_u32(ca, red);
+    if (threadIdx.x == 0) {
+        bcnt[3 * blockIdx.x] = cs;
+        bcnt[3 * blockIdx.x + 1] = cb;
+        bcnt[3 * blockIdx.x + 2] = ca;
+    }
+}
+
+// one block of 1024 threads; nb <= 4096 (four per thread)
+__global__ __launch_bounds__(1024) void select_scan_kernel(const unsigned *__restrict__ bcnt, int nb,
+                                                           unsigned *__restrict__ boff, unsigned *__restrict__ counts)
+{
+    __shared__ unsigned sc[1024];
+    const int t = threadIdx.x;
+    unsigned v[4], loc = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int b = 4 * t + q;
+        v[q] = b < nb ? bcnt[3 * b] : 0u;
+        loc += v[q];
+    }
+    sc[t] = loc;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan
+        const unsigned add = t >= o ? sc[t - o] : 0u;
+        __syncthreads();
+        sc[t] += add;
+        __syncthreads();
+    }
+    unsigned run = sc[t] - loc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int b = 4 * t + q;
+        if (b < nb) boff[b] = run;
+        run += v[q];
+    }
+    if (t == 0) {
+        unsigned tb = 0, ta = 0;
+        for (int b = 0; b < nb; ++b) {
+            tb += bcnt[3 * b + 1];
+            ta += bcnt[3 * b + 2];
         }
-        const uint64_t sel = __ballot(f != 0), bnd = __ballot(f & 1u), aud = __ballot((f & 2u) != 0);
-        unsigned wbase = 0;
-        if (lane == 0 && sel) {
-            wbase = atomicAdd(&counts[0], (unsigned)__popcll(sel));
-            atomicAdd(&counts[1], (unsigned)__popcll(bnd));
-            atomicAdd(&counts[2], (unsigned)__popcll(aud));
-        }
-        wbase = __shfl(wbase, 0, 64);
-        if (f) idx[wbase + __popcll(sel & ((1ull << lane) - 1ull))] = (int32_t)i;
+        counts[0] = sc[1023];
+        counts[1] = tb;
+        counts[2] = ta;
+    }
+}
+
+__global__ __launch_bounds__(256) void select_write_kernel(const uint8_t *__restrict__ flags, int64_t n, int64_t seg,
+                                                           const unsigned *__restrict__ boff, int32_t *__restrict__ idx)
+{
+    __shared__ unsigned wsum[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * seg, b1 = b0 + seg < n ? b0 + seg : n;
+    unsigned base = boff[blockIdx.x];
+    for (int64_t s0 = b0; s0 < b1; s0 += 256) {
+        const int64_t i = s0 + threadIdx.x;
+        const bool f = i < b1 && flags[i] != 0;
+        const uint64_t m = __ballot(f);
+        if (lane == 0) wsum[wv] = (unsigned)__popcll(m);
+        __syncthreads();
+        unsigned pre = 0;
+        for (int q = 0; q < wv; ++q) pre += wsum[q];
+        if (f) idx[base + pre + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+        base += (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+        __syncthreads();
     }
 }
 
@@ -781,7 +875,8 @@ RunLayout run_layout(int64_t H, int64_t W, int64_t Lp, int Dp, const hsad_window
     // counts (4 u32, 64 B) | predicted-map stats (4) | final stats (4) | audit (4) doubles,
     // then the threshold / error-statistics workspace
     L.small = o;
-    o = align256(o + 256 + std::max(hsad_threshold_workspace_bytes(n), (size_t)3 * 1024 * sizeof(double)));
+    o = align256(o + 256 + std::max({hsad_threshold_workspace_bytes(n), (size_t)3 * 1024 * sizeof(double),
+                                     (size_t)kSelMaxBlocks * 4 * sizeof(unsigned)}));
     L.gen = o;
     size_t g = hsad_workspace_bytes(HSAD_OP_LRX, H, W, Lp, p);
     g = std::max(g, generic_ws_per_pixel(Lp, GRAM_LRX) * (size_t)std::min<int64_t>(n, 8192));
@@ -893,7 +988,7 @@ int hsad_mlp_gradient(const uint16_t *X, int64_t nX, const float *tgt, const int
     if (int rc = grad_common("hsad_mlp_gradient", X, nX, tgt, rows, batch, Dp, params, wbf, ws, ws_bytes, stream))
         return rc;
     const int nwg = (int)((batch + 63) / 64);
-    hipLaunchKernelGGL(grad_sum_kernel, dim3(grid_for(mlp_nparams(Dp) + 1, 1024)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(grad_sum_kernel, dim3((unsigned)((mlp_nparams(Dp) + 64) / 64)), dim3(256), 0, stream,
                        (const float *)ws, nwg, Dp, 1.0f / (float)batch, grad);
     return check_launch("grad_sum_kernel");
 }
@@ -908,7 +1003,7 @@ int hsad_mlp_train_step(const uint16_t *X, int64_t nX, const float *tgt, const i
         return rc;
     const int nwg = (int)((batch + 63) / 64);
     const float b1c = (float)(1.0 - std::pow(0.9, (double)step)), b2c = (float)(1.0 - std::pow(0.999, (double)step));
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3(grid_for(mlp_nparams(Dp) + 1, 1024)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((unsigned)((mlp_nparams(Dp) + 64) / 64)), dim3(256), 0, stream,
                        (const float *)ws, nwg, Dp, params, adam_m, adam_v, wbf, lr, b1c, b2c,
                        1.0f / (float)batch, loss);
     return check_launch("mlp_adam_kernel");
@@ -929,19 +1024,37 @@ int hsad_error_stats(const float *yhat, const float *ref, int32_t ref_is_score, 
     return err_stats_launch(yhat, ref, ref_is_score, flags, flag_mask, n, out, ws, stream);
 }
 
+size_t hsad_surrogate_select_workspace_bytes(int64_t n)
+{
+    (void)n;
+    return (size_t)kSelMaxBlocks * 4 * sizeof(unsigned);
+}
+
 int hsad_surrogate_select(const float *yhat, int64_t n, const double *stats, double band, uint64_t seed,
-                          double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, hipStream_t stream)
+                          double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, void *ws,
+                          size_t ws_bytes, hipStream_t stream)
 {
     clear_error();
     if (!yhat || !stats || !flags || !idx || !counts || n < 1 || n > ((int64_t)1 << 31) - 1 || !(band >= 0.0) ||
         !(audit_frac >= 0.0 && audit_frac <= 1.0))
         return fail(HSAD_EINVAL, "hsad_surrogate_select: bad arguments");
+    if (!ws || ws_bytes < hsad_surrogate_select_workspace_bytes(n))
+        return fail(HSAD_ENOMEM, "hsad_surrogate_select: workspace too small");
     const double cut = std::ldexp(audit_frac, 32);
     const uint32_t audit_cut = cut >= 4294967295.0 ? 0xffffffffu : (uint32_t)cut;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, stream, (unsigned *)counts, 3, 0u);
-    hipLaunchKernelGGL(surr_select_kernel, dim3(grid_for(n)), dim3(256), 0, stream, yhat, n, stats, band, seed,
-                       audit_cut, flags, idx, (unsigned *)counts);
-    return check_launch("surr_select_kernel");
+    int64_t nb = (n + 255) / 256;
+    if (nb > kSelMaxBlocks) nb = kSelMaxBlocks;
+    int64_t seg = (n + nb - 1) / nb;
+    seg = (seg + 255) / 256 * 256;
+    nb = (n + seg - 1) / seg;
+    unsigned *bcnt = (unsigned *)ws, *boff = bcnt + 3 * kSelMaxBlocks;
+    hipLaunchKernelGGL(select_flags_kernel, dim3((unsigned)nb), dim3(256), 0, stream, yhat, n, stats, band, seed,
+                       audit_cut, seg, flags, bcnt);
+    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(1024), 0, stream, (const unsigned *)bcnt, (int)nb, boff,
+                       (unsigned *)counts);
+    hipLaunchKernelGGL(select_write_kernel, dim3((unsigned)nb), dim3(256), 0, stream, flags, n, seg,
+                       (const unsigned *)boff, idx);
+    return check_launch("hsad_surrogate_select");
 }
 
 int hsad_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
@@ -1009,7 +1122,7 @@ int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const h
         return rc;
     // near-threshold band + audit sample, then exact LRX there (overwrites those pixels)
     if ((rc = hsad_surrogate_select(yhat, n, dev_stats, opt->band_k * model->rmse_val, opt->seed, opt->audit_frac,
-                                    flags, idx, counts, stream)))
+                                    flags, idx, counts, ws_small, ws_small_bytes, stream)))
         return rc;
     uint32_t hc[3] = {0, 0, 0};
     if (hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, stream) != hipSuccess ||

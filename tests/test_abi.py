@@ -146,8 +146,9 @@ def test_surrogate_argument_errors():
                               None) == hs.HSAD_ENOMEM
     assert L.hsad_lrx_dwrx_at(FAKE, 8, 8, 14, ctypes.byref(p), idx, 0, FAKE, None, None, 0, None) == hs.HSAD_OK
     # selection
-    assert L.hsad_surrogate_select(FAKE, 10, FAKE, -1.0, 0, 0.01, FAKE, FAKE, FAKE, None) == hs.HSAD_EINVAL
-    assert L.hsad_surrogate_select(FAKE, 10, FAKE, 1.0, 0, 1.5, FAKE, FAKE, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_surrogate_select(FAKE, 10, FAKE, -1.0, 0, 0.01, FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    assert L.hsad_surrogate_select(FAKE, 10, FAKE, 1.0, 0, 1.5, FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    assert L.hsad_surrogate_select(FAKE, 10, FAKE, 1.0, 0, 0.5, FAKE, FAKE, FAKE, FAKE, 16, None) == hs.HSAD_ENOMEM
     # network entry points: Dp must be a multiple of 32 in 32..256
     assert L.hsad_mlp_infer(FAKE, 10, 48, FAKE, FAKE, FAKE, None) == hs.HSAD_EINVAL
     assert L.hsad_mlp_gradient(FAKE, 100, FAKE, FAKE, 64, 64, FAKE, FAKE, FAKE, FAKE, 10, None) == hs.HSAD_ENOMEM

@@ -39,24 +39,25 @@ def test_dwt_parity(H, W, L, levels):
     assert dwt_rel_err(got, ref) <= TOL
 
 
-@pytest.mark.parametrize("L,levels", [(224, 6), (224, 4), (189, 5), (131, 5)])
+@pytest.mark.parametrize("L,levels", [(224, 6), (224, 4), (189, 5), (131, 5), (224, 1), (224, 2), (224, 3),
+                                      (430, 2), (189, 3), (101, 2), (7, 1)])
 def test_dwt_equivalent_filter_and_cascade_agree(L, levels):
+    # every kernel that can serve a shape (forced), and the automatic choice
     print("dwt kernels", L, levels, flush=True)
     s = scene(77, 19, 23, L)
     ref = oracle.dwt_approx(s.cube, levels)
     L_ = hs.lib()
+    outs = {}
     try:
-        L_.hsad_internal_dwt_force(0)
-        casc = _gpu_dwt(s.cube, levels)
-        L_.hsad_internal_dwt_force(1)
-        eq = _gpu_dwt(s.cube, levels)
-        L_.hsad_internal_dwt_force(2)
-        lane = _gpu_dwt(s.cube, levels)
+        for mode, name in [(0, "cascade"), (1, "equiv_lds"), (2, "equiv_lane"), (3, "banded"), (-1, "auto")]:
+            L_.hsad_internal_dwt_force(mode)
+            outs[name] = _gpu_dwt(s.cube, levels)
     finally:
         L_.hsad_internal_dwt_force(-1)
-    assert dwt_rel_err(casc, ref) <= TOL
-    assert dwt_rel_err(eq, ref) <= TOL
-    assert dwt_rel_err(lane, ref) <= TOL
+    for name, got in outs.items():
+        e = dwt_rel_err(got, ref)
+        print("  ", name, e, flush=True)
+        assert e <= TOL, name
 
 
 @pytest.mark.parametrize("levels", [1, 2, 3, 4, 5, 6])
