@@ -110,6 +110,10 @@ size_t hsad_workspace_bytes(int op, int64_t H, int64_t W, int64_t Lp,
 /* LRX: eq. (1) with a local background, the annulus of the pixel.  For pixel r:
  * mu, C = mean and 1/n covariance of the annulus samples,
  * score = (r - mu)^T (C + lambda I)^-1 (r - mu).
+ * Exact precision (AUTO / FP64) computes the statistics in FP64: by sliding box sums for
+ * L' <= 8 (fused with the factorisation) and for L' <= 64 with outer <= 31 (per-pixel
+ * records in the workspace, then an FP64 Cholesky per pixel), otherwise by a per-pixel
+ * matrix-core FP64 Gram.  The FP32 / BF16 / FP16 precisions always use the Gram.
  *   x      : device, H*W*Lp float32 reduced (or full-band) cube
  *   scores : device, H*W float32
  *   ws     : device workspace of ws_bytes (may be NULL when hsad_workspace_bytes is 0)
@@ -245,8 +249,9 @@ int hsad_batch_plan_info(const hsad_batch_plan *plan, int64_t *info, int n);
  * Gram and the FP64 Cholesky.  Only lrx[idx[j]] / dwrx[idx[j]] are written; the rest of
  * the maps is left as it was.  Duplicates are allowed.  ws needs at least (L'+2) L' doubles; larger
  * workspaces process more pixels per chunk (up to 192 MiB worth).  precision must be
- * AUTO or FP64.  For L' > 8 the scores are bitwise those of hsad_lrx_dwrx.  Entries of
- * idx outside [0, H*W) are skipped.
+ * AUTO or FP64.  The statistics come from the per-pixel matrix-core Gram (the full-map
+ * calls may use sliding box sums instead; both are exact FP64 paths within the same
+ * tolerance).  Entries of idx outside [0, H*W) are skipped.
  * Errors: HSAD_EINVAL, HSAD_ENOMEM, HSAD_EHIP. */
 int hsad_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
                      const int32_t *idx, int64_t nidx, float *lrx, float *dwrx, void *ws, size_t ws_bytes,

@@ -134,6 +134,8 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_dwt_force", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_chunk", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_variant", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    ("hsad_internal_generic_force", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_boxg_resident_kb", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_gram", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.c_int, ctypes.c_int,
                                           _i64, ctypes.c_int, _vp, _vp]),
 ]

@@ -245,6 +245,12 @@ size_t hsad_workspace_bytes(int op, int64_t H, int64_t W, int64_t Lp,
     size_t want = per * npix;
     if (want > cap) want = (cap / per) * per;
     if (want < per) want = per;
+    if (op != HSAD_OP_DWEST && exact(p->precision) && boxg_supported(Lp, w)) {
+        // box-statistics path: whole bands of 16 image rows, as many as its chunk rule uses
+        const int64_t bands = boxg_chunk_bands(H, W, Lp, (size_t)-1 / 2);
+        const size_t bw = (size_t)bands * 16 * (size_t)W * boxg_record_doubles(Lp) * sizeof(double);
+        if (bw > want) want = bw;
+    }
     return want;
 }
 

@@ -31,6 +31,7 @@
 #include "dev_box.hpp"
 #include "dev_chol.hpp"
 #include "dev_dwt.hpp"
+#include "dev_boxg.hpp"
 #include "dev_gram.hpp"
 
 namespace hsad {
@@ -43,17 +44,17 @@ struct SceneDev {
     int H, W, L, levels, Lp, R, RI, has_inner;
     double load_rel;
     int dwt_P;         // pixels per DWT item
-    int bucket;        // 0: box, 1: gram
+    int bucket;        // 0: box (fused), 1: gram + Cholesky, 2: box statistics + Cholesky
     uint32_t outer_magic;
     int pad;
 };
 
 struct Item {          // generic item: scene + two integers + workspace offset (doubles)
     int scene;
-    int a;             // DWT: first pixel / box: tile row / gram: first pixel
-    int b;             // DWT: pixel count / box: tile col / gram: pixel count
-    int pad;
-    int64_t ws_off;    // gram / chol: offset of the (first) pixel block in the chunk ws
+    int a;             // DWT: first pixel / box, box statistics: tile row / gram: first pixel
+    int b;             // DWT: pixel count / box, box statistics: tile col / gram: pixel count
+    int raw;           // chol: 1 for a box-statistics record
+    int64_t ws_off;    // gram / box statistics / chol: offset of the (first) record in the chunk ws
 };
 
 static constexpr int kCounters = 16384;           // queue counters (uint32)
@@ -80,16 +81,20 @@ struct hsad_batch_plan {
     };
     struct Chunk {
         std::vector<GramLaunch> grams;
+        int64_t boxg_first, boxg_count;          // range in boxg_items
+        size_t boxg_smem;                        // LDS of the largest box-statistics tile
         int64_t chol_first, chol_count;          // range in chol_items
         int max_Lp;
     };
+    std::vector<hsad::Item> boxg_items;
+    int boxg_resident_kb = 0;                    // resident-staging budget the LDS sizes assume
     std::vector<hsad::Item> gram_items;
     std::vector<hsad::Item> chol_items;
     std::vector<Chunk> chunks;
     int64_t chunk_doubles = 0;
     hsad_batch_options opt;
     // workspace layout (bytes)
-    size_t off_scenes = 0, off_dwt = 0, off_box = 0, off_gram = 0, off_chol = 0, off_chunk = 0;
+    size_t off_scenes = 0, off_dwt = 0, off_box = 0, off_boxg = 0, off_gram = 0, off_chol = 0, off_chunk = 0;
     size_t total = 0;
     std::vector<size_t> box_off;                 // per bucket
     bool uploaded = false;
@@ -185,6 +190,67 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const SceneDev *__restr
     }
 }
 
+__global__ __launch_bounds__(256) void batch_boxg_kernel(const SceneDev *__restrict__ sc,
+                                                         const Item *__restrict__ items, int n,
+                                                         unsigned *ctr, double *chunk_ws, int resident_kb)
+{
+    extern __shared__ unsigned char bgs[];
+    __shared__ int slot;
+    for (;;) {
+        const int it = pop_item(ctr, &slot);
+        if (it >= n) break;
+        const Item m = items[it];
+        const SceneDev &s = sc[m.scene];
+        boxg_tile(s.approx, s.H, s.W, s.Lp, s.R, s.RI, s.has_inner, chunk_ws + m.ws_off, -1,
+                  (int64_t)(s.Lp + 3) * s.Lp, m.a, m.b, bgs, resident_kb);
+        __syncthreads();
+    }
+}
+
+// one wavefront per pixel item (L' <= 64), four wavefronts per workgroup; each wavefront
+// takes kCholGrab consecutive items per atomic
+static constexpr unsigned kCholGrab = 8;
+
+__global__ __launch_bounds__(256) void batch_chol_wave_kernel(const SceneDev *__restrict__ sc,
+                                                              const Item *__restrict__ items, int n,
+                                                              unsigned *ctr, double *chunk_ws, int lds_per_wave)
+{
+    extern __shared__ double cw[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *A = cw + (size_t)wv * lds_per_wave;
+    for (;;) {
+        unsigned it0 = 0;
+        if (lane == 0) it0 = atomicAdd(ctr, kCholGrab);
+        it0 = __shfl(it0, 0, 64);
+        if (it0 >= (unsigned)n) break;
+        const unsigned it1 = it0 + kCholGrab < (unsigned)n ? it0 + kCholGrab : (unsigned)n;
+        for (unsigned it = it0; it < it1; ++it) {
+            const Item m = items[it];
+            const SceneDev &s = sc[m.scene];
+            const int64_t p = m.a;
+            chol_wave_pixel(chunk_ws + m.ws_off, s.Lp, m.raw, s.load_rel, s.lrx ? s.lrx + p : nullptr,
+                            s.dwrx ? s.dwrx + p : nullptr, A);
+            wave_sync_lds();
+        }
+    }
+}
+
+// G lanes per pixel item (register-resident rows, L' + 2 <= G), 256 / G items per workgroup
+template <int G>
+__global__ __launch_bounds__(256) void batch_chol_group_kernel(const SceneDev *__restrict__ sc,
+                                                               const Item *__restrict__ items, int n,
+                                                               double *chunk_ws)
+{
+    const int it = (int)((blockIdx.x * 256 + threadIdx.x) / G);
+    const bool active = it < n;
+    const Item m = items[active ? it : 0];
+    const SceneDev &s = sc[m.scene];
+    const int64_t p = m.a;
+    __shared__ double colbuf[256];
+    chol_group_pixel<G>(chunk_ws + m.ws_off, s.Lp, m.raw, s.load_rel, active, s.lrx ? s.lrx + p : nullptr,
+                        s.dwrx ? s.dwrx + p : nullptr, colbuf + (threadIdx.x & ~(G - 1)));
+}
+
 __global__ __launch_bounds__(256) void batch_chol_kernel(const SceneDev *__restrict__ sc,
                                                          const Item *__restrict__ items, int n,
                                                          unsigned *ctr, double *chunk_ws)
@@ -198,7 +264,7 @@ __global__ __launch_bounds__(256) void batch_chol_kernel(const SceneDev *__restr
         const SceneDev &s = sc[m.scene];
         const int64_t p = m.a;
         chol_pixel(chunk_ws + m.ws_off, s.Lp, s.load_rel, s.lrx ? s.lrx + p : nullptr,
-                   s.dwrx ? s.dwrx + p : nullptr, sm);
+                   s.dwrx ? s.dwrx + p : nullptr, sm, m.raw);
     }
 }
 
@@ -313,7 +379,7 @@ int hsad_batch_plan_create(const hsad_scene *scenes, int n, const hsad_batch_opt
         }
         d.dwt_P = (int)dp;
         Windows w{p.inner, p.outer, p.inner / 2, p.outer / 2};
-        d.bucket = box_supported(Lp, w) ? 0 : 1;
+        d.bucket = box_supported(Lp, w) ? 0 : boxg_supported(Lp, w) ? 2 : 1;
         d.outer_magic = (uint32_t)((((uint64_t)1 << 32) + p.outer - 1) / p.outer);
         P->sdev.push_back(d);
         if (Lp > max_lp) max_lp = (int)Lp;
@@ -325,7 +391,10 @@ int hsad_batch_plan_create(const hsad_scene *scenes, int n, const hsad_batch_opt
         const SceneDev &d = P->sdev[i];
         const double np = (double)d.H * d.W;
         const double win = (2.0 * d.R + 1) * (2.0 * d.R + 1);
-        return np * (d.L + (d.bucket ? win * d.Lp * d.Lp / 16.0 : 0.0));
+        const double stats = d.bucket == 1 ? win * d.Lp * d.Lp / 16.0
+                             : d.bucket == 2 ? 40.0 * d.Lp * (d.Lp + 1) / 2.0 + d.Lp * d.Lp * d.Lp / 6.0
+                                             : 0.0;
+        return np * (d.L + stats);
     };
     std::sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
     for (int i : order) {
@@ -351,8 +420,12 @@ int hsad_batch_plan_create(const hsad_scene *scenes, int n, const hsad_batch_opt
         }
     }
     // gram chunks
+    P->boxg_resident_kb = boxg_resident_kb();
     const int64_t budget = P->opt.chunk_bytes / (int64_t)sizeof(double);
     hsad_batch_plan::Chunk cur;
+    cur.boxg_first = 0;
+    cur.boxg_count = 0;
+    cur.boxg_smem = 0;
     cur.chol_first = 0;
     cur.chol_count = 0;
     cur.max_Lp = 0;
@@ -376,11 +449,36 @@ int hsad_batch_plan_create(const hsad_scene *scenes, int n, const hsad_batch_opt
         P->chunks.push_back(cur);
         P->chunk_doubles = std::max<int64_t>(P->chunk_doubles, used);
         cur = hsad_batch_plan::Chunk();
+        cur.boxg_first = (int64_t)P->boxg_items.size();
+        cur.boxg_count = 0;
+        cur.boxg_smem = 0;
         cur.chol_first = (int64_t)P->chol_items.size();
         cur.chol_count = 0;
         cur.max_Lp = 0;
         used = 0;
     };
+    for (int i : order) {
+        const SceneDev &d = P->sdev[i];
+        if (d.bucket != 2) continue;
+        const int64_t per = (int64_t)(d.Lp + 3) * d.Lp, tile = per * 256;
+        const int nby = (d.H + 15) / 16, nbx = (d.W + 15) / 16;
+        for (int by = 0; by < nby; ++by)
+            for (int bx = 0; bx < nbx; ++bx) {
+                if (used + tile > budget) flush();
+                P->boxg_items.push_back(Item{i, by, bx, 0, used});
+                ++cur.boxg_count;
+                cur.boxg_smem = std::max(cur.boxg_smem, bg_smem_bytes(d.Lp, d.R, boxg_resident_kb()));
+                for (int ty = 0; ty < 16; ++ty)
+                    for (int tx = 0; tx < 16; ++tx) {
+                        const int py = by * 16 + ty, px = bx * 16 + tx;
+                        if (py >= d.H || px >= d.W) continue;
+                        P->chol_items.push_back(Item{i, py * d.W + px, 1, 1, used + per * (ty * 16 + tx)});
+                        ++cur.chol_count;
+                    }
+                cur.max_Lp = std::max(cur.max_Lp, d.Lp);
+                used += tile;
+            }
+    }
     for (int i : order) {
         const SceneDev &d = P->sdev[i];
         if (d.bucket != 1) continue;
@@ -399,7 +497,7 @@ int hsad_batch_plan_create(const hsad_scene *scenes, int n, const hsad_batch_opt
         }
     }
     flush();
-    if ((int)P->chunks.size() * 6 + (int)P->box.size() + 1 > kCounters) {
+    if ((int)P->chunks.size() * 7 + (int)P->box.size() + 1 > kCounters) {
         delete P;
         return fail(HSAD_EUNSUPPORTED, "hsad_batch_plan_create: too many chunks; raise chunk_bytes");
     }
@@ -413,6 +511,8 @@ int hsad_batch_plan_create(const hsad_scene *scenes, int n, const hsad_batch_opt
         P->box_off.push_back(off);
         off = align_up(off + b.second.size() * sizeof(Item), 256);
     }
+    P->off_boxg = off;
+    off = align_up(off + P->boxg_items.size() * sizeof(Item), 256);
     P->off_gram = off;
     off = align_up(off + P->gram_items.size() * sizeof(Item), 256);
     P->off_chol = off;
@@ -437,6 +537,8 @@ int hsad_batch_upload(hsad_batch_plan *P, void *ws, size_t ws_bytes, hipStream_t
     for (size_t b = 0; b < P->box.size(); ++b)
         std::memcpy(host.data() + P->box_off[b], P->box[b].second.data(),
                     P->box[b].second.size() * sizeof(Item));
+    if (!P->boxg_items.empty())
+        std::memcpy(host.data() + P->off_boxg, P->boxg_items.data(), P->boxg_items.size() * sizeof(Item));
     if (!P->gram_items.empty())
         std::memcpy(host.data() + P->off_gram, P->gram_items.data(), P->gram_items.size() * sizeof(Item));
     if (!P->chol_items.empty())
@@ -495,9 +597,18 @@ int hsad_batch_run(const hsad_batch_plan *P, void *ws, hipStream_t s)
         if (int rc = check_launch("batch_box_kernel")) return rc;
     }
     double *chunk_ws = (double *)(base + P->off_chunk);
+    const Item *bgi = (const Item *)(base + P->off_boxg);
     const Item *gi = (const Item *)(base + P->off_gram);
     const Item *ci = (const Item *)(base + P->off_chol);
     for (const auto &ch : P->chunks) {
+        if (ch.boxg_count > 0) {
+            if (int rc = allow_lds((const void *)batch_boxg_kernel, ch.boxg_smem, "batch_boxg_kernel")) return rc;
+            int g2 = (int)std::min<int64_t>(grid, ch.boxg_count);
+            hipLaunchKernelGGL(batch_boxg_kernel, dim3(g2), dim3(256), ch.boxg_smem, s, sc, bgi + ch.boxg_first,
+                               (int)ch.boxg_count, ctr + c, chunk_ws, P->boxg_resident_kb);
+            ++c;
+            if (int rc = check_launch("batch_boxg_kernel")) return rc;
+        }
         for (const auto &g : ch.grams) {
             const size_t sh = (size_t)g.lds_doubles_per_wave * 4 * sizeof(double);
             const int n = (int)g.count;
@@ -519,13 +630,34 @@ int hsad_batch_run(const hsad_batch_plan *P, void *ws, hipStream_t s)
             ++c;
             if (int rc = check_launch("batch_gram_kernel")) return rc;
         }
-        const size_t sh = chol_smem_doubles(ch.max_Lp) * sizeof(double);
-        const int nt = ch.max_Lp <= 32 ? 64 : 256;
-        if (int rc = allow_lds((const void *)batch_chol_kernel, sh, "batch_chol_kernel")) return rc;
-        hipLaunchKernelGGL(batch_chol_kernel, dim3(grid * (nt == 64 ? 4 : 1)), dim3(nt), sh, s, sc,
-                           ci + ch.chol_first, (int)ch.chol_count, ctr + c, chunk_ws);
-        ++c;
-        if (int rc = check_launch("batch_chol_kernel")) return rc;
+        if (ch.max_Lp + 2 <= 64) {
+            const int G = ch.max_Lp + 2 <= 16 ? 16 : ch.max_Lp + 2 <= 32 ? 32 : 64;
+            const int n = (int)ch.chol_count;
+            dim3 g2((unsigned)(((int64_t)n * G + 255) / 256));
+            if (G == 16)
+                hipLaunchKernelGGL(batch_chol_group_kernel<16>, g2, dim3(256), 0, s, sc, ci + ch.chol_first, n, chunk_ws);
+            else if (G == 32)
+                hipLaunchKernelGGL(batch_chol_group_kernel<32>, g2, dim3(256), 0, s, sc, ci + ch.chol_first, n, chunk_ws);
+            else
+                hipLaunchKernelGGL(batch_chol_group_kernel<64>, g2, dim3(256), 0, s, sc, ci + ch.chol_first, n, chunk_ws);
+            if (int rc = check_launch("batch_chol_group_kernel")) return rc;
+        } else if (ch.max_Lp <= 64) {
+            const int per_wave = (int)chol_wave_lds_doubles(ch.max_Lp);
+            const size_t sh = (size_t)4 * per_wave * sizeof(double);
+            if (int rc = allow_lds((const void *)batch_chol_wave_kernel, sh, "batch_chol_wave_kernel")) return rc;
+            hipLaunchKernelGGL(batch_chol_wave_kernel, dim3(grid * 2), dim3(256), sh, s, sc, ci + ch.chol_first,
+                               (int)ch.chol_count, ctr + c, chunk_ws, per_wave);
+            ++c;
+            if (int rc = check_launch("batch_chol_wave_kernel")) return rc;
+        } else {
+            const size_t sh = chol_smem_doubles(ch.max_Lp) * sizeof(double);
+            const int nt = ch.max_Lp <= 32 ? 64 : 256;
+            if (int rc = allow_lds((const void *)batch_chol_kernel, sh, "batch_chol_kernel")) return rc;
+            hipLaunchKernelGGL(batch_chol_kernel, dim3(grid * (nt == 64 ? 4 : 1)), dim3(nt), sh, s, sc,
+                               ci + ch.chol_first, (int)ch.chol_count, ctr + c, chunk_ws);
+            ++c;
+            if (int rc = check_launch("batch_chol_kernel")) return rc;
+        }
     }
     return HSAD_OK;
 }
@@ -543,7 +675,7 @@ int hsad_batch_plan_info(const hsad_batch_plan *P, int64_t *info, int n)
     for (const auto &d : P->sdev) {
         const int64_t np = (int64_t)d.H * d.W;
         npix += np;
-        (d.bucket ? gram_px : box_px) += np;
+        (d.bucket != 0 ? gram_px : box_px) += np;
     }
     int64_t box_items = 0;
     for (const auto &b : P->box) box_items += (int64_t)b.second.size();

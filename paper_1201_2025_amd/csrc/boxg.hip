@@ -1,0 +1,53 @@
+// boxg.hip -- launcher of the sliding-box window statistics for mid-size L' (dev_boxg.hpp):
+// one workgroup per 16 x 16 tile of a band of tile rows, raw records into the chunk
+// workspace, finalised and factorised by the Cholesky kernel.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "dev_boxg.hpp"
+
+namespace hsad {
+
+__global__ __launch_bounds__(BG_NT) void boxg_kernel(const float *__restrict__ x, int H, int W, int Lp, int R, int RI,
+                                                     int has_inner, int tile_row0, double *__restrict__ rec,
+                                                     int64_t pix0, int64_t rec_stride, int resident_kb)
+{
+    extern __shared__ unsigned char bg_smem[];
+    boxg_tile(x, H, W, Lp, R, RI, has_inner, rec, pix0, rec_stride, tile_row0 + (int)blockIdx.y, (int)blockIdx.x,
+              bg_smem, resident_kb);
+}
+
+// LDS budget (KiB) under which a tile keeps all its bands resident; tunable for tests
+static int g_boxg_resident_kb = 156;
+int boxg_resident_kb() { return g_boxg_resident_kb; }
+
+bool boxg_supported(int64_t Lp, const Windows &w)
+{
+    return Lp >= 2 && Lp <= BG_MAX_LP && w.ro <= BG_MAX_R &&
+           bg_smem_bytes((int)Lp, w.ro, g_boxg_resident_kb) <= 160 * 1024;
+}
+
+size_t boxg_record_doubles(int64_t Lp) { return (size_t)((Lp + 3) * Lp); }
+
+// Records for the tile rows [tile_row0, tile_row0 + ntile_rows) into rec; record of pixel p
+// at rec + (p - tile_row0 * 16 * W) * (L'+3) L'.
+int boxg_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, int tile_row0, int ntile_rows,
+                double *rec, hipStream_t s)
+{
+    const size_t sh = bg_smem_bytes((int)Lp, w.ro, g_boxg_resident_kb);
+    if (int rc = allow_lds((const void *)boxg_kernel, sh, "boxg_kernel")) return rc;
+    dim3 grid((unsigned)((W + BG_TX - 1) / BG_TX), (unsigned)ntile_rows);
+    const int64_t pix0 = (int64_t)tile_row0 * BG_TY * W;
+    hipLaunchKernelGGL(boxg_kernel, grid, dim3(BG_NT), sh, s, x, (int)H, (int)W, (int)Lp, w.ro, w.ri,
+                       w.inner > 0 ? 1 : 0, tile_row0, rec, pix0, (int64_t)boxg_record_doubles(Lp),
+                       g_boxg_resident_kb);
+    return check_launch("boxg_kernel");
+}
+
+}  // namespace hsad
+
+extern "C" int hsad_internal_boxg_resident_kb(int kb)
+{
+    hsad::g_boxg_resident_kb = kb < 0 ? 0 : kb > 156 ? 156 : kb;
+    return 0;
+}

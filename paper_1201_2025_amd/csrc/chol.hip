@@ -24,27 +24,86 @@ __global__ __launch_bounds__(256) void chol_rx_kernel(double *__restrict__ ws, i
                                                       int64_t pix0, double load_rel,
                                                       float *__restrict__ lrx,
                                                       float *__restrict__ dwrx,
-                                                      const int32_t *__restrict__ idx, int64_t npix_img)
+                                                      const int32_t *__restrict__ idx, int64_t npix_img,
+                                                      int raw, int64_t stride)
 {
     extern __shared__ double sm[];
     const int local = blockIdx.x;
     if (local >= npix) return;
     const int64_t p = idx ? (int64_t)idx[pix0 + local] : pix0 + local;
     if (p < 0 || p >= npix_img) return;   // listed index outside the image: skipped
-    chol_pixel(ws + (size_t)local * (Lp + 2) * Lp, Lp, load_rel, lrx ? lrx + p : nullptr,
-               dwrx ? dwrx + p : nullptr, sm);
+    chol_pixel(ws + (size_t)local * stride, Lp, load_rel, lrx ? lrx + p : nullptr, dwrx ? dwrx + p : nullptr, sm,
+               raw);
+}
+
+// one wavefront per pixel (L' <= 64), four pixels per workgroup
+__global__ __launch_bounds__(256) void chol_wave_kernel(const double *__restrict__ ws, int Lp, int npix, int64_t pix0,
+                                                        double load_rel, float *__restrict__ lrx,
+                                                        float *__restrict__ dwrx, const int32_t *__restrict__ idx,
+                                                        int64_t npix_img, int raw, int64_t stride)
+{
+    extern __shared__ double smw[];
+    const int wv = threadIdx.x >> 6;
+    const int local = blockIdx.x * 4 + wv;
+    if (local >= npix) return;
+    const int64_t p = idx ? (int64_t)idx[pix0 + local] : pix0 + local;
+    if (p < 0 || p >= npix_img) return;   // listed index outside the image: skipped
+    chol_wave_pixel(ws + (size_t)local * stride, Lp, raw, load_rel, lrx ? lrx + p : nullptr,
+                    dwrx ? dwrx + p : nullptr, smw + (size_t)wv * chol_wave_lds_doubles(Lp));
+}
+
+// G lanes per pixel (register-resident rows), 256 / G pixels per workgroup
+template <int G>
+__global__ __launch_bounds__(256) void chol_group_kernel(const double *__restrict__ ws, int Lp, int npix, int64_t pix0,
+                                                         double load_rel, float *__restrict__ lrx,
+                                                         float *__restrict__ dwrx, const int32_t *__restrict__ idx,
+                                                         int64_t npix_img, int raw, int64_t stride)
+{
+    const int local = (int)((blockIdx.x * 256 + threadIdx.x) / G);
+    bool active = local < npix;
+    int64_t p = 0;
+    if (active) {
+        p = idx ? (int64_t)idx[pix0 + local] : pix0 + local;
+        active = p >= 0 && p < npix_img;    // listed index outside the image: skipped
+    }
+    __shared__ double colbuf[256];
+    chol_group_pixel<G>(ws + (size_t)(active ? local : 0) * stride, Lp, raw, load_rel, active,
+                        lrx ? lrx + p : nullptr, dwrx ? dwrx + p : nullptr,
+                        colbuf + (threadIdx.x & ~(G - 1)));
 }
 
 size_t chol_smem(int64_t Lp) { return chol_smem_doubles((int)Lp) * sizeof(double); }
 
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
-                float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img)
+                float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img, int raw)
 {
+    const int64_t stride = raw ? (Lp + 3) * Lp : (Lp + 2) * Lp;
+    if (Lp + 2 <= 64) {
+        const int G = Lp + 2 <= 16 ? 16 : Lp + 2 <= 32 ? 32 : 64;
+        dim3 grid((unsigned)(((int64_t)npix * G + 255) / 256));
+        if (G == 16)
+            hipLaunchKernelGGL(chol_group_kernel<16>, grid, dim3(256), 0, s, ws, (int)Lp, npix, pix0, load_rel, lrx,
+                               dwrx, idx, npix_img, raw, stride);
+        else if (G == 32)
+            hipLaunchKernelGGL(chol_group_kernel<32>, grid, dim3(256), 0, s, ws, (int)Lp, npix, pix0, load_rel, lrx,
+                               dwrx, idx, npix_img, raw, stride);
+        else
+            hipLaunchKernelGGL(chol_group_kernel<64>, grid, dim3(256), 0, s, ws, (int)Lp, npix, pix0, load_rel, lrx,
+                               dwrx, idx, npix_img, raw, stride);
+        return check_launch("chol_group_kernel");
+    }
+    if (Lp <= 64) {
+        const size_t shw = 4 * chol_wave_lds_doubles((int)Lp) * sizeof(double);
+        if (int rc = allow_lds((const void *)chol_wave_kernel, shw, "chol_wave_kernel")) return rc;
+        hipLaunchKernelGGL(chol_wave_kernel, dim3((unsigned)((npix + 3) / 4)), dim3(256), shw, s, ws, (int)Lp, npix,
+                           pix0, load_rel, lrx, dwrx, idx, npix_img, raw, stride);
+        return check_launch("chol_wave_kernel");
+    }
     const size_t sh = chol_smem(Lp);
     const int nt = Lp <= 32 ? 64 : 256;
     if (int rc = allow_lds((const void *)chol_rx_kernel, sh, "chol_rx_kernel")) return rc;
     hipLaunchKernelGGL(chol_rx_kernel, dim3((unsigned)npix), dim3(nt), sh, s, ws, (int)Lp, npix,
-                       pix0, load_rel, lrx, dwrx, idx, npix_img);
+                       pix0, load_rel, lrx, dwrx, idx, npix_img, raw, stride);
     return check_launch("chol_rx_kernel");
 }
 

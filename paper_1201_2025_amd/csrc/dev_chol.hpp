@@ -25,14 +25,25 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 // Factorises one pixel's trapezoid A ((L'+2) x L', FP64) in place and writes the two
 // scores to *lrx_out / *dwrx_out (either may be NULL).  Whole workgroup; sm holds
 // chol_smem_doubles(L') doubles.
+// raw != 0: A is a box-statistics record (dev_boxg.hpp): the upper triangle holds the
+// second moments R and row L'+2 the mean mu_f; the covariance C = R - mu_f mu_f^T is
+// formed in the lower triangle first.
 __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_rel,
-                                  float *lrx_out, float *dwrx_out, double *sm)
+                                  float *lrx_out, float *dwrx_out, double *sm, int raw = 0)
 {
     const int rows = Lp + 2;
     double *panel = sm;                        // rows x NB (row stride NB+1)
     double *red = sm + (size_t)rows * (NB + 1);
     double &bad = red[6];                      // 0/1 flag shared by the workgroup
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (raw) {
+        const double *mu = A + (size_t)(Lp + 2) * Lp;
+        for (int t = tid; t < Lp * Lp; t += nt) {
+            const int i = t / Lp, j = t - i * Lp;
+            if (j >= i) A[(size_t)j * Lp + i] = A[(size_t)i * Lp + j] - mu[i] * mu[j];
+        }
+        __syncthreads();
+    }
 
     // trace -> loading
     double tr = 0.0;
@@ -135,5 +146,176 @@ __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_re
 
 
 __host__ __device__ inline size_t chol_smem_doubles(int Lp) { return (size_t)(Lp + 2) * (NB + 1) + 8; }
+
+}  // namespace hsad
+
+namespace hsad {
+
+// ------------------------------------------------------------------------------------
+// One wavefront per pixel, L' <= 64: the record is copied once into LDS with coalesced
+// loads, then (raw records) C = R - mu mu^T, the loading, the unblocked right-looking
+// Cholesky of the (L'+2) x L' trapezoid and the two squared norms run there, with wave
+// barriers only.  Same definitions and operation order per column as chol_pixel's single
+// panel.  lds holds chol_wave_lds_doubles(L') doubles for this wavefront.
+// ------------------------------------------------------------------------------------
+__host__ __device__ inline int chol_wave_lda(int Lp) { return Lp | 1; }
+__host__ __device__ inline size_t chol_wave_lds_doubles(int Lp)
+{
+    return (size_t)(Lp + 2) * chol_wave_lda(Lp) + (size_t)Lp;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline void chol_wave_pixel(const double *__restrict__ rec, int Lp, int raw, double load_rel,
+                                       float *lrx_out, float *dwrx_out, double *A)
+{
+    const int lane = threadIdx.x & 63;
+    const int lda = chol_wave_lda(Lp), rows = Lp + 2;
+    double *mu = A + (size_t)rows * lda;
+    for (int t = lane; t < rows * Lp; t += 64) {
+        const int r = t / Lp, c = t - r * Lp;
+        A[r * lda + c] = rec[t];
+    }
+    if (raw)
+        for (int c = lane; c < Lp; c += 64) mu[c] = rec[(size_t)rows * Lp + c];
+    wave_sync_lds();
+    if (raw) {
+        for (int t = lane; t < Lp * Lp; t += 64) {
+            const int i = t / Lp, j = t - i * Lp;
+            if (j >= i) A[j * lda + i] = A[i * lda + j] - mu[i] * mu[j];
+        }
+        wave_sync_lds();
+    }
+    double tr = 0.0;
+    for (int i = lane; i < Lp; i += 64) tr += A[i * lda + i];
+    tr = wave_sum_d(tr);
+    double lam = load_rel * tr / (double)Lp;
+    lam = lam < 1e-30 ? 1e-30 : lam;
+    for (int i = lane; i < Lp; i += 64) A[i * lda + i] += lam;
+    wave_sync_lds();
+    bool bad = false;
+    for (int j = 0; j < Lp; ++j) {
+        const double d = A[j * lda + j];
+        bad = bad || !(d > 0.0);
+        const double inv = 1.0 / sqrt(d);
+        wave_sync_lds();
+        for (int r = j + lane; r < rows; r += 64) A[r * lda + j] *= inv;
+        wave_sync_lds();
+        const int ncol = Lp - j - 1, nrow = rows - j - 1;
+        if (ncol > 0) {
+            // t / ncol by a multiply-high; ceil(2^32 / ncol) fits 32 bits only for ncol >= 2
+            const uint32_t magic =
+                ncol > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)ncol - 1) / (uint64_t)ncol) : 0u;
+            for (int t = lane; t < nrow * ncol; t += 64) {
+                const int q = ncol > 1 ? (int)__umulhi((uint32_t)t, magic) : t;
+                const int r = j + 1 + q, c = j + 1 + (t - q * ncol);
+                if (c <= r) A[r * lda + c] -= A[r * lda + j] * A[c * lda + j];
+            }
+        }
+        wave_sync_lds();
+    }
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = lane; k < Lp; k += 64) {
+        const double a = A[Lp * lda + k], b = A[(Lp + 1) * lda + k];
+        s1 += a * a;
+        s2 += b * b;
+    }
+    s1 = wave_sum_d(s1);
+    s2 = wave_sum_d(s2);
+    if (lane == 0) {
+        if (lrx_out) *lrx_out = bad ? INFINITY : (float)s1;
+        if (dwrx_out) *dwrx_out = bad ? INFINITY : (float)s2;
+    }
+}
+
+}  // namespace hsad
+
+namespace hsad {
+
+// ------------------------------------------------------------------------------------
+// Register-resident Cholesky: a group of G lanes (G = 16, 32 or 64; 64/G pixels per
+// wavefront) owns one pixel, lane r of the group holds row r of the (L'+2) x L' trapezoid
+// (its lower part) in registers, L' + 2 <= G.  Column j: the pivot comes from lane j,
+// each lane scales its element j and publishes it in the group's LDS column buffer, and
+// the rank-1 update of column c reads l_cj there (a broadcast read).  Same operations in
+// the same order per column as the unblocked factorisation of chol_pixel (loading added
+// before factorising).  All indices into the register row are compile-time constants
+// (loops over the G - 2 columns are unrolled; columns past L' are skipped by uniform
+// branches).  rec is the record of the pixel ((L'+2) x L' for Gram records, (L'+3) x L'
+// for raw box-statistics records); col is this lane's group's G-double LDS buffer.
+// ------------------------------------------------------------------------------------
+template <int G>
+__device__ inline void chol_group_pixel(const double *__restrict__ rec, int Lp, int raw, double load_rel,
+                                        bool active, float *lrx_out, float *dwrx_out, double *col)
+{
+    constexpr int CM = G - 2;                  // largest L' of this group size
+    const int lane = threadIdx.x & 63, r = lane & (G - 1), base = lane & ~(G - 1);
+    const bool row_in = active && r < Lp + 2;
+    double mur = 0.0;
+    if (raw && active && r < Lp) mur = rec[(size_t)(Lp + 2) * Lp + r];
+    // diagonal for the trace (rows < L')
+    double diag = 0.0;
+    if (active && r < Lp) diag = raw ? rec[(size_t)r * Lp + r] - mur * mur : rec[(size_t)r * Lp + r];
+    double tr = diag;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) tr += __shfl_xor(tr, o, 64);
+    double lam = load_rel * tr / (double)Lp;
+    lam = lam < 1e-30 ? 1e-30 : lam;
+    // row r: lower part (c <= r) of C + lam I, or the d / m rows (r = L', L'+1)
+    double A[CM];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+        double v = 0.0;
+        if (row_in && c < Lp && (c <= r || r >= Lp)) {
+            if (r >= Lp) v = rec[(size_t)r * Lp + c];
+            else if (raw) v = rec[(size_t)c * Lp + r] - rec[(size_t)(Lp + 2) * Lp + c] * mur;
+            else v = rec[(size_t)r * Lp + c];
+            if (c == r) v += lam;
+        }
+        A[c] = v;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < CM; ++j) {
+        if (j < Lp) {
+            const double d = __shfl(A[j], base + j, 64);
+            bad = bad || !(d > 0.0);
+            const double inv = 1.0 / sqrt(d);
+            const double l = A[j] * inv;
+            if (r >= j) A[j] = l;
+            col[r] = l;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+            for (int c = j + 1; c < CM; ++c) {
+                if (c < Lp) {
+                    const double lc = col[c];
+                    if (r >= c) A[c] -= l * lc;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < CM; ++c)
+        if (c < Lp) s += A[c] * A[c];
+    if (active && r == Lp && lrx_out) *lrx_out = bad ? INFINITY : (float)s;
+    if (active && r == Lp + 1 && dwrx_out) *dwrx_out = bad ? INFINITY : (float)s;
+}
 
 }  // namespace hsad

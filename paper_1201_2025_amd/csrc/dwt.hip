@@ -406,6 +406,7 @@ __global__ __launch_bounds__(256) void dwt_banded_kernel(const float *__restrict
     dwt_banded_tile<VEC>(cube, p0, np, L, Lp, W, coef, start, magic_L, magic_Lp, out, ldsf, P);
 }
 
+// ceil(2^32 / d) for d >= 2 (the banded path has L >= L' >= 2 whenever it runs)
 static uint32_t magic_u32(int64_t d) { return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d); }
 
 // Pixels per banded tile: at most 32 and as many as fit 40 KiB of LDS, so that four
@@ -488,7 +489,7 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
     BandedCoefs bc;
     int bP = 0;
     if (g_dwt_force != 0 && g_dwt_force != 1 && g_dwt_force != 2 && L < 8192 &&
-        banded_coefs(L, levels, Lp, 128, s, &bc) && (bP = banded_pixels(L, Lp, bc.W)) >= 4) {
+        Lp >= 2 && banded_coefs(L, levels, Lp, 128, s, &bc) && (bP = banded_pixels(L, Lp, bc.W)) >= 4) {
         const size_t sh = (size_t)dwt_banded_lds_floats(L, Lp, bc.W, bP) * sizeof(float);
         const void *kern = (L % 4 == 0) ? (const void *)dwt_banded_kernel<4> : (const void *)dwt_banded_kernel<1>;
         if (int rc = allow_lds(kern, sh, "dwt_banded_kernel")) return rc;

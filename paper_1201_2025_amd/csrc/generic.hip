@@ -13,7 +13,9 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
                 const int32_t *idx = nullptr);
 size_t chol_smem(int64_t Lp);
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
-                float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img);
+                float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img, int raw);
+int boxg_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, int tile_row0, int ntile_rows,
+                double *rec, hipStream_t s);
 size_t jacobi_smem(int64_t n);
 int jacobi_launch(const double *ws, int64_t n, int npix, int64_t pix0, float *score,
                   float *literal, int32_t *npos, hipStream_t s);
@@ -39,10 +41,45 @@ static int64_t chunk_pixels(int64_t total, int64_t Lp, size_t ws_bytes)
     return P;
 }
 
+// Tile-row bands per chunk of the box-statistics path: as many as the workspace holds, at
+// most what keeps ~4096 tiles (16 per CU) in flight, within 8 GiB of records.
+int64_t boxg_chunk_bands(int64_t H, int64_t W, int64_t Lp, size_t ws_bytes)
+{
+    const int64_t band_bytes = (int64_t)(boxg_record_doubles(Lp) * sizeof(double)) * 16 * W;
+    const int64_t total = (H + 15) / 16, tiles_per_band = (W + 15) / 16;
+    int64_t want = (4096 + tiles_per_band - 1) / tiles_per_band;
+    const int64_t cap = ((int64_t)8 << 30) / band_bytes;
+    if (want > cap) want = cap > 1 ? cap : 1;
+    if (want > total) want = total;
+    int64_t fit = (int64_t)(ws_bytes / (size_t)band_bytes);
+    return fit < want ? fit : want;
+}
+
+// -1 automatic, 1 matrix-core Gram only (tests compare the two statistics paths)
+static int g_generic_force = -1;
+
 int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                      double load_rel, GramPrec prec, float *lrx, float *dwrx, void *ws,
                      size_t ws_bytes, hipStream_t s)
 {
+    // exact statistics by sliding box sums when they fit (raw records, finalised by the
+    // Cholesky kernel); otherwise the per-pixel matrix-core Gram
+    if (prec == GP_FP64 && g_generic_force != 1 && boxg_supported(Lp, w)) {
+        const int64_t bands = boxg_chunk_bands(H, W, Lp, ws_bytes);
+        if (bands >= 1) {
+            const int64_t total = (H + 15) / 16;
+            for (int64_t b0 = 0; b0 < total; b0 += bands) {
+                const int64_t nb = total - b0 < bands ? total - b0 : bands;
+                int rc = boxg_launch(x, H, W, Lp, w, (int)b0, (int)nb, (double *)ws, s);
+                if (rc) return rc;
+                const int64_t y1 = (b0 + nb) * 16 < H ? (b0 + nb) * 16 : H;
+                const int64_t p0 = b0 * 16 * W, n = y1 * W - p0;
+                rc = chol_launch((double *)ws, Lp, (int)n, p0, load_rel, lrx, dwrx, s, nullptr, H * W, 1);
+                if (rc) return rc;
+            }
+            return HSAD_OK;
+        }
+    }
     if (gram_lds_per_wave(Lp, prec) > 160 * 1024 || chol_smem(Lp) > 160 * 1024)
         return fail(HSAD_EUNSUPPORTED, "generic path: L' too large");
     const int64_t total = H * W;
@@ -52,7 +89,7 @@ int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Win
         const int n = (int)((total - p0) < P ? (total - p0) : P);
         int rc = gram_launch(x, H, W, Lp, w, GRAM_LRX, prec, p0, n, (double *)ws, s);
         if (rc) return rc;
-        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s, nullptr, H * W);
+        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s, nullptr, H * W, 0);
         if (rc) return rc;
     }
     return HSAD_OK;
@@ -71,7 +108,7 @@ int generic_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const 
         const int n = (int)((nidx - p0) < P ? (nidx - p0) : P);
         int rc = gram_launch(x, H, W, Lp, w, GRAM_LRX, prec, p0, n, (double *)ws, s, idx);
         if (rc) return rc;
-        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s, idx, H * W);
+        rc = chol_launch((double *)ws, Lp, n, p0, load_rel, lrx, dwrx, s, idx, H * W, 0);
         if (rc) return rc;
     }
     return HSAD_OK;
@@ -109,4 +146,10 @@ extern "C" int hsad_internal_gram(const float *x, int64_t H, int64_t W, int64_t 
         return fail(HSAD_EINVAL, "hsad_internal_gram: bad arguments");
     Windows w{p->inner, p->outer, p->inner / 2, p->outer / 2};
     return gram_launch(x, H, W, Lp, w, mode, prec, pix0, npix, ws, s);
+}
+
+extern "C" int hsad_internal_generic_force(int mode)
+{
+    hsad::g_generic_force = mode;
+    return 0;
 }

@@ -41,6 +41,12 @@ bool box_supported(int64_t Lp, const Windows &w);
 int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                         double load_rel, float *lrx, float *dwrx, hipStream_t s);
 
+// ---- box-sum statistics for mid-size L' (boxg.hip) ----
+bool boxg_supported(int64_t Lp, const Windows &w);
+size_t boxg_record_doubles(int64_t Lp);
+int64_t boxg_chunk_bands(int64_t H, int64_t W, int64_t Lp, size_t ws_bytes);
+int boxg_resident_kb();
+
 // ---- generic Gram + factorisation path (gram.hip, chol.hip, jacobi.hip) ----
 enum GramMode { GRAM_LRX = 0, GRAM_DWEST = 1 };
 enum GramPrec { GP_FP64 = 0, GP_FP32 = 1, GP_BF16 = 2, GP_FP16 = 3 };

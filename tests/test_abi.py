@@ -108,8 +108,12 @@ def test_workspace_sizes():
     p = _p(5, 15)
     # box path (exact, L' <= 8) needs none; the generic path needs (L'+2) L' doubles/pixel
     assert L.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, 512, 512, 4, ctypes.byref(p)) == 0
+    # L' = 14 with outer 15: box statistics, (L'+3) L' doubles per pixel for whole bands of 16 rows
     n = L.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, 64, 64, 14, ctypes.byref(p))
-    assert n == 64 * 64 * 16 * 14 * 8
+    assert n == 64 * 64 * 17 * 14 * 8
+    # outside the box-statistics range (outer 33): the Gram path's (L'+2) L' doubles per pixel
+    p33 = _p(5, 33)
+    assert L.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, 64, 64, 14, ctypes.byref(p33)) == 64 * 64 * 16 * 14 * 8
     big = L.hsad_workspace_bytes(hs.HSAD_OP_LRX, 512, 512, 224, ctypes.byref(p))
     assert 0 < big <= (1 << 30) and big % (226 * 224 * 8) == 0
     pb = _p(5, 15, prec=hs.HSAD_PREC_GRAM_BF16)

@@ -15,14 +15,16 @@ pytestmark = pytest.mark.gpu
 
 
 def _specs():
-    # a small uneven batch: box (L' <= 8) and Gram buckets, odd L, ragged sizes
+    # a small uneven batch: the fused box bucket (L' <= 8), the box-statistics bucket
+    # (L' <= 64, outer <= 31) and the Gram bucket; odd L, ragged sizes
     return [
         dict(seed=1, H=37, W=29, L=224, levels=6, inner=5, outer=15),    # L' = 4 (box)
         dict(seed=2, H=20, W=41, L=189, levels=5, inner=3, outer=13),    # L' = 6 (box)
-        dict(seed=3, H=19, W=23, L=131, levels=3, inner=3, outer=9),     # L' = 17 (gram)
-        dict(seed=4, H=24, W=17, L=224, levels=4, inner=5, outer=11),    # L' = 14 (gram)
+        dict(seed=3, H=19, W=23, L=131, levels=3, inner=3, outer=9),     # L' = 17 (box statistics)
+        dict(seed=4, H=24, W=17, L=224, levels=4, inner=5, outer=11),    # L' = 14 (box statistics)
         dict(seed=5, H=9, W=33, L=430, levels=2, inner=7, outer=21),     # L' = 108 (gram)
         dict(seed=6, H=31, W=16, L=100, levels=5, inner=1, outer=9),     # L' = 4 (box)
+        dict(seed=7, H=22, W=19, L=160, levels=3, inner=3, outer=33),    # L' = 20, outer 33 (gram)
     ]
 
 

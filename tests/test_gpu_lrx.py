@@ -79,13 +79,55 @@ GEN = [(23, 19, 14, 5, 15), (20, 17, 28, 3, 11), (12, 14, 56, 3, 11), (9, 11, 11
 
 
 @pytest.mark.parametrize("H,W,Lp,inner,outer", GEN)
-def test_generic_path_parity(H, W, Lp, inner, outer):
+@pytest.mark.parametrize("stats", ["auto", "gram"])
+def test_generic_path_parity(H, W, Lp, inner, outer, stats):
+    # auto: sliding box statistics where they apply (L' <= 64, outer <= 31), else the Gram;
+    # gram: the matrix-core Gram forced for every shape
     if Lp in (14, 28, 56, 112, 224):
         x, _ = _reduced(H * W + Lp, H, W, Lp)
     else:
         from paper_1201_2025_amd import synth
         x = synth.random_cube(H + W + Lp, H, W, Lp) + 2.0
-    _check(np.ascontiguousarray(x, dtype=np.float32), inner, outer)
+    L_ = hs.lib()
+    try:
+        L_.hsad_internal_generic_force(1 if stats == "gram" else -1)
+        _check(np.ascontiguousarray(x, dtype=np.float32), inner, outer)
+    finally:
+        L_.hsad_internal_generic_force(-1)
+
+
+# box statistics for mid-size L': ragged tiles, the largest window it takes (outer 31),
+# no inner window, the largest L' (64), odd L'
+BOXG = [(37, 29, 14, 5, 15), (40, 35, 9, 5, 31), (33, 18, 13, 0, 9), (20, 19, 64, 3, 9), (17, 50, 23, 1, 7),
+        (70, 3, 12, 3, 11), (1, 1, 10, 0, 3)]
+
+
+@pytest.mark.parametrize("H,W,Lp,inner,outer", BOXG)
+@pytest.mark.parametrize("resident_kb", [0, 156])
+def test_box_statistics_path(H, W, Lp, inner, outer, resident_kb):
+    # resident_kb 0: bands staged per feature chunk; 156: the whole tile resident when it fits
+    from paper_1201_2025_amd import synth
+    x = np.ascontiguousarray(synth.random_cube(7 * H + W + Lp, H, W, Lp) * 0.3 + 1.5, dtype=np.float32)
+    print("box statistics", H, W, Lp, inner, outer, resident_kb, flush=True)
+    L_ = hs.lib()
+    try:
+        L_.hsad_internal_boxg_resident_kb(resident_kb)
+        _check(x, inner, outer)
+    finally:
+        L_.hsad_internal_boxg_resident_kb(156)
+
+
+def test_box_statistics_chunking_is_invariant():
+    # a workspace of exactly one band of 16 rows gives the same bits as the default one
+    import torch
+    x, _ = _reduced(21, 70, 45, 28)
+    t = torch.from_numpy(x).cuda()
+    a, b = hs.hsad_lrx_dwrx(t, 3, 11, 1e-6)
+    band = 16 * 45 * (28 + 3) * 28 * 8
+    ws = torch.empty(band, dtype=torch.uint8, device="cuda")
+    c, d = hs.hsad_lrx_dwrx(t, 3, 11, 1e-6, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), c.cpu().numpy()) and np.array_equal(b.cpu().numpy(), d.cpu().numpy())
 
 
 def test_small_lp_fp32_gram_generic_path():
@@ -139,7 +181,7 @@ def test_end_to_end_dwt_lrx(cfg):
     assert np.array_equal(oracle.mask(gl, tau)[~band], oracle.mask(rl, tau)[~band])
 
 
-@pytest.mark.parametrize("levels", [6, 4])
+@pytest.mark.parametrize("levels", [6, 4, 3])
 def test_full_size_sampled_dwt_lrx(levels):
     # 512 x 512 x 224 at the bench's launch configuration; the oracle scores a sample
     import torch
@@ -160,7 +202,7 @@ def test_full_size_sampled_dwt_lrx(levels):
         assert e.max() <= TOL
 
 
-@pytest.mark.parametrize("Lp,bad", [(4, np.nan), (4, np.inf), (14, np.nan)])
+@pytest.mark.parametrize("Lp,bad", [(4, np.nan), (4, np.inf), (14, np.nan), (28, np.inf)])
 def test_non_finite_inputs_match_definition(Lp, bad):
     # a non-finite sample in the annulus gives +inf (covariance not positive definite);
     # one at the pixel itself, or in its inner window only, propagates through the means

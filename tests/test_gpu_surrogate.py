@@ -15,8 +15,9 @@ Bounds:
                                       the GPU's inputs of that stage, within 2^-21 times
                                       the operand magnitudes (a few FP32 units)
   selection flags and counts          bitwise (SplitMix64 on both sides, same FP64 test)
-  exact LRX at listed pixels          1e-3 relative vs the oracle; bitwise vs hsad_lrx
-                                      for L' > 8 (same FP64 Gram / Cholesky kernels)
+  exact LRX at listed pixels          1e-3 relative vs the oracle; bitwise vs the full map
+                                      through the same statistics (matrix-core Gram) and
+                                      Cholesky kernels
   hybrid map                          exact LRX on the selected pixels (bitwise),
                                       expm1(prediction) elsewhere, eq. (12) mask
 The trained network's accuracy itself has no exact counterpart ("parity unpinned"): it is
@@ -337,7 +338,12 @@ def test_lrx_dwrx_at(H, W, Lp, inner, outer):
     # tiny workspace: one pixel per chunk
     lrx1 = torch.full((H, W), -1.0, device="cuda")
     hs.hsad_lrx_dwrx_at(xt, _t(idx[:40]), inner, outer, 1e-6, lrx=lrx1, ws_bytes=(Lp + 2) * Lp * 8)
-    fl, fd = hs.hsad_lrx_dwrx(xt, inner, outer, 1e-6)
+    L_ = hs.lib()
+    try:       # the full maps through the same statistics (matrix-core Gram) and Cholesky
+        L_.hsad_internal_generic_force(1)
+        fl, fd = hs.hsad_lrx_dwrx(xt, inner, outer, 1e-6)
+    finally:
+        L_.hsad_internal_generic_force(-1)
     torch.cuda.synchronize()
     gl, gd = lrx.cpu().numpy().ravel(), dwrx.cpu().numpy().ravel()
     untouched = np.ones(H * W, bool)
@@ -394,11 +400,16 @@ def test_training_deterministic(trained):
     assert np.array_equal(sur.params.cpu().numpy(), again.params.cpu().numpy())
 
 
-def _hybrid_case(sur, seed=2100, size=160):
+def _hybrid_case(sur, seed=2100, size=160, gram=False):
     import torch
     s = scene(seed, size, size, 224, K=6, n_single=size * size // 600, n_blob=4)
     x = hs.hsad_dwt(_t(s.cube), LV)
-    exact = hs.hsad_lrx(x, IN, OUT)
+    L_ = hs.lib()
+    try:
+        L_.hsad_internal_generic_force(1 if gram else -1)
+        exact = hs.hsad_lrx(x, IN, OUT)
+    finally:
+        L_.hsad_internal_generic_force(-1)
     yhat = sur.predict(x)
     torch.cuda.synchronize()
     return s, x, exact, yhat
@@ -407,7 +418,8 @@ def _hybrid_case(sur, seed=2100, size=160):
 def test_hybrid_map(trained):
     import torch
     sur, _ = trained
-    s, x, exact, yhat = _hybrid_case(sur)
+    s, x, exact, yhat = _hybrid_case(sur, gram=True)      # the recompute's own statistics path
+    exact_auto = hs.hsad_lrx(x, IN, OUT).cpu().numpy().ravel()
     seed, frac, band_k, z = 77, 0.01, 3.0, 3.0
     scores, mask, rep = sur.run(x, z_alpha=z, band_k=band_k, audit_frac=frac, fallback_factor=4.0, seed=seed)
     torch.cuda.synchronize()
@@ -424,6 +436,7 @@ def test_hybrid_map(trained):
     assert rep["audit"] == ((flags & 2) > 0).sum()
     sel = flags > 0
     assert np.array_equal(sc[sel], ex[sel])
+    assert score_rel_err(sc[sel], exact_auto[sel]).max() <= 1e-3     # and the default exact map
     assert np.allclose(sc[~sel], pred[~sel], rtol=1e-6)
     ea = y[(flags & 2) > 0].astype(np.float64) - np.log1p(ex[(flags & 2) > 0].astype(np.float64))
     assert np.isclose(rep["audit_rmse"], np.sqrt(np.mean(ea * ea)), rtol=1e-9)
