@@ -17,6 +17,7 @@ printed.  Beside the timed step, the script also measures:
   * ROC AUC of the GPU scores minus that of the FP64 oracle scores (truth mask known);
   * the FP64 CPU oracle on the host cores, for the same workload (cpu_baseline);
   * the 64-scene uneven batch through the persistent batch engine;
+  * DWEST (eqs. 2-4) at L' = 14 / 28 / 56 on the same cube (inner 3, outer 11);
   * the learned surrogate: exact vs hybrid LRX on a 2048 x 2048 x 224 scene at L' = 14
     and 56, with the change of ROC AUC.
 """
@@ -49,6 +50,7 @@ def parse():
     ap.add_argument("--no-fullband", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batch measurement")
     ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--no-dwest", action="store_true", help="skip the DWEST measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
     ap.add_argument("--surrogate-scenes", type=int, default=200,
                     help="training scenes of 256x256x224 for the surrogate (200 in the full workload)")
@@ -139,6 +141,38 @@ def bench_batch(args, dev):
             "schedule": {"wgs_per_cu": best.wgs_per_cu, "dwt_pixels": best.dwt_pixels,
                          "chunk_bytes": best.chunk_bytes, "tuning_ms": tune_ms},
             "plan": info}
+
+
+def bench_dwest(cube, dev, log):
+    """DWEST (eqs. 2-4) on the 512 x 512 x 224 cube reduced to L' = 14 / 28 / 56, inner 3 x 3,
+    outer 11 x 11: FP64 Gram of the inner and annulus windows, then a parallel Jacobi
+    eigensolve per pixel.  Reports time, pixels/s and the FP64 rate of the nominal
+    9 L'^3 flop per pixel of a symmetric eigensolve with vectors."""
+    import torch
+    import paper_1201_2025_amd as hs
+    H, W = cube.shape[0], cube.shape[1]
+    out = []
+    for lv in (4, 3, 2):
+        if out and out[-1]["ms"] > 2000.0:
+            break
+        x = hs.hsad_dwt(cube, lv)
+        Lp = x.shape[2]
+        ws = torch.empty(hs.hsad_workspace_bytes(hs.HSAD_OP_DWEST, H, W, Lp, 3, 11, 0.0), dtype=torch.uint8,
+                         device=dev)
+        hs.hsad_dwest(x, 3, 11, ws=ws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        hs.hsad_dwest(x, 3, 11, ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        nominal = 9.0 * Lp ** 3 * H * W
+        out.append({"levels": lv, "Lp": Lp, "ms": ms, "pixels_per_s": H * W / (ms * 1e-3),
+                    "nominal_fp64_tflops": nominal / (ms * 1e-3) / 1e12})
+        log("dwest L'=%d: %.2f ms" % (Lp, ms))
+        del ws
+    return {"workload": "512x512x224 cube (C2 recipe) at L' = 14/28/56, inner 3, outer 11", "levels": out}
 
 
 def bench_surrogate(args, dev, log):
@@ -434,6 +468,13 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    dwest = None
+    if not args.no_dwest:
+        try:
+            dwest = bench_dwest(cubes[0], dev, log)
+        except Exception as e:     # report, keep the headline line
+            dwest = {"error": repr(e)}
+
     surrogate = None
     if not args.no_surrogate:
         try:
@@ -475,6 +516,7 @@ def main():
         "full_band_gpu": full,
         "sweep": sweep,
         "batch": batch,
+        "dwest": dwest,
         "surrogate": surrogate,
     }
     out.update(result_extra)
