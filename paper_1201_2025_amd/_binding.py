@@ -8,6 +8,7 @@ caller-side memory, and the library itself never allocates.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 import threading
 
@@ -133,6 +134,7 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_filter", ctypes.c_int, [ctypes.POINTER(ctypes.c_double)]),
     ("hsad_internal_dwt_force", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_chunk", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_dwt_nt", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_variant", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     ("hsad_internal_generic_force", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_boxg_resident_kb", ctypes.c_int, [ctypes.c_int]),
@@ -148,6 +150,8 @@ def lib_path() -> str:
 def lib():
     """The loaded libhsad; raises if it has not been built."""
     global _lib
+    if _lib is not None:
+        return _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB_PATH):
@@ -174,6 +178,7 @@ def _check(fn: str, rc: int):
         raise HsadError(fn, rc, hsad_last_error())
 
 
+@functools.lru_cache(maxsize=256)
 def hsad_dwt_out_len(L: int, levels: int) -> int:
     out = _i64(0)
     _check("hsad_dwt_out_len", lib().hsad_dwt_out_len(int(L), int(levels), ctypes.byref(out)))
@@ -205,8 +210,12 @@ def _torch():
 
 def _stream(stream):
     torch = _torch()
-    s = torch.cuda.current_stream() if stream is None else stream
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)   # no Stream object per call
+    if raw is not None:
+        return ctypes.c_void_p(raw(torch.cuda.current_device()))
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _dev(t, name, dtype=None, ndim=None):

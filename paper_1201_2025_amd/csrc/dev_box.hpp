@@ -63,6 +63,100 @@ __device__ __forceinline__ int clip_count(int c, int r, int n)
     return hi - lo + 1;
 }
 
+// Step 3 of the tile: statistics of the annulus from its sums S (features in the order of
+// feat(): L' linear, the upper triangle of products, the non-finite count), loading,
+// Cholesky and both scores for output pixel (py, px).
+template <int LP, int GT>
+__device__ __forceinline__ void box_score(const float *__restrict__ x, int H, int W, int R, int RI,
+                                          int has_inner, double load_rel, const double *ref,
+                                          const double *S, double *sin_lin, double in_bad, int py,
+                                          int px, float *__restrict__ lrx, float *__restrict__ dwrx)
+{
+    constexpr int G = GT - 1;
+    // 3. statistics of the annulus, loading, Cholesky, scores
+    const int n_o = clip_count(py, R, H) * clip_count(px, R, W);
+    const int n_i = has_inner ? clip_count(py, RI, H) * clip_count(px, RI, W) : 0;
+    const double inv_na = 1.0 / (double)(n_o - n_i);
+    const bool ann_bad = S[G] > 0.5;      // exact small integers in FP64
+    double mu[LP];
+#pragma unroll
+    for (int i = 0; i < LP; ++i) mu[i] = S[i] * inv_na;
+    double Lm[LP][LP];
+    double tr = 0.0;
+    {
+        int g = LP;
+#pragma unroll
+        for (int i = 0; i < LP; ++i)
+#pragma unroll
+            for (int j = i; j < LP; ++j) {
+                const double c = S[g++] * inv_na - mu[i] * mu[j];
+                Lm[j][i] = c;
+                if (i == j) tr += c;
+            }
+    }
+    double lam = load_rel * tr / (double)LP;
+    lam = lam < 1e-30 ? 1e-30 : lam;
+    // Cholesky with reciprocal pivots: Lm[j][j] holds 1/L_jj
+    bool pd = true;
+#pragma unroll
+    for (int j = 0; j < LP; ++j) {
+        double d = Lm[j][j] + lam;
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
+        pd = pd && (d > 0.0);
+        const double inv = rsqrt(d);
+        Lm[j][j] = inv;
+#pragma unroll
+        for (int i = j + 1; i < LP; ++i) {
+            double t = Lm[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= Lm[i][k] * Lm[j][k];
+            Lm[i][j] = t * inv;
+        }
+    }
+    const size_t o = (size_t)py * W + px;
+    if (lrx) {
+        const float *pc = x + o * LP;            // raw centre pixel
+        double z[LP], s = 0.0;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            double t = ((double)pc[i] - ref[i]) - mu[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
+            z[i] = t * Lm[i][i];
+            s += z[i] * z[i];
+        }
+        lrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
+    }
+    if (dwrx) {
+        if (in_bad > 0.5) {
+            // rare: a non-finite inner sample; take the mean from the raw values so that
+            // NaN / Inf propagate exactly as in the definition
+#pragma unroll
+            for (int i = 0; i < LP; ++i) sin_lin[i] = 0.0;
+            for (int dy = -RI; dy <= RI; ++dy)
+                for (int dx = -RI; dx <= RI; ++dx) {
+                    const int gy = py + dy, gx = px + dx;
+                    if (gy < 0 || gy >= H || gx < 0 || gx >= W) continue;
+                    const float *raw = x + ((size_t)gy * W + gx) * LP;
+#pragma unroll
+                    for (int i = 0; i < LP; ++i) sin_lin[i] += (double)raw[i] - ref[i];
+                }
+        }
+        const double inv_ni = 1.0 / (double)n_i;
+        double z[LP], s = 0.0;
+#pragma unroll
+        for (int i = 0; i < LP; ++i) {
+            double t = sin_lin[i] * inv_ni - mu[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
+            z[i] = t * Lm[i][i];
+            s += z[i] * z[i];
+        }
+        dwrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
+    }
+}
+
 template <int LP, int GCMAX>
 __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R, int RI,
                                 int has_inner, double load_rel, float *__restrict__ lrx,
@@ -202,89 +296,7 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
     }
 
     if (py >= H || px >= W) return;
-
-    // 3. statistics of the annulus, loading, Cholesky, scores
-    const int n_o = clip_count(py, R, H) * clip_count(px, R, W);
-    const int n_i = has_inner ? clip_count(py, RI, H) * clip_count(px, RI, W) : 0;
-    const double inv_na = 1.0 / (double)(n_o - n_i);
-    const bool ann_bad = S[C::G] > 0.5;      // exact small integers in FP64
-    double mu[LP];
-#pragma unroll
-    for (int i = 0; i < LP; ++i) mu[i] = S[i] * inv_na;
-    double Lm[LP][LP];
-    double tr = 0.0;
-    {
-        int g = LP;
-#pragma unroll
-        for (int i = 0; i < LP; ++i)
-#pragma unroll
-            for (int j = i; j < LP; ++j) {
-                const double c = S[g++] * inv_na - mu[i] * mu[j];
-                Lm[j][i] = c;
-                if (i == j) tr += c;
-            }
-    }
-    double lam = load_rel * tr / (double)LP;
-    lam = lam < 1e-30 ? 1e-30 : lam;
-    // Cholesky with reciprocal pivots: Lm[j][j] holds 1/L_jj
-    bool pd = true;
-#pragma unroll
-    for (int j = 0; j < LP; ++j) {
-        double d = Lm[j][j] + lam;
-#pragma unroll
-        for (int k = 0; k < j; ++k) d -= Lm[j][k] * Lm[j][k];
-        pd = pd && (d > 0.0);
-        const double inv = rsqrt(d);
-        Lm[j][j] = inv;
-#pragma unroll
-        for (int i = j + 1; i < LP; ++i) {
-            double t = Lm[i][j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) t -= Lm[i][k] * Lm[j][k];
-            Lm[i][j] = t * inv;
-        }
-    }
-    const size_t o = (size_t)py * W + px;
-    if (lrx) {
-        const float *pc = x + o * LP;            // raw centre pixel
-        double z[LP], s = 0.0;
-#pragma unroll
-        for (int i = 0; i < LP; ++i) {
-            double t = ((double)pc[i] - ref[i]) - mu[i];
-#pragma unroll
-            for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
-            z[i] = t * Lm[i][i];
-            s += z[i] * z[i];
-        }
-        lrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
-    }
-    if (dwrx) {
-        if (in_bad > 0.5) {
-            // rare: a non-finite inner sample; take the mean from the raw values so that
-            // NaN / Inf propagate exactly as in the definition
-#pragma unroll
-            for (int i = 0; i < LP; ++i) sin_lin[i] = 0.0;
-            for (int dy = -RI; dy <= RI; ++dy)
-                for (int dx = -RI; dx <= RI; ++dx) {
-                    const int gy = py + dy, gx = px + dx;
-                    if (gy < 0 || gy >= H || gx < 0 || gx >= W) continue;
-                    const float *raw = x + ((size_t)gy * W + gx) * LP;
-#pragma unroll
-                    for (int i = 0; i < LP; ++i) sin_lin[i] += (double)raw[i] - ref[i];
-                }
-        }
-        const double inv_ni = 1.0 / (double)n_i;
-        double z[LP], s = 0.0;
-#pragma unroll
-        for (int i = 0; i < LP; ++i) {
-            double t = sin_lin[i] * inv_ni - mu[i];
-#pragma unroll
-            for (int k = 0; k < i; ++k) t -= Lm[i][k] * z[k];
-            z[i] = t * Lm[i][i];
-            s += z[i] * z[i];
-        }
-        dwrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
-    }
+    box_score<LP, C::GT>(x, H, W, R, RI, has_inner, load_rel, ref, S, sin_lin, in_bad, py, px, lrx, dwrx);
 }
 
 

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void dwt_equiv_kernel(const float *__restrict_
 // so HBM streaming overlaps the FP64 FMAs.
 constexpr int kEqCB = 32, kEqTP = 256, kEqLd = kEqCB + 1;
 
-template <int LP, int VEC>
+template <int LP, int VEC, bool NTL = true>
 __global__ __launch_bounds__(kEqTP) void dwt_equiv_lds_kernel(const float *__restrict__ cube,
                                                               int64_t npix, int L,
                                                               const double *__restrict__ coef,
@@ -315,8 +315,12 @@ __global__ __launch_bounds__(kEqTP) void dwt_equiv_lds_kernel(const float *__res
         for (int i = 0; i < NV; ++i) {
             const int q = t + kEqTP * i;
             const int p = q / PER, j = q % PER;
-            if (p < np && j * VEC < cb)
-                buf[i] = *reinterpret_cast<const V *>(cube + (p0 + p) * (int64_t)L + c0 + j * VEC);
+            if (p < np && j * VEC < cb) {
+                // the cube is read exactly once: non-temporal loads keep it from displacing
+                // cached data
+                const V *a = reinterpret_cast<const V *>(cube + (p0 + p) * (int64_t)L + c0 + j * VEC);
+                buf[i] = NTL ? __builtin_nontemporal_load(a) : *a;
+            }
         }
     };
     auto store_chunk = [&](int c0) {
@@ -424,14 +428,18 @@ static int banded_pixels(int64_t L, int64_t Lp, int64_t W)
 // ------------------------------------------------------------------------------------
 // dispatch
 // ------------------------------------------------------------------------------------
+static int g_dwt_nt = 1;   // non-temporal cube loads in the LDS-staged kernel (tuning switch)
+
 template <int LP>
 static int launch_equiv(const float *cube, int64_t npix, int64_t L, const double *coef, int vec,
                         bool lds, float *out, hipStream_t s)
 {
     if (lds) {
         dim3 grid((unsigned)((npix + kEqTP - 1) / kEqTP)), block(kEqTP);
-        if (vec == 4)
-            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+        if (vec == 4 && g_dwt_nt)
+            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4, true>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+        else if (vec == 4)
+            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4, false>), grid, block, 0, s, cube, npix, (int)L, coef, out);
         else
             hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 1>), grid, block, 0, s, cube, npix, (int)L, coef, out);
         return check_launch("dwt_equiv_lds_kernel");
@@ -522,5 +530,11 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
 extern "C" int hsad_internal_dwt_force(int mode)
 {
     hsad::g_dwt_force = mode;
+    return 0;
+}
+
+extern "C" int hsad_internal_dwt_nt(int on)
+{
+    hsad::g_dwt_nt = on ? 1 : 0;
     return 0;
 }

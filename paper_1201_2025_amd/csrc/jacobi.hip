@@ -14,7 +14,9 @@
 //   score   = ||V_P^T m_diff||_2        (independent of eigenvector signs)
 //   literal = sum_P |v_i^T m_diff|      (eq. 4 with v_i signed so that v_i^T m_diff >= 0)
 //   npos    = |P|
-// A, V and the rotation pairs live in LDS (stride n+1 doubles); lanes split the
+// Only the projections y = V^T m_diff are needed, never V itself: every rotation J applied
+// to A as J^T A J is applied to y as J^T y, which keeps y = V^T m_diff throughout.  A, y and
+// the round's pairs and rotations live in LDS (A with stride n+1 doubles); lanes split the
 // (pair, index) updates of each round.
 #include <hip/hip_runtime.h>
 
@@ -41,8 +43,12 @@ __device__ __forceinline__ void tournament_pair(int i, int r, int m, int &p, int
     }
 }
 
+// floor(t / d) from mg = ceil(2^32 / d) (d >= 2; mg = 0 stands for d = 1).  Exact while
+// t * (mg d - 2^32) < 2^32; with t < d^2 and an excess below d that holds for d <= 1625.
+__device__ __forceinline__ unsigned div_magic(unsigned t, unsigned mg) { return mg ? __umulhi(t, mg) : t; }
+
 __global__ __launch_bounds__(64) void jacobi_dwest_kernel(const double *__restrict__ ws, int n,
-                                                          int npix, int64_t pix0,
+                                                          int npix, int64_t pix0, unsigned mg,
                                                           float *__restrict__ score,
                                                           float *__restrict__ literal,
                                                           int32_t *__restrict__ npos)
@@ -52,9 +58,9 @@ __global__ __launch_bounds__(64) void jacobi_dwest_kernel(const double *__restri
     const int m = n + (n & 1);
     const int np = m / 2;
     double *A = sm;                            // n x ld
-    double *V = A + (size_t)n * ld;            // n x ld
-    double *cs = V + (size_t)n * ld;           // np x 2
-    double *md = cs + 2 * np;                  // n
+    double *cs = A + (size_t)n * ld;           // np x 2 (c, s)
+    double *y = cs + 2 * np;                   // n: V^T m_diff
+    int *pq = reinterpret_cast<int *>(y + n);  // np x 2 (p, q); q >= n marks the dummy pair
     const int lane = threadIdx.x;
     const int local = blockIdx.x;
     if (local >= npix) return;
@@ -62,32 +68,33 @@ __global__ __launch_bounds__(64) void jacobi_dwest_kernel(const double *__restri
 
     double fro2 = 0.0;
     for (int t = lane; t < n * n; t += 64) {
-        const int i = t / n, j = t - i * n;
+        const unsigned i = div_magic((unsigned)t, mg), j = (unsigned)t - i * (unsigned)n;
         const double v = src[t];
         A[i * ld + j] = v;
-        V[i * ld + j] = (i == j) ? 1.0 : 0.0;
         fro2 += v * v;
     }
-    for (int k = lane; k < n; k += 64) md[k] = src[(size_t)n * n + k];
+    for (int k = lane; k < n; k += 64) y[k] = src[(size_t)n * n + k];
     fro2 = wave_sum(fro2);
     const double tol2 = 1e-28 * fro2;          // (1e-14 ||A||_F)^2
     __syncthreads();
+    const int nu = np * n;
 
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off2 = 0.0;
         for (int t = lane; t < n * n; t += 64) {
-            const int i = t / n, j = t - i * n;
+            const unsigned i = div_magic((unsigned)t, mg), j = (unsigned)t - i * (unsigned)n;
             if (i != j) off2 += A[i * ld + j] * A[i * ld + j];
         }
         off2 = wave_sum(off2);
         if (off2 <= tol2) break;
         for (int r = 0; r < m - 1; ++r) {
-            // rotation parameters, one lane per pair
+            // pairs and rotation parameters, one lane per pair; the projection vector is
+            // rotated here too (the pairs of a round are disjoint)
             for (int i = lane; i < np; i += 64) {
                 int p, q;
                 tournament_pair(i, r, m, p, q);
                 double c = 1.0, s = 0.0;
-                if (p < n && q < n) {
+                if (q < n && p < n) {
                     const double apq = A[p * ld + q];
                     if (apq != 0.0) {
                         const double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
@@ -96,36 +103,39 @@ __global__ __launch_bounds__(64) void jacobi_dwest_kernel(const double *__restri
                         c = 1.0 / sqrt(t * t + 1.0);
                         s = t * c;
                     }
+                    const double yp = y[p], yq = y[q];
+                    y[p] = c * yp - s * yq;
+                    y[q] = s * yp + c * yq;
+                } else {
+                    p = p < q ? p : q;
+                    q = n;                     // dummy index of an odd n
                 }
                 cs[2 * i] = c;
                 cs[2 * i + 1] = s;
+                pq[2 * i] = p;
+                pq[2 * i + 1] = q;
             }
             __syncthreads();
             // A <- J^T A (rows p, q)
-            for (int t = lane; t < np * n; t += 64) {
-                const int i = t / n, k = t - i * n;
-                int p, q;
-                tournament_pair(i, r, m, p, q);
-                if (q >= n || p >= n) continue;
+            for (int t = lane; t < nu; t += 64) {
+                const unsigned i = div_magic((unsigned)t, mg), k = (unsigned)t - i * (unsigned)n;
+                const int p = pq[2 * i], q = pq[2 * i + 1];
+                if (q >= n) continue;
                 const double c = cs[2 * i], s = cs[2 * i + 1];
                 const double apk = A[p * ld + k], aqk = A[q * ld + k];
                 A[p * ld + k] = c * apk - s * aqk;
                 A[q * ld + k] = s * apk + c * aqk;
             }
             __syncthreads();
-            // A <- A J and V <- V J (columns p, q)
-            for (int t = lane; t < np * n; t += 64) {
-                const int i = t / n, k = t - i * n;
-                int p, q;
-                tournament_pair(i, r, m, p, q);
-                if (q >= n || p >= n) continue;
+            // A <- A J (columns p, q)
+            for (int t = lane; t < nu; t += 64) {
+                const unsigned i = div_magic((unsigned)t, mg), k = (unsigned)t - i * (unsigned)n;
+                const int p = pq[2 * i], q = pq[2 * i + 1];
+                if (q >= n) continue;
                 const double c = cs[2 * i], s = cs[2 * i + 1];
                 const double akp = A[k * ld + p], akq = A[k * ld + q];
                 A[k * ld + p] = c * akp - s * akq;
                 A[k * ld + q] = s * akp + c * akq;
-                const double vkp = V[k * ld + p], vkq = V[k * ld + q];
-                V[k * ld + p] = c * vkp - s * vkq;
-                V[k * ld + q] = s * vkp + c * vkq;
             }
             __syncthreads();
         }
@@ -137,8 +147,7 @@ __global__ __launch_bounds__(64) void jacobi_dwest_kernel(const double *__restri
     double s2 = 0.0, s1 = 0.0, cnt = 0.0;
     for (int i = lane; i < n; i += 64) {
         if (A[i * ld + i] > 1e-12 * emax) {
-            double pr = 0.0;
-            for (int k = 0; k < n; ++k) pr += V[k * ld + i] * md[k];
+            const double pr = y[i];
             s2 += pr * pr;
             s1 += fabs(pr);
             cnt += 1.0;
@@ -158,16 +167,18 @@ __global__ __launch_bounds__(64) void jacobi_dwest_kernel(const double *__restri
 size_t jacobi_smem(int64_t n)
 {
     const int64_t np = (n + 1) / 2;
-    return (size_t)(2 * n * (n + 1) + 2 * np + n) * sizeof(double);
+    return (size_t)(n * (n + 1) + 2 * np + n + np) * sizeof(double);
 }
 
 int jacobi_launch(const double *ws, int64_t n, int npix, int64_t pix0, float *score,
                   float *literal, int32_t *npos, hipStream_t s)
 {
+    if (n < 1 || n > 1024) return fail(HSAD_EUNSUPPORTED, "jacobi_dwest: L' must be in [1, 1024]");
     const size_t sh = jacobi_smem(n);
     if (int rc = allow_lds((const void *)jacobi_dwest_kernel, sh, "jacobi_dwest_kernel")) return rc;
+    const unsigned mg = n == 1 ? 0u : (unsigned)((0x100000000ull + (uint64_t)n - 1) / (uint64_t)n);
     hipLaunchKernelGGL(jacobi_dwest_kernel, dim3((unsigned)npix), dim3(64), sh, s, ws, (int)n, npix,
-                       pix0, score, literal, npos);
+                       pix0, mg, score, literal, npos);
     return check_launch("jacobi_dwest_kernel");
 }
 

@@ -674,13 +674,26 @@ __global__ __launch_bounds__(1024) void select_scan_kernel(const unsigned *__res
                                                            unsigned *__restrict__ boff, unsigned *__restrict__ counts)
 {
     __shared__ unsigned sc[1024];
+    __shared__ unsigned wtot[2][16];
     const int t = threadIdx.x;
-    unsigned v[4], loc = 0;
+    unsigned v[4], loc = 0, lb = 0, la = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int b = 4 * t + q;
         v[q] = b < nb ? bcnt[3 * b] : 0u;
+        lb += b < nb ? bcnt[3 * b + 1] : 0u;
+        la += b < nb ? bcnt[3 * b + 2] : 0u;
         loc += v[q];
+    }
+    // band and audit totals: wave sums, then the 16 wave totals (integer sums, any order)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lb += __shfl_down(lb, o, 64);
+        la += __shfl_down(la, o, 64);
+    }
+    if ((t & 63) == 0) {
+        wtot[0][t >> 6] = lb;
+        wtot[1][t >> 6] = la;
     }
     sc[t] = loc;
     __syncthreads();
@@ -699,9 +712,9 @@ __global__ __launch_bounds__(1024) void select_scan_kernel(const unsigned *__res
     }
     if (t == 0) {
         unsigned tb = 0, ta = 0;
-        for (int b = 0; b < nb; ++b) {
-            tb += bcnt[3 * b + 1];
-            ta += bcnt[3 * b + 2];
+        for (int w = 0; w < 16; ++w) {
+            tb += wtot[0][w];
+            ta += wtot[1][w];
         }
         counts[0] = sc[1023];
         counts[1] = tb;
@@ -778,18 +791,37 @@ __global__ __launch_bounds__(256) void err_partial_kernel(const float *__restric
     }
 }
 
-__global__ void err_final_kernel(const double *__restrict__ part, int nb, double *__restrict__ out)
+// one block of 256 threads: strided partial sums per thread, then a fixed tree (the same
+// order on every run)
+__global__ __launch_bounds__(256) void err_final_kernel(const double *__restrict__ part, int nb,
+                                                        double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
     double c = 0.0, s = 0.0, mx = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = t; b < nb; b += 256) {
         c += part[3 * b];
         s += part[3 * b + 1];
         mx = fmax(mx, part[3 * b + 2]);
     }
-    out[0] = c;
-    out[1] = c > 0.0 ? sqrt(s / c) : 0.0;
-    out[2] = mx;
+    red[0][t] = c;
+    red[1][t] = s;
+    red[2][t] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            red[0][t] += red[0][t + o];
+            red[1][t] += red[1][t + o];
+            red[2][t] = fmax(red[2][t], red[2][t + o]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        c = red[0][0];
+        out[0] = c;
+        out[1] = c > 0.0 ? sqrt(red[1][0] / c) : 0.0;
+        out[2] = red[2][0];
+    }
 }
 
 int grid_for(int64_t n, int cap = 8192)
@@ -816,7 +848,7 @@ int err_stats_launch(const float *yhat, const float *ref, int ref_is_score, cons
     const int nb = grid_for(n, 1024);
     hipLaunchKernelGGL(err_partial_kernel, dim3(nb), dim3(256), 0, s, yhat, ref, ref_is_score, flags, mask, n,
                        (double *)ws);
-    hipLaunchKernelGGL(err_final_kernel, dim3(1), dim3(64), 0, s, (const double *)ws, nb, out);
+    hipLaunchKernelGGL(err_final_kernel, dim3(1), dim3(256), 0, s, (const double *)ws, nb, out);
     return check_launch("err_stats");
 }
 

@@ -68,9 +68,38 @@ def _box_input(H, W, Lp):
     return np.ascontiguousarray(x, dtype=np.float32)
 
 
+# the box path's tile kernel at feature chunks 5 / 8 / 15 (the default picks 5 or 8), set
+# through the library's internal switches
+BOX_KERNELS = {"tile5": (1, 5), "tile8": (1, 8), "tile15": (1, 15)}
+
+
+@pytest.fixture(params=sorted(BOX_KERNELS))
+def box_kernel(request):
+    L_ = hs.lib()
+    v, gc = BOX_KERNELS[request.param]
+    L_.hsad_internal_box_variant(v, 2)
+    L_.hsad_internal_box_chunk(gc)
+    yield request.param
+    L_.hsad_internal_box_variant(0, 2)
+    L_.hsad_internal_box_chunk(0)
+
+
 @pytest.mark.parametrize("H,W,Lp,inner,outer", BOX)
-def test_box_path_parity(H, W, Lp, inner, outer):
+def test_box_path_parity(H, W, Lp, inner, outer, box_kernel):
     _check(_box_input(H, W, Lp), inner, outer)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_box_kernels_non_finite(bad, box_kernel):
+    x, _ = _reduced(8, 40, 40, 4)
+    x = x.copy()
+    x[20, 20, 1] = bad
+    x[3, 37, 0] = bad
+    x[0, 0, 3] = bad
+    gl, gd = _gpu(x, 3, 9)
+    rl, rd = oracle.lrx_dwrx(x.astype(np.float64), 3, 9, 1e-6)
+    for g, r in ((gl, rl), (gd, rd)):
+        assert score_rel_err(g, r).max() <= TOL
 
 
 # generic path: matrix-core Gram + FP64 Cholesky
