@@ -1,0 +1,224 @@
+// eig.hip -- DWEST projection (Sec. 2.2, eqs. 2-4) by Householder tridiagonalisation and
+// the implicit QL iteration, FP64, in two kernels.
+//
+// Input per pixel (chunk workspace, written by the Gram kernel in DWEST mode):
+// rows 0..L'-1 = C_diff = C_inner - C_outer, row L' = m_diff = m_inner - m_outer.
+// DWEST needs the eigenvalues of C_diff and the projections y_i = v_i^T m_diff, never the
+// eigenvectors themselves.  Every orthogonal similarity applied to C_diff is therefore
+// also applied to m_diff, as a vector:
+//   1. tridiag_dwest_kernel (one wavefront per pixel, the matrix in LDS, lane = row):
+//      n-2 Householder reflections H_k = I - beta v v^T, each annihilating column k below
+//      the subdiagonal, give T = Q^T C_diff Q tridiagonal and y = Q^T m_diff.  Per step:
+//      p = beta A v, q = p - (beta/2)(v^T p) v, A <- A - v q^T - q v^T on the trailing
+//      block, y <- y - beta (v^T y) v (Golub & Van Loan, Sec. 8.3.1).  The diagonal d,
+//      the subdiagonal e and y overwrite the pixel's workspace.
+//   2. ql_dwest_kernel (lane = pixel, d, e, y in LDS columns): the implicit QL iteration
+//      with Wilkinson's shift on T (Golub & Van Loan, Sec. 8.3.5; the tql2 procedure of
+//      Bowdler, Martin, Reinsch and Wilkinson).  Each plane rotation of a sweep is also
+//      applied to y, which keeps y = V^T m_diff.  A subdiagonal entry counts as zero once
+//      |e_m| <= eps (|d_m| + |d_m+1|), eps = 2^-52.  At most 64 sweeps per eigenvalue; a
+//      pixel that does not converge gets NaN scores.
+// Eigenvalues above 1e-12 max|lambda| are "positive".  Outputs:
+//   score   = ||V_P^T m_diff||_2 = sqrt(sum_P y_i^2)
+//   literal = sum_P |y_i|          (eq. 4 with v_i signed so that v_i^T m_diff >= 0)
+//   npos    = |P|
+// Work per pixel: about 4/3 n^3 flops for step 1 and O(n^2) for step 2, against roughly
+// 8 sweeps x 4 n^3 for a cyclic Jacobi solver.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "internal.hpp"
+
+namespace hsad {
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One wavefront per pixel; rows i = lane, lane + 64, ...
+__global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ ws, int n, int npix)
+{
+    extern __shared__ double sm[];
+    const int ld = n + 1;
+    double *A = sm;                       // n x ld
+    double *v = A + (size_t)n * ld;       // n (Householder vector; entries <= k unused)
+    double *q = v + n;                    // n
+    double *y = q + n;                    // n
+    const int lane = threadIdx.x;
+    const int local = blockIdx.x;
+    if (local >= npix) return;
+    double *pix = ws + (size_t)local * (n + 2) * n;
+
+    for (int t = lane; t < n * n; t += 64) {
+        const int i = t / n, j = t - i * n;
+        A[i * ld + j] = pix[t];
+    }
+    for (int i = lane; i < n; i += 64) y[i] = pix[(size_t)n * n + i];
+    __syncthreads();
+
+    for (int k = 0; k + 2 < n; ++k) {
+        // column k below the diagonal: x = A[k+1.., k]
+        double s2 = 0.0;
+        for (int i = k + 1 + lane; i < n; i += 64) s2 += A[i * ld + k] * A[i * ld + k];
+        s2 = wave_sum64(s2);
+        const double x0 = A[(k + 1) * ld + k];
+        if (s2 - x0 * x0 == 0.0) continue;    // already reduced: e_k = x0, no reflection
+        const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
+        const double beta = 1.0 / (alpha * (alpha - x0));   // 2 / v^T v
+        for (int i = k + 1 + lane; i < n; i += 64) v[i] = i == k + 1 ? x0 - alpha : A[i * ld + k];
+        __syncthreads();
+        // p = beta A' v on the trailing block; K = (beta/2) v^T p; q = p - K v
+        double vp = 0.0, vy = 0.0;
+        for (int i = k + 1 + lane; i < n; i += 64) {
+            const double *row = A + (size_t)i * ld;
+            double p = 0.0;
+            for (int j = k + 1; j < n; ++j) p = fma(row[j], v[j], p);
+            p *= beta;
+            q[i] = p;
+            vp = fma(v[i], p, vp);
+            vy = fma(v[i], y[i], vy);
+        }
+        vp = wave_sum64(vp);
+        vy = wave_sum64(vy);
+        const double K = 0.5 * beta * vp, gam = beta * vy;
+        for (int i = k + 1 + lane; i < n; i += 64) {
+            q[i] = fma(-K, v[i], q[i]);
+            y[i] = fma(-gam, v[i], y[i]);
+        }
+        __syncthreads();
+        // A' <- A' - v q^T - q v^T
+        for (int i = k + 1 + lane; i < n; i += 64) {
+            double *row = A + (size_t)i * ld;
+            const double vi = v[i], qi = q[i];
+            for (int j = k + 1; j < n; ++j) row[j] -= fma(vi, q[j], qi * v[j]);
+        }
+        // column k itself becomes alpha e_1 (only the subdiagonal is read later)
+        if (lane == 0) A[(k + 1) * ld + k] = alpha;
+        __syncthreads();
+    }
+    // d, e, y -> the start of the pixel's workspace (the matrix is in LDS now)
+    for (int i = lane; i < n; i += 64) {
+        pix[i] = A[i * ld + i];
+        pix[n + i] = i + 1 < n ? A[(i + 1) * ld + i] : 0.0;
+        pix[2 * n + i] = y[i];
+    }
+}
+
+// lane = pixel; d, e, y of pixel lane in LDS columns (entry i at i * P + lane).
+__global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, int64_t pix0, int P,
+                                float *__restrict__ score, float *__restrict__ literal,
+                                int32_t *__restrict__ npos)
+{
+    extern __shared__ double sm[];
+    const int lane = threadIdx.x;
+    const int local = blockIdx.x * P + lane;
+    double *d = sm, *e = sm + (size_t)n * P, *y = sm + (size_t)2 * n * P;
+    const bool act = lane < P && local < npix;
+    if (!act) return;      // no barriers below: lanes are independent
+    const double *pix = ws + (size_t)local * (n + 2) * n;
+    for (int i = 0; i < n; ++i) {
+        d[i * P + lane] = pix[i];
+        e[i * P + lane] = pix[n + i];
+        y[i * P + lane] = pix[2 * n + i];
+    }
+#define D(i) d[(i) * P + lane]
+#define E(i) e[(i) * P + lane]
+#define Y(i) y[(i) * P + lane]
+    bool ok = true;
+    E(n - 1) = 0.0;
+    for (int l = 0; l < n && ok; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m + 1 < n; ++m) {
+                const double dd = fabs(D(m)) + fabs(D(m + 1));
+                if (fabs(E(m)) <= DBL_EPSILON * dd) break;
+            }
+            if (m == l) break;
+            if (++iter > 64) {
+                ok = false;
+                break;
+            }
+            // Wilkinson shift from the leading 2 x 2 block of the unreduced part
+            double g = (D(l + 1) - D(l)) / (2.0 * E(l));
+            double r = hypot(g, 1.0);
+            g = D(m) - D(l) + E(l) / (g + (g >= 0.0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool underflow = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double f = s * E(i), b = c * E(i);
+                r = hypot(f, g);
+                E(i + 1) = r;
+                if (r == 0.0) {          // the chase split the matrix: restart at l
+                    D(i + 1) -= p;
+                    E(m) = 0.0;
+                    underflow = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = D(i + 1) - p;
+                r = (D(i) - g) * s + 2.0 * c * b;
+                p = s * r;
+                D(i + 1) = g + p;
+                g = c * r - b;
+                const double yi = Y(i), yi1 = Y(i + 1);
+                Y(i + 1) = fma(s, yi, c * yi1);
+                Y(i) = fma(c, yi, -s * yi1);
+            }
+            if (underflow) continue;
+            D(l) -= p;
+            E(l) = g;
+            E(m) = 0.0;
+        }
+    }
+    double emax = 0.0;
+    for (int i = 0; i < n; ++i) emax = fmax(emax, fabs(D(i)));
+    double s2 = 0.0, s1 = 0.0;
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) {
+        if (D(i) > 1e-12 * emax) {
+            const double pr = Y(i);
+            s2 += pr * pr;
+            s1 += fabs(pr);
+            ++cnt;
+        }
+    }
+#undef D
+#undef E
+#undef Y
+    const int64_t o = pix0 + local;
+    score[o] = ok ? (float)sqrt(s2) : NAN;
+    if (literal) literal[o] = ok ? (float)s1 : NAN;
+    if (npos) npos[o] = ok ? cnt : -1;
+}
+
+size_t eig_smem(int64_t n) { return (size_t)(n * (n + 1) + 3 * n) * sizeof(double); }
+
+// pixels per workgroup of the QL kernel: the largest power of two <= 64 whose three LDS
+// columns stay within 48 KiB
+static int ql_pixels(int64_t n)
+{
+    int P = 64;
+    while (P > 1 && (size_t)(3 * n * P) * sizeof(double) > 48 * 1024) P >>= 1;
+    return P;
+}
+
+int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score, float *literal,
+                     int32_t *npos, hipStream_t s)
+{
+    const size_t sh = eig_smem(n);
+    if (int rc = allow_lds((const void *)tridiag_dwest_kernel, sh, "tridiag_dwest_kernel")) return rc;
+    hipLaunchKernelGGL(tridiag_dwest_kernel, dim3((unsigned)npix), dim3(64), sh, s, ws, (int)n, npix);
+    if (int rc = check_launch("tridiag_dwest_kernel")) return rc;
+    const int P = ql_pixels(n);
+    const size_t sq = (size_t)(3 * n * P) * sizeof(double);
+    hipLaunchKernelGGL(ql_dwest_kernel, dim3((unsigned)((npix + P - 1) / P)), dim3(P), sq, s,
+                       (const double *)ws, (int)n, npix, pix0, P, score, literal, npos);
+    return check_launch("ql_dwest_kernel");
+}
+
+}  // namespace hsad

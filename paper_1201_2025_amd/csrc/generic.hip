@@ -17,6 +17,10 @@ int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel,
 int boxg_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, int tile_row0, int ntile_rows,
                 double *rec, hipStream_t s);
 size_t jacobi_smem(int64_t n);
+size_t eig_smem(int64_t n);
+int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score, float *literal,
+                     int32_t *npos, hipStream_t s);
+static int g_dwest_solver = 0;   // 0: Householder + implicit QL, 1: cyclic Jacobi (tests)
 int jacobi_launch(const double *ws, int64_t n, int npix, int64_t pix0, float *score,
                   float *literal, int32_t *npos, hipStream_t s);
 
@@ -118,8 +122,9 @@ int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Window
                   float *score, float *literal, int32_t *npos, void *ws, size_t ws_bytes,
                   hipStream_t s)
 {
-    if (jacobi_smem(Lp) > 160 * 1024 || gram_lds_per_wave(Lp, GP_FP64) > 160 * 1024)
-        return fail(HSAD_EUNSUPPORTED, "hsad_dwest: L' above the Jacobi LDS limit (88)");
+    const bool jac = g_dwest_solver == 1;
+    if ((jac ? jacobi_smem(Lp) : eig_smem(Lp)) > 160 * 1024 || gram_lds_per_wave(Lp, GP_FP64) > 160 * 1024)
+        return fail(HSAD_EUNSUPPORTED, "hsad_dwest: L' above the eigensolver's LDS limit");
     const int64_t total = H * W;
     const int64_t P = chunk_pixels(total, Lp, ws_bytes);
     if (P < 1) return fail(HSAD_ENOMEM, "hsad_dwest: workspace below one pixel");
@@ -127,7 +132,8 @@ int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Window
         const int n = (int)((total - p0) < P ? (total - p0) : P);
         int rc = gram_launch(x, H, W, Lp, w, GRAM_DWEST, GP_FP64, p0, n, (double *)ws, s);
         if (rc) return rc;
-        rc = jacobi_launch((const double *)ws, Lp, n, p0, score, literal, npos, s);
+        rc = jac ? jacobi_launch((const double *)ws, Lp, n, p0, score, literal, npos, s)
+                 : eig_dwest_launch((double *)ws, Lp, n, p0, score, literal, npos, s);
         if (rc) return rc;
     }
     return HSAD_OK;
@@ -151,5 +157,11 @@ extern "C" int hsad_internal_gram(const float *x, int64_t H, int64_t W, int64_t 
 extern "C" int hsad_internal_generic_force(int mode)
 {
     hsad::g_generic_force = mode;
+    return 0;
+}
+
+extern "C" int hsad_internal_dwest_solver(int solver)
+{
+    hsad::g_dwest_solver = solver == 1 ? 1 : 0;
     return 0;
 }

@@ -3,7 +3,8 @@
 Scores (||V_P^T m_diff||_2), literal scores (sum_P |v_i^T m_diff|) and the number of
 positive eigenvalues are compared.  The score bound is an elementwise relative error
 <= 1e-3, with a floor of 1e-3 * median.  The positive-eigenvalue counts must match
-exactly.
+exactly.  Both GPU eigensolvers are covered: Householder tridiagonalisation + implicit QL
+(the default) and the cyclic Jacobi solver (selected through an internal switch).
 """
 import numpy as np
 import pytest
@@ -14,6 +15,14 @@ from gpu_util import err_summary, sample_pixels, scene, score_rel_err
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-3
+
+
+@pytest.fixture(params=["ql", "jacobi"])
+def solver(request):
+    L_ = hs.lib()
+    L_.hsad_internal_dwest_solver(1 if request.param == "jacobi" else 0)
+    yield request.param
+    L_.hsad_internal_dwest_solver(0)
 
 
 def _gpu(x, inner, outer):
@@ -27,7 +36,7 @@ def _gpu(x, inner, outer):
 @pytest.mark.parametrize("H,W,levels,inner,outer", [
     (26, 21, 4, 3, 11), (17, 19, 3, 3, 11), (9, 10, 2, 3, 11), (20, 20, 6, 5, 13),
     (15, 33, 5, 1, 7), (6, 5, 4, 3, 5)])
-def test_dwest_parity(H, W, levels, inner, outer):
+def test_dwest_parity(H, W, levels, inner, outer, solver):
     s = scene(H * W + levels, H, W, 224)
     x = oracle.dwt_approx(s.cube, levels).astype(np.float32)
     gs, gl, gn = _gpu(x, inner, outer)
@@ -41,7 +50,7 @@ def test_dwest_parity(H, W, levels, inner, outer):
     assert el.max() <= TOL
 
 
-@pytest.mark.parametrize("levels", [4, 3])
+@pytest.mark.parametrize("levels", [4, 3, 2])
 def test_dwest_full_size_sampled(levels):
     import torch
     from paper_1201_2025_amd import synth
@@ -59,3 +68,23 @@ def test_dwest_full_size_sampled(levels):
     print("C3 level", levels, err_summary(e), flush=True)
     assert e.max() <= TOL
     assert np.array_equal(gn.cpu().numpy().ravel()[idx], rn)
+
+
+def test_dwest_degenerate_and_short_spectra(solver):
+    # L' = 1 and 2 (no reflection), a constant cube (C_diff = 0: no positive eigenvalue,
+    # score 0) and a cube constant in one band
+    for Lp in (1, 2, 3):
+        x = np.random.default_rng(Lp).standard_normal((12, 13, Lp)).astype(np.float32)
+        gs, gl, gn = _gpu(x, 3, 7)
+        rs, rl, rn = oracle.dwest(x.astype(np.float64), 3, 7)
+        assert np.array_equal(gn, rn)
+        assert score_rel_err(gs, rs).max() <= TOL
+    x = np.full((10, 11, 6), 0.25, dtype=np.float32)
+    gs, gl, gn = _gpu(x, 3, 7)
+    assert (gn == 0).all() and (gs == 0).all()
+    x = np.random.default_rng(9).standard_normal((10, 11, 6)).astype(np.float32)
+    x[..., 2] = 1.5
+    gs, gl, gn = _gpu(x, 3, 7)
+    rs, rl, rn = oracle.dwest(x.astype(np.float64), 3, 7)
+    assert np.array_equal(gn, rn)
+    assert score_rel_err(gs, rs).max() <= TOL
