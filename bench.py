@@ -308,26 +308,21 @@ def main():
     lrx = torch.empty((H, W), dtype=torch.float32, device=dev)
     dwrx = torch.empty((H, W), dtype=torch.float32, device=dev)
     mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
-    ws_bytes = hs.hsad_workspace_bytes(hs.HSAD_OP_LRX_DWRX, H, W, Lp, inner, outer, load)
-    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
-    th_ws = torch.empty(hs.hsad_threshold_workspace_bytes(npix), dtype=torch.uint8, device=dev)
+    det_ws = torch.empty(hs.hsad_detect_workspace_bytes(H, W, Lp, inner, outer, load), dtype=torch.uint8,
+                         device=dev)
     th_out = torch.empty(4, dtype=torch.float64, device=dev)
 
-    def step(i, ev=None, split=False):
-        # ev: events around the DWT (its launch duration for the roofline); split: also
-        # after the detector (per-kernel split, recorded outside the timed region only,
-        # since every event adds a few microseconds to the step)
+    def step(i, ev=None):
+        # ev: events around the DWT, whose launch duration the roofline needs (each event
+        # adds a few microseconds to the step, so there are no others in the timed region)
         if ev is not None:
             ev[0].record()
         hs.hsad_dwt(cubes[i & 1], J, out=approx)
         if ev is not None:
             ev[1].record()
-        hs.hsad_lrx_dwrx(approx, inner, outer, load, lrx=lrx, dwrx=dwrx, ws=ws if ws_bytes else None)
-        if ev is not None and split:
-            ev[2].record()
-        hs.hsad_threshold(lrx, 3.0, stats=th_out, mask=mask, ws=th_ws)
-        if ev is not None and split:
-            ev[3].record()
+        # LRX + DWRX, then eq. (12) on the LRX map and the mask, in one library call
+        hs.hsad_detect(approx, inner, outer, load, 3.0, lrx=lrx, dwrx=dwrx, stats=th_out, mask=mask,
+                       ws=det_ws)
 
     for i in range(args.warmup):
         step(i)
@@ -346,14 +341,14 @@ def main():
     ms_step = t0.elapsed_time(t1) / args.steps
     dwt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     value = npix / (ms_step * 1e-3)
-    # per-kernel split from a separate instrumented pass (not part of the timed region)
+    # the detection call's share, from a separate instrumented pass (not the timed region)
     nsplit = min(args.steps, 50)
-    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nsplit)]
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nsplit)]
     for i in range(nsplit):
-        step(i, sev[i], split=True)
+        step(i, sev[i])
+        sev[i][2].record()
     torch.cuda.synchronize()
     det_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in sev]))
-    thr_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in sev]))
 
     if args.profile:
         # plain copies of known size: what FETCH_SIZE / WRITE_SIZE read for 256 MiB moved
@@ -363,7 +358,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"profile_steps": args.steps, "ms_per_step": ms_step, "dwt_ms": dwt_ms,
-                          "lrx_dwrx_ms": det_ms, "threshold_ms": thr_ms}))
+                          "detect_ms": det_ms}))
         return
 
     # dominant kernel: the DWT, bound by HBM.  Algorithmic bytes per launch: read the cube
@@ -515,7 +510,7 @@ def main():
                                "outer 15 + eq. 12 mask" % (J, Lp),
                    "H": H, "W": W, "L": L, "levels": J, "Lp": Lp, "inner": inner,
                    "outer": outer, "load_rel": load, "storage": "f32", "parallelism": "1 GPU"},
-        "kernel_ms": {"dwt": dwt_ms, "lrx_dwrx": det_ms, "threshold": thr_ms},
+        "kernel_ms": {"dwt": dwt_ms, "detect": det_ms},
         "wall_s_timed": wall,
         "roofline": {"bound": "hbm", "kernel": dwt_kernel, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,

@@ -134,9 +134,30 @@ int hsad_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp,
                   const hsad_window_params *p, float *lrx, float *dwrx, void *ws,
                   size_t ws_bytes, hipStream_t stream);
 
+/* Device workspace for hsad_detect (bytes). */
+size_t hsad_detect_workspace_bytes(int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p);
+
+/* The detection step in one call: LRX (eq. 1) and DWRX (eq. 5) as hsad_lrx_dwrx, then the
+ * adaptive threshold of eq. (12) on the LRX map (Sec. 5.3.2) and its mask, as
+ * hsad_threshold.  On the L' <= 8 box path the detector kernel also leaves the (count,
+ * mean, M2) of each 16 x 16 tile's finite LRX scores, which replaces the threshold's own
+ * statistics pass; the tiles are merged in a fixed order (deterministic).
+ *   lrx    : device, H*W float32 (required); dwrx: device, H*W float32 or NULL
+ *   stats  : device, 4 doubles written {count, mu_d, sigma_d, tau}
+ *   mask   : device, H*W uint8 written (lrx > tau), or NULL
+ *   ws     : device workspace of at least hsad_detect_workspace_bytes
+ * Errors: as hsad_lrx_dwrx and hsad_threshold. */
+int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,
+                size_t ws_bytes, hipStream_t stream);
+
 /* DWEST, eqs. (2)-(4): C_diff = C_inner - C_annulus, m_diff = m_inner - m_annulus.
- * The eigenvectors of C_diff with eigenvalue > 1e-12 * max|eigenvalue| ("positive")
- * are found by an FP64 cyclic Jacobi.  Outputs, each a device [y][x] array:
+ * The eigenvalues of C_diff and the projections v_i^T m_diff come from an FP64
+ * Householder tridiagonalisation followed by the implicit QL iteration, with every
+ * transform also applied to m_diff (the eigenvectors are never formed); the eigenvalues
+ * > 1e-12 * max|eigenvalue| are "positive".  A pixel whose QL iteration does not converge
+ * within 64 sweeps per eigenvalue gets NaN scores and npos = -1.  Outputs, each a device
+ * [y][x] array:
  *   scores         : ||V_P^T m_diff||_2 (invariant to eigenvector signs), float32
  *   scores_literal : sum_P |v_i^T m_diff| (eq. 4 with each v_i signed so that its
  *                    projection is >= 0), float32, may be NULL

@@ -84,6 +84,9 @@ SIGNATURES = [
     ("hsad_lrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_dwrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_lrx_dwrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_detect_workspace_bytes", ctypes.c_size_t, [_i64, _i64, _i64, _P]),
+    ("hsad_detect", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.c_double, _vp, _vp, _vp, _vp, _vp,
+                                   ctypes.c_size_t, _vp]),
     ("hsad_dwest", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_threshold_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("hsad_threshold", ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -310,6 +313,44 @@ def hsad_dwrx(x, inner: int, outer: int, load_rel: float = 1e-6, precision: int 
     _check("hsad_dwrx", lib().hsad_dwrx(px, H, W, Lp, ctypes.byref(p), _dev(out, "out", torch.float32),
                                         pws, nws, _stream(stream)))
     return out
+
+
+def hsad_detect_workspace_bytes(H: int, W: int, Lp: int, inner: int, outer: int,
+                                load_rel: float = 1e-6, precision: int = HSAD_PREC_AUTO) -> int:
+    p = _params(inner, outer, load_rel, precision)
+    return int(lib().hsad_detect_workspace_bytes(int(H), int(W), int(Lp), ctypes.byref(p)))
+
+
+def hsad_detect(x, inner: int, outer: int, load_rel: float = 1e-6, z_alpha: float = 3.0,
+                precision: int = HSAD_PREC_AUTO, lrx=None, dwrx=True, stats=None, mask=True, ws=None,
+                stream=None):
+    """LRX + DWRX of the reduced cube x and the eq. (12) threshold + mask of the LRX map in one
+    call.  Returns (lrx, dwrx or None, stats {count, mu, sigma, tau}, mask or None); pass
+    tensors to write into them, dwrx/mask False to skip."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    p = _params(inner, outer, load_rel, precision)
+    dev = x.device
+    lrx = torch.empty((H, W), dtype=torch.float32, device=dev) if lrx is None else lrx
+    if dwrx is True:
+        dwrx = torch.empty((H, W), dtype=torch.float32, device=dev)
+    elif dwrx is False:
+        dwrx = None
+    if mask is True:
+        mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    elif mask is False:
+        mask = None
+    stats = torch.empty(4, dtype=torch.float64, device=dev) if stats is None else stats
+    if ws is None:
+        ws = torch.empty(max(1, hsad_detect_workspace_bytes(H, W, Lp, inner, outer, load_rel, precision)),
+                         dtype=torch.uint8, device=dev)
+    rc = lib().hsad_detect(px, H, W, Lp, ctypes.byref(p), float(z_alpha), _dev(lrx, "lrx", torch.float32),
+                           _ptr_or_null(dwrx, "dwrx", torch.float32), _dev(stats, "stats", torch.float64),
+                           _ptr_or_null(mask, "mask", torch.uint8), _dev(ws, "ws"),
+                           ws.numel() * ws.element_size(), _stream(stream))
+    _check("hsad_detect", rc)
+    return lrx, dwrx, stats, mask
 
 
 def hsad_dwest(x, inner: int, outer: int, literal: bool = True, npos: bool = True, ws=None,

@@ -294,6 +294,54 @@ int hsad_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp,
     return lrx_dwrx_common("hsad_lrx_dwrx", x, H, W, Lp, p, lrx, dwrx, ws, ws_bytes, stream);
 }
 
+// Workspace of hsad_detect: eq. (12) partials (one per 16 x 16 tile on the box path, else
+// the threshold's blocks) and the fold buffer, 256-byte aligned, then what hsad_lrx_dwrx
+// needs.
+static size_t detect_head_bytes(int64_t H, int64_t W)
+{
+    size_t np = box_tiles(H, W);
+    const size_t tb = hsad_threshold_workspace_bytes(H * W) / (3 * sizeof(double));
+    if (np < tb) np = tb;
+    const size_t b = (np + threshold_fold_doubles() / 3) * 3 * sizeof(double);
+    return (b + 255) & ~(size_t)255;
+}
+
+size_t hsad_detect_workspace_bytes(int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p)
+{
+    if (H < 1 || W < 1) return 0;
+    const int op = p && p->inner > 0 ? HSAD_OP_LRX_DWRX : HSAD_OP_LRX;
+    return detect_head_bytes(H, W) + hsad_workspace_bytes(op, H, W, Lp, p);
+}
+
+int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,
+                size_t ws_bytes, hipStream_t stream)
+{
+    clear_error();
+    Windows w;
+    int rc = check_windows("hsad_detect", p, H, W, Lp, dwrx != nullptr, &w);
+    if (rc) return rc;
+    if (!x || !lrx || !stats) return fail(HSAD_EINVAL, "hsad_detect: x, lrx and stats are required");
+    if (!std::isfinite(z_alpha)) return fail(HSAD_EINVAL, "hsad_detect: z_alpha not finite");
+    const size_t head = detect_head_bytes(H, W);
+    if (!ws || ws_bytes < head) return fail(HSAD_ENOMEM, "hsad_detect: workspace too small");
+    double *part = (double *)ws;
+    const size_t np = (head / (3 * sizeof(double))) - threshold_fold_doubles() / 3;
+    double *fold = part + 3 * np;
+    const int64_t n = H * W;
+    if (exact(p->precision) && box_supported(Lp, w)) {
+        // the box kernel leaves one partial per tile: no separate statistics pass
+        rc = box_lrx_dwrx_launch(x, H, W, Lp, w, p->load_rel, lrx, dwrx, stream, part);
+        if (rc) return rc;
+        return threshold_from_partials(lrx, n, part, (int64_t)box_tiles(H, W), z_alpha, stats, mask, fold,
+                                       stream);
+    }
+    rc = lrx_dwrx_common("hsad_detect", x, H, W, Lp, p, lrx, dwrx, (char *)ws + head, ws_bytes - head,
+                         stream);
+    if (rc) return rc;
+    return hsad_threshold(lrx, n, z_alpha, stats, mask, part, head, stream);
+}
+
 int hsad_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
                float *scores, float *scores_literal, int32_t *npos, void *ws,
                size_t ws_bytes, hipStream_t stream)

@@ -41,10 +41,11 @@ __global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restric
                                                           int W, int R, int RI, int has_inner,
                                                           double load_rel,
                                                           float *__restrict__ lrx,
-                                                          float *__restrict__ dwrx)
+                                                          float *__restrict__ dwrx,
+                                                          double *__restrict__ part)
 {
     extern __shared__ double smem[];
-    box_tile<LP, GCMAX>(x, H, W, R, RI, has_inner, load_rel, lrx, dwrx, blockIdx.y, blockIdx.x, smem);
+    box_tile<LP, GCMAX>(x, H, W, R, RI, has_inner, load_rel, lrx, dwrx, blockIdx.y, blockIdx.x, smem, part);
 }
 
 static size_t box_smem_lp(int64_t Lp, int R)
@@ -74,28 +75,28 @@ static int g_box_gc = 0;   // 0: default feature chunk; 15 / 8 / 5 forced (tunin
 
 template <int LP, int GCMAX>
 static int box_launch_gc(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
-                         float *lrx, float *dwrx, hipStream_t s)
+                         float *lrx, float *dwrx, double *part, hipStream_t s)
 {
     const size_t sh = box_smem<LP, GCMAX>(w.ro);
     if (int rc = allow_lds((const void *)box_lrx_dwrx_kernel<LP, GCMAX>, sh, "box_lrx_dwrx_kernel"))
         return rc;
     dim3 grid((unsigned)((W + TX - 1) / TX), (unsigned)((H + TY - 1) / TY)), block(NT);
     hipLaunchKernelGGL((box_lrx_dwrx_kernel<LP, GCMAX>), grid, block, sh, s, x, (int)H, (int)W, w.ro,
-                       w.ri, w.inner > 0 ? 1 : 0, load_rel, lrx, dwrx);
+                       w.ri, w.inner > 0 ? 1 : 0, load_rel, lrx, dwrx, part);
     return check_launch("box_lrx_dwrx_kernel");
 }
 
 template <int LP>
 static int box_launch(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
-                      float *lrx, float *dwrx, hipStream_t s)
+                      float *lrx, float *dwrx, double *part, hipStream_t s)
 {
     // default chunk width: measured fastest on gfx950 at 512 x 512 (5 features keep four
     // workgroups resident per CU; 8 for L' = 5..7, where 5 spills registers)
     const int gc = g_box_gc ? g_box_gc : ((LP >= 5 && LP <= 7) ? 8 : 5);
     switch (gc) {
-    case 8: return box_launch_gc<LP, 8>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 15: return box_launch_gc<LP, 15>(x, H, W, w, load_rel, lrx, dwrx, s);
-    default: return box_launch_gc<LP, 5>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 8: return box_launch_gc<LP, 8>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 15: return box_launch_gc<LP, 15>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    default: return box_launch_gc<LP, 5>(x, H, W, w, load_rel, lrx, dwrx, part, s);
     }
 }
 
@@ -104,22 +105,24 @@ int wave_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const
 bool wave_supported(int64_t Lp, const Windows &w);
 int box_variant();
 
+size_t box_tiles(int64_t H, int64_t W) { return (size_t)((H + TY - 1) / TY) * (size_t)((W + TX - 1) / TX); }
+
 int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
-                        double load_rel, float *lrx, float *dwrx, hipStream_t s)
+                        double load_rel, float *lrx, float *dwrx, hipStream_t s, double *part)
 {
     if (H > (1 << 24) || W > (1 << 24)) return fail(HSAD_EUNSUPPORTED, "box path: image too large");
     const int v = box_variant();
-    if (v == 2 && wave_supported(Lp, w))
+    if (v == 2 && !part && wave_supported(Lp, w))
         return wave_lrx_dwrx_launch(x, H, W, Lp, w, load_rel, lrx, dwrx, s);
     switch (Lp) {
-    case 1: return box_launch<1>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 2: return box_launch<2>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 3: return box_launch<3>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 4: return box_launch<4>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 5: return box_launch<5>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 6: return box_launch<6>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 7: return box_launch<7>(x, H, W, w, load_rel, lrx, dwrx, s);
-    case 8: return box_launch<8>(x, H, W, w, load_rel, lrx, dwrx, s);
+    case 1: return box_launch<1>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 2: return box_launch<2>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 3: return box_launch<3>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 4: return box_launch<4>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 5: return box_launch<5>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 6: return box_launch<6>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 7: return box_launch<7>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    case 8: return box_launch<8>(x, H, W, w, load_rel, lrx, dwrx, part, s);
     default: return fail(HSAD_EUNSUPPORTED, "box path: L' > 8");
     }
 }

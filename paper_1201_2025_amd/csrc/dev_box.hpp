@@ -67,10 +67,11 @@ __device__ __forceinline__ int clip_count(int c, int r, int n)
 // feat(): L' linear, the upper triangle of products, the non-finite count), loading,
 // Cholesky and both scores for output pixel (py, px).
 template <int LP, int GT>
-__device__ __forceinline__ void box_score(const float *__restrict__ x, int H, int W, int R, int RI,
-                                          int has_inner, double load_rel, const double *ref,
-                                          const double *S, double *sin_lin, double in_bad, int py,
-                                          int px, float *__restrict__ lrx, float *__restrict__ dwrx)
+// Returns the LRX score it wrote (NaN when lrx is NULL).
+__device__ __forceinline__ float box_score(const float *__restrict__ x, int H, int W, int R, int RI,
+                                           int has_inner, double load_rel, const double *ref,
+                                           const double *S, double *sin_lin, double in_bad, int py,
+                                           int px, float *__restrict__ lrx, float *__restrict__ dwrx)
 {
     constexpr int G = GT - 1;
     // 3. statistics of the annulus, loading, Cholesky, scores
@@ -115,6 +116,7 @@ __device__ __forceinline__ void box_score(const float *__restrict__ x, int H, in
         }
     }
     const size_t o = (size_t)py * W + px;
+    float lrx_v = NAN;
     if (lrx) {
         const float *pc = x + o * LP;            // raw centre pixel
         double z[LP], s = 0.0;
@@ -126,7 +128,8 @@ __device__ __forceinline__ void box_score(const float *__restrict__ x, int H, in
             z[i] = t * Lm[i][i];
             s += z[i] * z[i];
         }
-        lrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
+        lrx_v = (pd && !ann_bad) ? (float)s : INFINITY;
+        lrx[o] = lrx_v;
     }
     if (dwrx) {
         if (in_bad > 0.5) {
@@ -155,12 +158,43 @@ __device__ __forceinline__ void box_score(const float *__restrict__ x, int H, in
         }
         dwrx[o] = (pd && !ann_bad) ? (float)s : INFINITY;
     }
+    return lrx_v;
+}
+
+// Deterministic block sum of 256 threads (fixed shuffle tree per wavefront, then the four
+// wavefront sums in order); red holds 4 doubles of LDS; the result is valid in every thread.
+__device__ __forceinline__ double box_block_sum(double v, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return t;
+}
+
+// (count, mean, centred sum of squares) of the finite values v of a tile's threads, two
+// passes in FP64 -> out[0..2].  The partial statistics of eq. (12) for one tile.
+__device__ inline void box_tile_stats(float v, bool valid, double *out, double *red)
+{
+    const bool fin = valid && isfinite(v);
+    const double c = box_block_sum(fin ? 1.0 : 0.0, red);
+    const double sum = box_block_sum(fin ? (double)v : 0.0, red);
+    const double mean = c > 0.0 ? sum / c : 0.0;
+    const double d = fin ? (double)v - mean : 0.0;
+    const double m2 = box_block_sum(d * d, red);
+    if (threadIdx.x == 0) {
+        out[0] = c;
+        out[1] = mean;
+        out[2] = m2;
+    }
 }
 
 template <int LP, int GCMAX>
 __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R, int RI,
                                 int has_inner, double load_rel, float *__restrict__ lrx,
-                                float *__restrict__ dwrx, int by, int bx, double *smem)
+                                float *__restrict__ dwrx, int by, int bx, double *smem,
+                                double *__restrict__ part = nullptr)
 {
     using C = BoxCfg<LP, GCMAX>;
     const int EX = TX + 2 * R, EY = TY + 2 * R;
@@ -295,8 +329,13 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
         }
     }
 
-    if (py >= H || px >= W) return;
-    box_score<LP, C::GT>(x, H, W, R, RI, has_inner, load_rel, ref, S, sin_lin, in_bad, py, px, lrx, dwrx);
+    const bool inside = py < H && px < W;
+    float v = NAN;
+    if (inside)
+        v = box_score<LP, C::GT>(x, H, W, R, RI, has_inner, load_rel, ref, S, sin_lin, in_bad, py, px, lrx,
+                                 dwrx);
+    // eq. (12) partials of this tile's LRX scores (the LDS tile is free again here)
+    if (part) box_tile_stats(v, inside, part + 3 * ((size_t)by * gridDim.x + bx), smem);
 }
 
 

@@ -74,9 +74,16 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
         double vp = 0.0, vy = 0.0;
         for (int i = k + 1 + lane; i < n; i += 64) {
             const double *row = A + (size_t)i * ld;
-            double p = 0.0;
-            for (int j = k + 1; j < n; ++j) p = fma(row[j], v[j], p);
-            p *= beta;
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;   // four chains hide the FMA latency
+            int j = k + 1;
+            for (; j + 3 < n; j += 4) {
+                p0 = fma(row[j], v[j], p0);
+                p1 = fma(row[j + 1], v[j + 1], p1);
+                p2 = fma(row[j + 2], v[j + 2], p2);
+                p3 = fma(row[j + 3], v[j + 3], p3);
+            }
+            for (; j < n; ++j) p0 = fma(row[j], v[j], p0);
+            const double p = beta * ((p0 + p1) + (p2 + p3));
             q[i] = p;
             vp = fma(v[i], p, vp);
             vy = fma(v[i], y[i], vy);
@@ -148,27 +155,43 @@ __global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, 
             g = D(m) - D(l) + E(l) / (g + (g >= 0.0 ? r : -r));
             double s = 1.0, c = 1.0, p = 0.0;
             bool underflow = false;
+            // the sweep reads d_i, e_i, y_i once each (prefetched one rotation ahead) and
+            // carries d_i+1 (still the value from before the sweep) and the rotated y_i+1
+            double dcar = D(m), ycar = Y(m);
+            double ei = E(m - 1), di = D(m - 1), yi = Y(m - 1);
             for (int i = m - 1; i >= l; --i) {
-                const double f = s * E(i), b = c * E(i);
-                r = hypot(f, g);
+                double en = 0.0, dn = 0.0, yn = 0.0;
+                if (i > l) {
+                    en = E(i - 1);
+                    dn = D(i - 1);
+                    yn = Y(i - 1);
+                }
+                const double f = s * ei, b = c * ei;
+                r = sqrt(fma(f, f, g * g));   // |f|, |g| stay far from the FP64 range limits here
                 E(i + 1) = r;
                 if (r == 0.0) {          // the chase split the matrix: restart at l
-                    D(i + 1) -= p;
+                    D(i + 1) = dcar - p;
+                    Y(i + 1) = ycar;
                     E(m) = 0.0;
                     underflow = true;
                     break;
                 }
-                s = f / r;
-                c = g / r;
-                g = D(i + 1) - p;
-                r = (D(i) - g) * s + 2.0 * c * b;
+                const double ir = 1.0 / r;
+                s = f * ir;
+                c = g * ir;
+                g = dcar - p;
+                r = (di - g) * s + 2.0 * c * b;
                 p = s * r;
                 D(i + 1) = g + p;
                 g = c * r - b;
-                const double yi = Y(i), yi1 = Y(i + 1);
-                Y(i + 1) = fma(s, yi, c * yi1);
-                Y(i) = fma(c, yi, -s * yi1);
+                Y(i + 1) = fma(s, yi, c * ycar);
+                ycar = fma(c, yi, -s * ycar);
+                dcar = di;
+                ei = en;
+                di = dn;
+                yi = yn;
             }
+            if (!underflow) Y(l) = ycar;
             if (underflow) continue;
             D(l) -= p;
             E(l) = g;

@@ -228,6 +228,41 @@ __global__ void auc_finish_kernel(int64_t n, const unsigned long long *npos_ctr,
     }
 }
 
+// Merges consecutive runs of partials, in order, down to at most kRedBlocks partials (one
+// thread per output partial).
+__global__ __launch_bounds__(256) void thr_fold_kernel(const double *__restrict__ part, int64_t nblk,
+                                                       int64_t run, int nout, double *__restrict__ out)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    double na = 0.0, ma = 0.0, Ma = 0.0;
+    const int64_t b0 = (int64_t)o * run, b1 = b0 + run < nblk ? b0 + run : nblk;
+    for (int64_t b = b0; b < b1; ++b) chan_merge(na, ma, Ma, part[3 * b], part[3 * b + 1], part[3 * b + 2]);
+    out[3 * o] = na;
+    out[3 * o + 1] = ma;
+    out[3 * o + 2] = Ma;
+}
+
+size_t threshold_fold_doubles() { return (size_t)kRedBlocks * 3; }
+
+int threshold_from_partials(const float *scores, int64_t n, const double *part, int64_t nblk, double z,
+                            double *stats, uint8_t *mask, double *fold, hipStream_t s)
+{
+    if (nblk > kRedBlocks) {
+        const int64_t run = (nblk + kRedBlocks - 1) / kRedBlocks;
+        const int nout = (int)((nblk + run - 1) / run);
+        hipLaunchKernelGGL(thr_fold_kernel, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, part, nblk,
+                           run, nout, fold);
+        part = fold;
+        nblk = nout;
+    }
+    int64_t mblk = (n + kRedThreads * 4 - 1) / (kRedThreads * 4);
+    if (mblk > kRedBlocks) mblk = kRedBlocks;
+    hipLaunchKernelGGL(thr_merge_mask_kernel, dim3((unsigned)mblk), dim3(kRedThreads), 0, s, scores, n,
+                       (int)nblk, part, z, stats, mask);
+    return check_launch("thr_merge_mask_kernel");
+}
+
 }  // namespace hsad
 
 using namespace hsad;

@@ -38,8 +38,20 @@ struct Windows {
 
 // ---- small-L' fused box-sum detector (box.hip) ----
 bool box_supported(int64_t Lp, const Windows &w);
+// part (optional): 3 doubles per 16 x 16 tile, row-major over tiles, receive the
+// (count, mean, M2) of the tile's finite LRX scores (eq. 12 partials; lrx must be set).
 int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
-                        double load_rel, float *lrx, float *dwrx, hipStream_t s);
+                        double load_rel, float *lrx, float *dwrx, hipStream_t s,
+                        double *part = nullptr);
+size_t box_tiles(int64_t H, int64_t W);
+
+// ---- eq. (12) from partial statistics (eval.hip) ----
+// Merges nblk (count, mean, M2) partials in a fixed order, writes stats {count, mu, sigma,
+// tau = mu + z sigma} and, if mask is set, mask = scores > tau.  fold: device scratch of
+// threshold_fold_doubles() doubles, used when nblk exceeds what one merge pass takes.
+size_t threshold_fold_doubles();
+int threshold_from_partials(const float *scores, int64_t n, const double *part, int64_t nblk, double z,
+                            double *stats, uint8_t *mask, double *fold, hipStream_t s);
 
 // ---- box-sum statistics for mid-size L' (boxg.hip) ----
 bool boxg_supported(int64_t Lp, const Windows &w);

@@ -121,6 +121,32 @@ def test_workspace_sizes():
     assert L.hsad_workspace_bytes(hs.HSAD_OP_DWEST, 64, 64, 4, ctypes.byref(p)) > 0
 
 
+def test_detect_arguments_and_workspace():
+    L = hs.lib()
+    p = _p(5, 15)
+    # box path: one (count, mean, M2) per 16 x 16 tile (at least the threshold's 1024
+    # blocks) plus the 1024-partial fold buffer, 256-byte aligned; no detector workspace
+    n = L.hsad_detect_workspace_bytes(512, 512, 4, ctypes.byref(p))
+    assert n == ((1024 + 1024) * 24 + 255) // 256 * 256
+    n2 = L.hsad_detect_workspace_bytes(2048, 2048, 4, ctypes.byref(p))
+    assert n2 == ((16384 + 1024) * 24 + 255) // 256 * 256
+    # generic path: the head plus hsad_workspace_bytes
+    g = L.hsad_detect_workspace_bytes(64, 64, 14, ctypes.byref(p))
+    assert g == ((1024 + 1024) * 24 + 255) // 256 * 256 + 64 * 64 * 17 * 14 * 8
+    stats = FAKE
+    assert L.hsad_detect(FAKE, 8, 8, 4, ctypes.byref(p), 3.0, None, FAKE, stats, FAKE, FAKE, 1 << 20,
+                         None) == hs.HSAD_EINVAL                       # lrx required
+    assert L.hsad_detect(FAKE, 8, 8, 4, ctypes.byref(p), 3.0, FAKE, FAKE, None, FAKE, FAKE, 1 << 20,
+                         None) == hs.HSAD_EINVAL                       # stats required
+    assert L.hsad_detect(FAKE, 8, 8, 4, ctypes.byref(p), float("inf"), FAKE, FAKE, stats, FAKE, FAKE,
+                         1 << 20, None) == hs.HSAD_EINVAL
+    assert L.hsad_detect(FAKE, 8, 8, 4, ctypes.byref(p), 3.0, FAKE, FAKE, stats, FAKE, FAKE, 16,
+                         None) == hs.HSAD_ENOMEM
+    q = _p(0, 9)
+    assert L.hsad_detect(FAKE, 8, 8, 4, ctypes.byref(q), 3.0, FAKE, FAKE, stats, FAKE, FAKE, 1 << 20,
+                         None) == hs.HSAD_EINVAL                       # DWRX needs an inner window
+
+
 def test_surrogate_dims_match_oracle():
     from oracle import mlp
     for Lp in (1, 4, 7, 14, 28, 56, 85):

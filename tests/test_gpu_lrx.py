@@ -289,3 +289,32 @@ def test_gram_step_against_window_stats(Lp, inner, outer, prec, tol):
             assert np.allclose(g[pix, Lp + 1], mi - mu, rtol=1e-12, atol=1e-12)
     print("gram prec", prec, "L'", Lp, "max normwise err %.3g" % worst)
     assert worst <= tol
+
+
+# hsad_detect: detector + eq. (12) threshold + mask in one call.  The maps must equal the
+# separate hsad_lrx_dwrx call bit for bit; tau must match the oracle's threshold of the
+# same LRX map to 1e-12 (the box path merges per-tile partials instead of the threshold's
+# own blocks, so only rounding differs); the mask must be exactly lrx > tau.
+@pytest.mark.parametrize("H,W,Lp,inner,outer", [(37, 29, 4, 5, 15), (600, 600, 4, 5, 15),
+                                                 (40, 33, 7, 3, 9), (23, 19, 14, 5, 15),
+                                                 (20, 21, 5, 0, 9)])
+def test_detect_matches_separate_calls(H, W, Lp, inner, outer):
+    import torch
+    x = _box_input(H, W, Lp) if Lp <= 8 else _reduced(H * W + Lp, H, W, Lp)[0]
+    if H == 37:
+        x = x.copy()
+        x[10, 10, 0] = np.inf         # an infinite LRX block must not enter the statistics
+    t = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    l0, d0 = hs.hsad_lrx_dwrx(t, inner, outer, 1e-6, lrx=True, dwrx=inner > 0)
+    l1, d1, st, m = hs.hsad_detect(t, inner, outer, 1e-6, 3.0, dwrx=inner > 0)
+    torch.cuda.synchronize()
+    l0, l1 = l0.cpu().numpy().ravel(), l1.cpu().numpy().ravel()
+    assert np.array_equal(l0, l1, equal_nan=True)
+    if inner > 0:
+        assert np.array_equal(d0.cpu().numpy(), d1.cpu().numpy(), equal_nan=True)
+    st = st.cpu().numpy()
+    fin = np.isfinite(l1)
+    assert st[0] == fin.sum()
+    tau = oracle.threshold(l1, 3.0)
+    assert abs(st[3] - tau) <= 1e-12 * abs(tau)
+    assert np.array_equal(m.cpu().numpy().ravel(), (l1.astype(np.float64) > st[3]).astype(np.uint8))
