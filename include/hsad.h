@@ -111,7 +111,7 @@ size_t hsad_workspace_bytes(int op, int64_t H, int64_t W, int64_t Lp,
  * mu, C = mean and 1/n covariance of the annulus samples,
  * score = (r - mu)^T (C + lambda I)^-1 (r - mu).
  * Exact precision (AUTO / FP64) computes the statistics in FP64: by sliding box sums for
- * L' <= 8 (fused with the factorisation) and for L' <= 64 with outer <= 31 (per-pixel
+ * L' <= 8 (fused with the factorisation) and for L' <= 128 with outer <= 31 (per-pixel
  * records in the workspace, then an FP64 Cholesky per pixel), otherwise by a per-pixel
  * matrix-core FP64 Gram.  The FP32 / BF16 / FP16 precisions always use the Gram.
  *   x      : device, H*W*Lp float32 reduced (or full-band) cube

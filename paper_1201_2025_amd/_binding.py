@@ -139,6 +139,8 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_box_chunk", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwt_nt", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwest_solver", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_chol_cb", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_boxg_rb", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_variant", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     ("hsad_internal_generic_force", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_boxg_resident_kb", ctypes.c_int, [ctypes.c_int]),

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void chol_wave_kernel(const double *__restrict
 }
 
 // G lanes per pixel (register-resident rows), 256 / G pixels per workgroup
-template <int G>
+template <int G, int CB>
 __global__ __launch_bounds__(256) void chol_group_kernel(const double *__restrict__ ws, int Lp, int npix, int64_t pix0,
                                                          double load_rel, float *__restrict__ lrx,
                                                          float *__restrict__ dwrx, const int32_t *__restrict__ idx,
@@ -67,12 +67,15 @@ __global__ __launch_bounds__(256) void chol_group_kernel(const double *__restric
         active = p >= 0 && p < npix_img;    // listed index outside the image: skipped
     }
     __shared__ double colbuf[256];
-    chol_group_pixel<G>(ws + (size_t)(active ? local : 0) * stride, Lp, raw, load_rel, active,
+    chol_group_pixel<G, CB>(ws + (size_t)(active ? local : 0) * stride, Lp, raw, load_rel, active,
                         lrx ? lrx + p : nullptr, dwrx ? dwrx + p : nullptr,
                         colbuf + (threadIdx.x & ~(G - 1)));
 }
 
 size_t chol_smem(int64_t Lp) { return chol_smem_doubles((int)Lp) * sizeof(double); }
+
+// columns per unrolled block of the register-resident factorisation (64: fully unrolled)
+static int g_chol_cb = 16;
 
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
                 float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img, int raw)
@@ -81,15 +84,20 @@ int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel,
     if (Lp + 2 <= 64) {
         const int G = Lp + 2 <= 16 ? 16 : Lp + 2 <= 32 ? 32 : 64;
         dim3 grid((unsigned)(((int64_t)npix * G + 255) / 256));
-        if (G == 16)
-            hipLaunchKernelGGL(chol_group_kernel<16>, grid, dim3(256), 0, s, ws, (int)Lp, npix, pix0, load_rel, lrx,
-                               dwrx, idx, npix_img, raw, stride);
-        else if (G == 32)
-            hipLaunchKernelGGL(chol_group_kernel<32>, grid, dim3(256), 0, s, ws, (int)Lp, npix, pix0, load_rel, lrx,
-                               dwrx, idx, npix_img, raw, stride);
-        else
-            hipLaunchKernelGGL(chol_group_kernel<64>, grid, dim3(256), 0, s, ws, (int)Lp, npix, pix0, load_rel, lrx,
-                               dwrx, idx, npix_img, raw, stride);
+        const void *k = nullptr;
+#define HSAD_CG(g, cb) \
+    if (G == g && cb_sel == cb) k = (const void *)chol_group_kernel<g, cb>;
+        const int cb_sel = g_chol_cb;
+        HSAD_CG(16, 4) HSAD_CG(16, 8) HSAD_CG(16, 16) HSAD_CG(16, 64)
+        HSAD_CG(32, 4) HSAD_CG(32, 8) HSAD_CG(32, 16) HSAD_CG(32, 64)
+        HSAD_CG(64, 4) HSAD_CG(64, 8) HSAD_CG(64, 16) HSAD_CG(64, 64)
+#undef HSAD_CG
+        if (!k) return fail(HSAD_EINVAL, "chol_group_kernel: bad column block");
+        int Lpi = (int)Lp;
+        void *args[] = {&ws, &Lpi, &npix, &pix0, &load_rel, &lrx, &dwrx, (void *)&idx, &npix_img, &raw,
+                        (void *)&stride};
+        if (hipLaunchKernel(k, grid, dim3(256), args, 0, s) != hipSuccess)
+            return fail(HSAD_EHIP, "chol_group_kernel: launch failed");
         return check_launch("chol_group_kernel");
     }
     if (Lp <= 64) {
@@ -108,3 +116,10 @@ int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel,
 }
 
 }  // namespace hsad
+
+extern "C" int hsad_internal_chol_cb(int cb)
+{
+    if (cb != 4 && cb != 8 && cb != 16 && cb != 64) return HSAD_EINVAL;
+    hsad::g_chol_cb = cb;
+    return 0;
+}

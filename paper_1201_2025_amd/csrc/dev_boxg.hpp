@@ -1,4 +1,4 @@
-// dev_boxg.hpp -- window statistics by sliding box sums for mid-size L' (any L' up to 64),
+// dev_boxg.hpp -- window statistics by sliding box sums for mid-size L' (any L' up to 128),
 // the producer of the raw per-pixel records that the FP64 Cholesky kernel finalises.
 //
 // The annulus statistics of Sec. 2.2 (outer window minus inner window, clipped to the
@@ -32,9 +32,9 @@
 
 namespace hsad {
 
-constexpr int BG_TX = 16, BG_TY = 16, BG_NT = 256, BG_RB = 2;
+constexpr int BG_TX = 16, BG_TY = 16, BG_NT = 256, BG_RB = 4;   // RB: output rows per vertical job
 constexpr int BG_VS = 9;                 // odd LDS stride of the vertical-sum rows (>= 8 features)
-constexpr int BG_MAX_LP = 64, BG_MAX_R = 15;
+constexpr int BG_MAX_LP = 128, BG_MAX_R = 15;
 
 __host__ __device__ inline int bg_lpad(int Lp) { return (Lp + 3) & ~3; }
 
@@ -76,10 +76,10 @@ __device__ __forceinline__ int bg_clip(int c, int r, int n)
 
 // Window sums of NF features for the thread's pixel: S_in (inner window, when has_inner)
 // and S_out (outer window).  feat(t, f) evaluates the NF features of extended-tile sample t.
-// Vertical running sums per (column, 2-row block) into V; then one job per (tile row,
+// Vertical running sums per (column, block of RB rows) into V; then one job per (tile row,
 // feature) slides the horizontal window along the row in registers and stores the 16
 // window sums of that row in Hs; each thread finally reads its pixel's NF sums.
-template <int NF, class Feat>
+template <int NF, int RB, class Feat>
 __device__ inline void bg_window_sums(const Feat &feat, int EX, int R, int RI, int has_inner, double *V,
                                       double *Hs, double *S_in, double *S_out)
 {
@@ -88,8 +88,8 @@ __device__ inline void bg_window_sums(const Feat &feat, int EX, int R, int RI, i
     for (int g = 0; g < NF; ++g) S_in[g] = 0.0;
     for (int win = has_inner ? 0 : 1; win < 2; ++win) {
         const int h = win == 0 ? RI : R, eoff = R - h;
-        for (int job = tid; job < EX * (BG_TY / BG_RB); job += BG_NT) {
-            const int rb = job / EX, c = job - rb * EX, r0 = rb * BG_RB;
+        for (int job = tid; job < EX * (BG_TY / RB); job += BG_NT) {
+            const int rb = job / EX, c = job - rb * EX, r0 = rb * RB;
             double acc[NF];
 #pragma unroll
             for (int g = 0; g < NF; ++g) acc[g] = 0.0;
@@ -104,7 +104,7 @@ __device__ inline void bg_window_sums(const Feat &feat, int EX, int R, int RI, i
 #pragma unroll
             for (int g = 0; g < NF; ++g) vr[g] = acc[g];
 #pragma unroll
-            for (int r = 1; r < BG_RB; ++r) {
+            for (int r = 1; r < RB; ++r) {
                 double fa[NF], fb[NF];
                 feat((r0 + r + eoff + 2 * h) * EX + c, fa);
                 feat((r0 + r - 1 + eoff) * EX + c, fb);
@@ -191,6 +191,7 @@ __device__ inline void bg_stage_all(const float *__restrict__ x, int H, int W, i
 // One tile: writes the raw records of its pixels (rows y0.., columns x0..) to
 // rec + (pixel - pix0) * rec_stride, or, with pix0 < 0, to rec + (ty * 16 + tx) * rec_stride
 // (tile-local records, as the batch engine allocates them).
+template <int RB = BG_RB>
 __device__ inline void boxg_tile(const float *__restrict__ x, int H, int W, int Lp, int R, int RI, int has_inner,
                                  double *__restrict__ rec, int64_t pix0, int64_t rec_stride, int by, int bx,
                                  unsigned char *smem, int resident_kb)
@@ -260,7 +261,7 @@ __device__ inline void boxg_tile(const float *__restrict__ x, int H, int W, int 
             f[4] = last ? (double)bad[t] : 0.0;
         };
         double S_in[5], S_out[5];
-        bg_window_sums<5>(feat, EX, R, RI, has_inner, V, Hs, S_in, S_out);
+        bg_window_sums<5, RB>(feat, EX, R, RI, has_inner, V, Hs, S_in, S_out);
         if (valid) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -303,7 +304,7 @@ __device__ inline void boxg_tile(const float *__restrict__ x, int H, int W, int 
                 }
             };
             double S_in[8], S_out[8];
-            bg_window_sums<8>(feat, EX, R, RI, has_inner, V, Hs, S_in, S_out);
+            bg_window_sums<8, RB>(feat, EX, R, RI, has_inner, V, Hs, S_in, S_out);
             if (valid) {
 #pragma unroll
                 for (int a = 0; a < 2; ++a)

@@ -251,11 +251,11 @@ namespace hsad {
 // the rank-1 update of column c reads l_cj there (a broadcast read).  Same operations in
 // the same order per column as the unblocked factorisation of chol_pixel (loading added
 // before factorising).  All indices into the register row are compile-time constants
-// (loops over the G - 2 columns are unrolled; columns past L' are skipped by uniform
-// branches).  rec is the record of the pixel ((L'+2) x L' for Gram records, (L'+3) x L'
+// (loops over the G - 2 register columns are unrolled; the column loop itself is not, and
+// columns past L' are skipped by uniform branches).  rec is the record of the pixel ((L'+2) x L' for Gram records, (L'+3) x L'
 // for raw box-statistics records); col is this lane's group's G-double LDS buffer.
 // ------------------------------------------------------------------------------------
-template <int G>
+template <int G, int CB = 16>
 __device__ inline void chol_group_pixel(const double *__restrict__ rec, int Lp, int raw, double load_rel,
                                         bool active, float *lrx_out, float *dwrx_out, double *col)
 {
@@ -286,34 +286,42 @@ __device__ inline void chol_group_pixel(const double *__restrict__ rec, int Lp, 
         A[c] = v;
     }
     bool bad = false;
-#pragma unroll
-    for (int j = 0; j < CM; ++j) {
-        if (j < Lp) {
-            const double d = __shfl(A[j], base + j, 64);
-            bad = bad || !(d > 0.0);
-            const double inv = 1.0 / sqrt(d);
-            const double l = A[j] * inv;
-            if (r >= j) A[j] = l;
-            col[r] = l;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-#pragma unroll
-            for (int c = j + 1; c < CM; ++c) {
-                if (c < Lp) {
-                    const double lc = col[c];
-                    if (r >= c) A[c] -= l * lc;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
-    }
     double s = 0.0;
+    // Columns go in blocks of CB: the block loop is not unrolled (a fully unrolled G = 64
+    // body is over 100 KB of code, beyond the instruction cache), the CB columns inside a
+    // block are.  After each block the register row shifts left by CB, so column j0 + c of
+    // block j0 sits in A[c]: every register index stays a compile-time constant.  The
+    // eliminated element of the d / m rows is z_j of L z = d; its squares sum to the score.
+    for (int j0 = 0; j0 < Lp; j0 += CB) {
 #pragma unroll
-    for (int c = 0; c < CM; ++c)
-        if (c < Lp) s += A[c] * A[c];
+        for (int jj = 0; jj < CB; ++jj) {
+            const int j = j0 + jj;
+            if (j < Lp) {
+                const double aj = A[jj];
+                const double d = __shfl(aj, base + j, 64);
+                bad = bad || !(d > 0.0);
+                const double inv = 1.0 / sqrt(d);
+                const double l = aj * inv;
+                s = fma(l, l, s);
+                col[r] = l;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+                for (int c = jj + 1; c < CM; ++c) {
+                    if (j0 + c < Lp) {
+                        const double lc = col[j0 + c];
+                        if (r >= j0 + c) A[c] -= l * lc;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CM; ++c) A[c] = c + CB < CM ? A[c + CB] : 0.0;
+    }
     if (active && r == Lp && lrx_out) *lrx_out = bad ? INFINITY : (float)s;
     if (active && r == Lp + 1 && dwrx_out) *dwrx_out = bad ? INFINITY : (float)s;
 }

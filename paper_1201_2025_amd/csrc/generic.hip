@@ -71,14 +71,15 @@ int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Win
     if (prec == GP_FP64 && g_generic_force != 1 && boxg_supported(Lp, w)) {
         const int64_t bands = boxg_chunk_bands(H, W, Lp, ws_bytes);
         if (bands >= 1) {
+            double *recs = (double *)ws;
             const int64_t total = (H + 15) / 16;
             for (int64_t b0 = 0; b0 < total; b0 += bands) {
                 const int64_t nb = total - b0 < bands ? total - b0 : bands;
-                int rc = boxg_launch(x, H, W, Lp, w, (int)b0, (int)nb, (double *)ws, s);
+                int rc = boxg_launch(x, H, W, Lp, w, (int)b0, (int)nb, recs, s);
                 if (rc) return rc;
                 const int64_t y1 = (b0 + nb) * 16 < H ? (b0 + nb) * 16 : H;
                 const int64_t p0 = b0 * 16 * W, n = y1 * W - p0;
-                rc = chol_launch((double *)ws, Lp, (int)n, p0, load_rel, lrx, dwrx, s, nullptr, H * W, 1);
+                rc = chol_launch(recs, Lp, (int)n, p0, load_rel, lrx, dwrx, s, nullptr, H * W, 1);
                 if (rc) return rc;
             }
             return HSAD_OK;

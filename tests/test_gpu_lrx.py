@@ -110,7 +110,7 @@ GEN = [(23, 19, 14, 5, 15), (20, 17, 28, 3, 11), (12, 14, 56, 3, 11), (9, 11, 11
 @pytest.mark.parametrize("H,W,Lp,inner,outer", GEN)
 @pytest.mark.parametrize("stats", ["auto", "gram"])
 def test_generic_path_parity(H, W, Lp, inner, outer, stats):
-    # auto: sliding box statistics where they apply (L' <= 64, outer <= 31), else the Gram;
+    # auto: sliding box statistics where they apply (L' <= 128, outer <= 31), else the Gram;
     # gram: the matrix-core Gram forced for every shape
     if Lp in (14, 28, 56, 112, 224):
         x, _ = _reduced(H * W + Lp, H, W, Lp)
@@ -126,9 +126,9 @@ def test_generic_path_parity(H, W, Lp, inner, outer, stats):
 
 
 # box statistics for mid-size L': ragged tiles, the largest window it takes (outer 31),
-# no inner window, the largest L' (64), odd L'
+# no inner window, L' at the group-Cholesky limit (64) and past it (65, 112, 128), odd L'
 BOXG = [(37, 29, 14, 5, 15), (40, 35, 9, 5, 31), (33, 18, 13, 0, 9), (20, 19, 64, 3, 9), (17, 50, 23, 1, 7),
-        (70, 3, 12, 3, 11), (1, 1, 10, 0, 3)]
+        (70, 3, 12, 3, 11), (1, 1, 10, 0, 3), (18, 21, 112, 5, 15), (9, 13, 128, 3, 9), (12, 10, 65, 1, 7)]
 
 
 @pytest.mark.parametrize("H,W,Lp,inner,outer", BOXG)
