@@ -262,6 +262,19 @@ __device__ inline void chol_group_pixel(const double *__restrict__ rec, int Lp, 
     constexpr int CM = G - 2;                  // largest L' of this group size
     const int lane = threadIdx.x & 63, r = lane & (G - 1), base = lane & ~(G - 1);
     const bool row_in = active && r < Lp + 2;
+    // Touch every 128-byte line of the record first with independent loads (one round trip
+    // to memory for the whole record); the row loads below, which run one after another,
+    // then hit the cache.
+    if constexpr (G >= 32) {
+        const int nl = (int)(((size_t)(raw ? Lp + 3 : Lp + 2) * Lp * sizeof(double) + 127) / 128);
+#pragma unroll
+        for (int k = 0; k < (G == 64 ? 4 : 2); ++k) {
+            int line = r + G * k;
+            line = line < nl ? line : nl - 1;
+            const double t = rec[(size_t)line * 16];
+            asm volatile("" ::"v"(t));
+        }
+    }
     double mur = 0.0;
     if (raw && active && r < Lp) mur = rec[(size_t)(Lp + 2) * Lp + r];
     // diagonal for the trace (rows < L')
@@ -307,11 +320,14 @@ __device__ inline void chol_group_pixel(const double *__restrict__ rec, int Lp, 
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                // rank-1 update of the rows below: rows above column j0 + c take a zero
+                // multiplier instead of a branch (their entries there are never read)
 #pragma unroll
                 for (int c = jj + 1; c < CM; ++c) {
                     if (j0 + c < Lp) {
                         const double lc = col[j0 + c];
-                        if (r >= j0 + c) A[c] -= l * lc;
+                        const double m = r >= j0 + c ? l : 0.0;
+                        A[c] = fma(-m, lc, A[c]);
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
