@@ -216,20 +216,23 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
         }
     }
 
-    // 1. halo tile
+    // 1. halo tile.  The loads are unconditional, from coordinates clamped into the image,
+    //    and the outside samples are dropped by selects afterwards: a load under a
+    //    lane-dependent branch whose value is used inside it waits for its round trip
+    //    before the next iteration's loads are issued.
+#pragma unroll 4
     for (int t = tid; t < EY * EX; t += NT) {
         const int ey = t / EX, ex = t - ey * EX;
         const int gy = y0 - R + ey, gx = x0 - R + ex;
+        const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        const int cy = gy < 0 ? 0 : gy >= H ? H - 1 : gy, cx = gx < 0 ? 0 : gx >= W ? W - 1 : gx;
+        const float *src = x + ((size_t)cy * W + cx) * LP;
         float v[LP];
-        bool ok = false, fin = true;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            const float *src = x + ((size_t)gy * W + gx) * LP;
-            ok = true;
+        bool fin = true;
 #pragma unroll
-            for (int i = 0; i < LP; ++i) {
-                v[i] = src[i];
-                fin = fin && isfinite(v[i]);
-            }
+        for (int i = 0; i < LP; ++i) {
+            v[i] = src[i];
+            fin = fin && isfinite(v[i]);
         }
         float *dst = xs + (size_t)t * LP;
 #pragma unroll

@@ -148,19 +148,35 @@ __device__ inline void bg_stage(const float *__restrict__ x, int H, int W, int L
                                 int y0, int x0, int b0, int stride, const double *ref, float *dst, float *bad,
                                 bool mark)
 {
+    // Eight elements per thread and pass: the eight loads are issued unconditionally (from
+    // coordinates clamped into the image) before any of their values is used, so their
+    // round trips overlap; flags are OR-ed in with LDS atomics, which need no branch.
+    constexpr int K = 8;
     const int n = EY * EX * NB;
-#pragma unroll 4
-    for (int e = threadIdx.x; e < n; e += BG_NT) {
-        const int t = e / NB, q = e - t * NB;     // NB is 2 or 4: shifts
-        const int ey = t / EX, ex = t - ey * EX;
-        const int gy = y0 - R + ey, gx = x0 - R + ex, b = b0 + q;
-        float v = (float)ref[b];
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W && b < Lp) {
-            const float u = x[((size_t)gy * W + gx) * Lp + b];
-            if (isfinite(u)) v = u;
-            else if (mark) bad[t] = 1.0f;
+    for (int e0 = threadIdx.x; e0 < n; e0 += K * BG_NT) {
+        float u[K];
+        bool ok[K];
+        int tt[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = e0 + k * BG_NT, ec = e < n ? e : n - 1;
+            const int t = ec / NB, q = ec - t * NB;     // NB is 2 or 4: shifts
+            const int ey = t / EX, ex = t - ey * EX;
+            const int gy = y0 - R + ey, gx = x0 - R + ex, b = b0 + q;
+            ok[k] = e < n && gy >= 0 && gy < H && gx >= 0 && gx < W && b < Lp;
+            const int cy = gy < 0 ? 0 : gy >= H ? H - 1 : gy, cx = gx < 0 ? 0 : gx >= W ? W - 1 : gx;
+            u[k] = x[((size_t)cy * W + cx) * Lp + (b < Lp ? b : Lp - 1)];
+            tt[k] = ec;
         }
-        dst[t * stride + q] = v;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (e0 + k * BG_NT < n) {
+                const int t = tt[k] / NB, q = tt[k] - t * NB;
+                const bool fin = isfinite(u[k]);
+                if (mark) atomicOr(reinterpret_cast<unsigned *>(bad + t), ok[k] && !fin ? 0x3f800000u : 0u);
+                dst[t * stride + q] = ok[k] && fin ? u[k] : (float)ref[b0 + q];
+            }
+        }
     }
 }
 
@@ -173,18 +189,33 @@ __device__ inline void bg_stage_all(const float *__restrict__ x, int H, int W, i
     const int per_row = EX * Lpad, n = EY * per_row;
     const uint32_t m_row = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)per_row - 1) / (uint64_t)per_row);
     const uint32_t m_lp = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)Lpad - 1) / (uint64_t)Lpad);
-#pragma unroll 4
-    for (int e = threadIdx.x; e < n; e += BG_NT) {
-        const int ey = (int)__umulhi((uint32_t)e, m_row), rem = e - ey * per_row;
-        const int ex = (int)__umulhi((uint32_t)rem, m_lp), b = rem - ex * Lpad;
-        const int gy = y0 - R + ey, gx = x0 - R + ex;
-        float v = (float)ref[b];
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W && b < Lp) {
-            const float u = x[((size_t)gy * W + gx) * Lp + b];
-            if (isfinite(u)) v = u;
-            else bad[ey * EX + ex] = 1.0f;
+    // eight elements per thread and pass, loads first (as bg_stage)
+    constexpr int K = 8;
+    for (int e0 = threadIdx.x; e0 < n; e0 += K * BG_NT) {
+        float u[K];
+        bool ok[K];
+        int tb[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = e0 + k * BG_NT, ec = e < n ? e : n - 1;
+            const int ey = (int)__umulhi((uint32_t)ec, m_row), rem = ec - ey * per_row;
+            const int ex = (int)__umulhi((uint32_t)rem, m_lp), b = rem - ex * Lpad;
+            const int gy = y0 - R + ey, gx = x0 - R + ex;
+            ok[k] = e < n && gy >= 0 && gy < H && gx >= 0 && gx < W && b < Lp;
+            const int cy = gy < 0 ? 0 : gy >= H ? H - 1 : gy, cx = gx < 0 ? 0 : gx >= W ? W - 1 : gx;
+            u[k] = x[((size_t)cy * W + cx) * Lp + (b < Lp ? b : Lp - 1)];
+            tb[k] = (ey * EX + ex) * 256 + b;        // sample index and band (Lpad <= 128)
         }
-        xs[e] = v;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = e0 + k * BG_NT;
+            if (e < n) {
+                const int t = tb[k] >> 8, b = tb[k] & 255;
+                const bool fin = isfinite(u[k]);
+                atomicOr(reinterpret_cast<unsigned *>(bad + t), ok[k] && !fin ? 0x3f800000u : 0u);
+                xs[e] = ok[k] && fin ? u[k] : (float)ref[b];
+            }
+        }
     }
 }
 
