@@ -266,7 +266,11 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
                 double acc[C::GC];
 #pragma unroll
                 for (int gg = 0; gg < C::GC; ++gg) acc[gg] = 0.0;
-                for (int ey = r0 + eoff; ey <= r0 + eoff + 2 * h; ++ey) {
+                // uniform trip count (2h+1) and counter: the loop is unrolled and its LDS
+                // reads overlap (a per-lane bound would wait for each read in turn)
+#pragma unroll 4
+                for (int k = 0; k <= 2 * h; ++k) {
+                    const int ey = r0 + eoff + k;
                     const size_t t = (size_t)ey * EX + c;
                     double f[LP];
                     centred<LP>(xs, t, ref, f);

@@ -93,8 +93,11 @@ __device__ inline void bg_window_sums(const Feat &feat, int EX, int R, int RI, i
             double acc[NF];
 #pragma unroll
             for (int g = 0; g < NF; ++g) acc[g] = 0.0;
+            // uniform trip count (2h+1) and counter: the loop is unrolled and its LDS
+            // reads overlap (a per-lane bound would wait for each read in turn)
 #pragma unroll 4
-            for (int ey = r0 + eoff; ey <= r0 + eoff + 2 * h; ++ey) {
+            for (int k = 0; k <= 2 * h; ++k) {
+                const int ey = r0 + eoff + k;
                 double f[NF];
                 feat(ey * EX + c, f);
 #pragma unroll

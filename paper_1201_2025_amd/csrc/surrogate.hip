@@ -130,7 +130,11 @@ __global__ __launch_bounds__(FNT) void surr_features_kernel(const float *__restr
                 double acc[GP];
 #pragma unroll
                 for (int g = 0; g < GP; ++g) acc[g] = 0.0;
-                for (int ey = r0 + eoff; ey <= r0 + eoff + 2 * h; ++ey) {
+                // uniform trip count (2h+1) and counter: the loop is unrolled and its LDS
+                // reads overlap (a per-lane bound would wait for each read in turn)
+#pragma unroll 4
+                for (int k = 0; k <= 2 * h; ++k) {
+                    const int ey = r0 + eoff + k;
 #pragma unroll
                     for (int i = 0; i < FCC; ++i) {
                         const double f = (double)xs[((size_t)ey * EX + c) * FCC + i] - ref[i];
