@@ -181,18 +181,58 @@ __global__ __launch_bounds__(FNT) void surr_features_kernel(const float *__restr
         if (valid) {
             const double inv = 1.0 / (double)n_a;
             const float *pc = x + pix * Lp + c0;
-            for (int i = 0; i < cc; ++i) {
-                const double mf = S[i] * inv;
-                double var = S[FCC + i] * inv - mf * mf;
-                var = var < 0.0 ? 0.0 : var;
-                const double mu = ref[i] + mf;
-                const double ve = var + 1e-12;
-                const float f3[3] = {(float)(((double)pc[i] - mu) / sqrt(ve)), (float)log(ve), (float)mu};
+            float f3[3][FCC];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
+            for (int i = 0; i < FCC; ++i) {
+                if (i < cc) {
+                    const double mf = S[i] * inv;
+                    double var = S[FCC + i] * inv - mf * mf;
+                    var = var < 0.0 ? 0.0 : var;
+                    const double mu = ref[i] + mf;
+                    const double ve = var + 1e-12;
+                    f3[0][i] = (float)(((double)pc[i] - mu) / sqrt(ve));
+                    f3[1][i] = (float)log(ve);
+                    f3[2][i] = (float)mu;
+                }
+            }
+            // the pixel's features go to three runs of cc consecutive columns; with an even
+            // L' the runs start at even columns and go out as 32-bit pairs of BF16 values
+            const bool pairs = norm && (Lp & 1) == 0 && (c0 & 1) == 0;
+            const bool quads = FCC == 4 && norm && (Lp & 3) == 0 && (c0 & 3) == 0 && cc == 4;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (quads) {     // four columns from a multiple of four: one 64-bit store
+                    const int k = q * Lp + c0;
+                    uint32_t w[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t lo = bf16_bits((f3[q][2 * h] - norm[2 * (k + 2 * h)]) * norm[2 * (k + 2 * h) + 1]);
+                        const uint32_t hi =
+                            bf16_bits((f3[q][2 * h + 1] - norm[2 * (k + 2 * h + 1)]) * norm[2 * (k + 2 * h + 1) + 1]);
+                        w[h] = lo | (hi << 16);
+                    }
+                    *reinterpret_cast<uint2 *>(packed + pix * Dp + k) = make_uint2(w[0], w[1]);
+                    continue;
+                }
+#pragma unroll
+                for (int i = 0; i < FCC; i += 2) {
                     const int k = q * Lp + c0 + i;
-                    if (norm) packed[pix * Dp + k] = bf16_bits((f3[q] - norm[2 * k]) * norm[2 * k + 1]);
-                    else feat[pix * D + k] = f3[q];
+                    if (pairs && i + 1 < cc) {
+                        const uint32_t lo = bf16_bits((f3[q][i] - norm[2 * k]) * norm[2 * k + 1]);
+                        const uint32_t hi = bf16_bits((f3[q][i + 1] - norm[2 * k + 2]) * norm[2 * k + 3]);
+                        *reinterpret_cast<uint32_t *>(packed + pix * Dp + k) = lo | (hi << 16);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            if (i + u < cc) {
+                                if (norm)
+                                    packed[pix * Dp + k + u] =
+                                        bf16_bits((f3[q][i + u] - norm[2 * (k + u)]) * norm[2 * (k + u) + 1]);
+                                else
+                                    feat[pix * D + k + u] = f3[q][i + u];
+                            }
+                        }
+                    }
                 }
             }
         }
