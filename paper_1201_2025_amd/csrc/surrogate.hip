@@ -110,13 +110,19 @@ __global__ __launch_bounds__(FNT) void surr_features_kernel(const float *__restr
             }
         }
         __syncthreads();
+        // unconditional loads from clamped coordinates, several iterations in flight
+#pragma unroll 4
         for (int t = tid; t < EY * EX; t += FNT) {
             const int ey = t / EX, ex = t - ey * EX;
             const int gy = y0 - R + ey, gx = x0 - R + ex;
             const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            const int cy = gy < 0 ? 0 : gy >= H ? H - 1 : gy, cx = gx < 0 ? 0 : gx >= W ? W - 1 : gx;
+            const float *src = x + ((size_t)cy * W + cx) * Lp + c0;
 #pragma unroll
-            for (int i = 0; i < FCC; ++i)
-                xs[(size_t)t * FCC + i] = (in && i < cc) ? x[((size_t)gy * W + gx) * Lp + c0 + i] : (float)ref[i];
+            for (int i = 0; i < FCC; ++i) {
+                const float v = src[i < cc ? i : cc - 1];
+                xs[(size_t)t * FCC + i] = (in && i < cc) ? v : (float)ref[i];
+            }
         }
         __syncthreads();
         double S[GP];
