@@ -65,17 +65,24 @@ __device__ inline void gram_pixel(const GramArgs &a, int local, double *stage)
     const int n_a = n_o - n_i;
 
     // ---- pass 1: FP64 sums over the annulus and the inner window ----
+    // Loads are unconditional (clamped coordinates and component) with a wave-uniform
+    // trip count; samples outside the window or the image are dropped by selects.  A load
+    // under a lane-dependent branch whose value is used inside it would wait for its round
+    // trip before the next one is issued.
     for (int b = 0; b < T; ++b) {
         const int comp = 16 * b + c16;
+        const int cc = comp < a.Lp ? comp : a.Lp - 1;
         double sa = 0.0, si = 0.0;
-        if (comp < a.Lp) {
-            for (int k = g4; k < K; k += 4) {
-                int sy, sx;
-                bool inn;
-                if (!sample_pos(a, py, px, k, sy, sx, inn)) continue;
-                const double v = (double)a.x[((size_t)sy * a.W + sx) * a.Lp + comp];
-                if (inn) si += v; else sa += v;
-            }
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + g4;
+            int sy, sx;
+            bool inn;
+            const bool ok = sample_pos(a, py, px, k < K ? k : K - 1, sy, sx, inn) && k < K && comp < a.Lp;
+            const int cy = sy < 0 ? 0 : sy >= a.H ? a.H - 1 : sy, cx = sx < 0 ? 0 : sx >= a.W ? a.W - 1 : sx;
+            const double v = (double)a.x[((size_t)cy * a.W + cx) * a.Lp + cc];
+            si += ok && inn ? v : 0.0;
+            sa += ok && !inn ? v : 0.0;
         }
         // reduce over the four sample groups (lanes c16, c16+16, c16+32, c16+48)
         sa += __shfl_xor(sa, 16);
@@ -149,15 +156,15 @@ __device__ inline void gram_pixel(const GramArgs &a, int local, double *stage)
 #pragma unroll
                     for (int s = 0; s < SPL; ++s) {
                         const int k = k0 + g4 * SPL + s;
-                        double v = 0.0;
                         int sy, sx;
                         bool inn;
-                        if (k < K && comp < a.Lp && sample_pos(a, py, px, k, sy, sx, inn) &&
-                            (set == 0 ? !inn : inn)) {
-                            const double xv = (double)a.x[((size_t)sy * a.W + sx) * a.Lp + comp];
-                            v = xv - (set == 0 ? mu[comp] : mi[comp]);
-                        }
-                        vals[s] = v;
+                        const bool ok = sample_pos(a, py, px, k < K ? k : K - 1, sy, sx, inn) && k < K &&
+                                        comp < a.Lp && (set == 0 ? !inn : inn);
+                        const int cc = comp < a.Lp ? comp : a.Lp - 1;
+                        const int cy = sy < 0 ? 0 : sy >= a.H ? a.H - 1 : sy;
+                        const int cx = sx < 0 ? 0 : sx >= a.W ? a.W - 1 : sx;
+                        const double xv = (double)a.x[((size_t)cy * a.W + cx) * a.Lp + cc];
+                        vals[s] = ok ? xv - (set == 0 ? mu[cc] : mi[cc]) : 0.0;
                     }
                     if constexpr (PREC == 0) {
                         stage[b * 64 + lane] = vals[0];
