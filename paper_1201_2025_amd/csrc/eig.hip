@@ -14,7 +14,8 @@
 //      the subdiagonal e and y overwrite the pixel's workspace.
 //   2. ql_dwest_kernel (lane = pixel, d, e, y in LDS columns): the implicit QL iteration
 //      with Wilkinson's shift on T (Golub & Van Loan, Sec. 8.3.5; the tql2 procedure of
-//      Bowdler, Martin, Reinsch and Wilkinson).  Each plane rotation of a sweep is also
+//      Bowdler, Martin, Reinsch and Wilkinson); the rotation's 1/r is the hardware
+//      reciprocal square root with two Newton steps.  Each plane rotation of a sweep is also
 //      applied to y, which keeps y = V^T m_diff.  A subdiagonal entry counts as zero once
 //      |e_m| <= eps (|d_m| + |d_m+1|), eps = 2^-52.  At most 64 sweeps per eigenvalue; a
 //      pixel that does not converge gets NaN scores.
@@ -160,23 +161,27 @@ __global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, 
             double dcar = D(m), ycar = Y(m);
             double ei = E(m - 1), di = D(m - 1), yi = Y(m - 1);
             for (int i = m - 1; i >= l; --i) {
-                double en = 0.0, dn = 0.0, yn = 0.0;
-                if (i > l) {
-                    en = E(i - 1);
-                    dn = D(i - 1);
-                    yn = Y(i - 1);
-                }
+                // next operands: an unconditional load (index clamped at 0; unused after the
+                // last rotation), so it is in flight during this rotation
+                const int in = i > 0 ? i - 1 : 0;
+                const double en = E(in), dn = D(in), yn = Y(in);
                 const double f = s * ei, b = c * ei;
-                r = sqrt(fma(f, f, g * g));   // |f|, |g| stay far from the FP64 range limits here
-                E(i + 1) = r;
-                if (r == 0.0) {          // the chase split the matrix: restart at l
+                // r = hypot(f, g) and 1/r from the hardware reciprocal square root refined by
+                // two Newton steps (|f|, |g| stay far from the FP64 range limits here)
+                const double r2 = fma(f, f, g * g);
+                if (r2 == 0.0) {         // the chase split the matrix: restart at l
+                    E(i + 1) = 0.0;
                     D(i + 1) = dcar - p;
                     Y(i + 1) = ycar;
                     E(m) = 0.0;
                     underflow = true;
                     break;
                 }
-                const double ir = 1.0 / r;
+                double ir = __builtin_amdgcn_rsq(r2);
+                ir = fma(0.5 * ir, fma(-r2 * ir, ir, 1.0), ir);
+                ir = fma(0.5 * ir, fma(-r2 * ir, ir, 1.0), ir);
+                r = r2 * ir;
+                E(i + 1) = r;
                 s = f * ir;
                 c = g * ir;
                 g = dcar - p;
