@@ -39,13 +39,17 @@ __device__ __forceinline__ double wave_sum64(double v)
     return v;
 }
 
-// One wavefront per pixel; rows i = lane, lane + 64, ...
+__device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
+
+// One wavefront per pixel; rows i = lane, lane + 64, ...  The symmetric matrix is kept as its
+// packed lower triangle (row i at tri(i)): half the LDS of a square, so twice the pixels
+// per CU.  Element (i, j) of the trailing block is read at tri(max) + min; the rank-2 update
+// writes the lower triangle only (a predicated store after an unconditional read).
 __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ ws, int n, int npix)
 {
     extern __shared__ double sm[];
-    const int ld = n + 1;
-    double *A = sm;                       // n x ld
-    double *v = A + (size_t)n * ld;       // n (Householder vector; entries <= k unused)
+    double *A = sm;                       // packed lower triangle, tri(n) doubles
+    double *v = A + tri(n);               // n (Householder vector; entries <= k unused)
     double *q = v + n;                    // n
     double *y = q + n;                    // n
     const int lane = threadIdx.x;
@@ -53,9 +57,21 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
     if (local >= npix) return;
     double *pix = ws + (size_t)local * (n + 2) * n;
 
-    for (int t = lane; t < n * n; t += 64) {
-        const int i = t / n, j = t - i * n;
-        A[i * ld + j] = pix[t];
+    // load: unconditional reads (index clamped) four at a time, predicated LDS stores
+    const int nn = n * n;
+    for (int t0 = 0; t0 < nn; t0 += 4 * 64) {
+        double val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + 64 * u + lane;
+            val[u] = pix[t < nn ? t : nn - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + 64 * u + lane;
+            const int i = t / n, j = t - i * n;
+            if (t < nn && j <= i) A[tri(i) + j] = val[u];
+        }
     }
     for (int i = lane; i < n; i += 64) y[i] = pix[(size_t)n * n + i];
     __syncthreads();
@@ -63,27 +79,32 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
     for (int k = 0; k + 2 < n; ++k) {
         // column k below the diagonal: x = A[k+1.., k]
         double s2 = 0.0;
-        for (int i = k + 1 + lane; i < n; i += 64) s2 += A[i * ld + k] * A[i * ld + k];
+        for (int i = k + 1 + lane; i < n; i += 64) s2 += A[tri(i) + k] * A[tri(i) + k];
         s2 = wave_sum64(s2);
-        const double x0 = A[(k + 1) * ld + k];
+        const double x0 = A[tri(k + 1) + k];
         if (s2 - x0 * x0 == 0.0) continue;    // already reduced: e_k = x0, no reflection
         const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
         const double beta = 1.0 / (alpha * (alpha - x0));   // 2 / v^T v
-        for (int i = k + 1 + lane; i < n; i += 64) v[i] = i == k + 1 ? x0 - alpha : A[i * ld + k];
+        for (int i = k + 1 + lane; i < n; i += 64) v[i] = i == k + 1 ? x0 - alpha : A[tri(i) + k];
         __syncthreads();
         // p = beta A' v on the trailing block; K = (beta/2) v^T p; q = p - K v
         double vp = 0.0, vy = 0.0;
         for (int i = k + 1 + lane; i < n; i += 64) {
-            const double *row = A + (size_t)i * ld;
+            const int ti = tri(i);
             double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;   // four chains hide the FMA latency
             int j = k + 1;
             for (; j + 3 < n; j += 4) {
-                p0 = fma(row[j], v[j], p0);
-                p1 = fma(row[j + 1], v[j + 1], p1);
-                p2 = fma(row[j + 2], v[j + 2], p2);
-                p3 = fma(row[j + 3], v[j + 3], p3);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = j + u;
+                    const double a = A[jj <= i ? ti + jj : tri(jj) + i];
+                    if (u == 0) p0 = fma(a, v[jj], p0);
+                    else if (u == 1) p1 = fma(a, v[jj], p1);
+                    else if (u == 2) p2 = fma(a, v[jj], p2);
+                    else p3 = fma(a, v[jj], p3);
+                }
             }
-            for (; j < n; ++j) p0 = fma(row[j], v[j], p0);
+            for (; j < n; ++j) p0 = fma(A[j <= i ? ti + j : tri(j) + i], v[j], p0);
             const double p = beta * ((p0 + p1) + (p2 + p3));
             q[i] = p;
             vp = fma(v[i], p, vp);
@@ -97,20 +118,25 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
             y[i] = fma(-gam, v[i], y[i]);
         }
         __syncthreads();
-        // A' <- A' - v q^T - q v^T
+        // A' <- A' - v q^T - q v^T on the lower triangle (j <= i).  tri(i) + j stays inside
+        // the packed array for j < n; past the row's end it is read and left alone.
         for (int i = k + 1 + lane; i < n; i += 64) {
-            double *row = A + (size_t)i * ld;
+            double *row = A + tri(i);
             const double vi = v[i], qi = q[i];
-            for (int j = k + 1; j < n; ++j) row[j] -= fma(vi, q[j], qi * v[j]);
+#pragma unroll 4
+            for (int j = k + 1; j < n; ++j) {
+                const double a = row[j] - fma(vi, q[j], qi * v[j]);
+                if (j <= i) row[j] = a;
+            }
         }
         // column k itself becomes alpha e_1 (only the subdiagonal is read later)
-        if (lane == 0) A[(k + 1) * ld + k] = alpha;
+        if (lane == 0) A[tri(k + 1) + k] = alpha;
         __syncthreads();
     }
     // d, e, y -> the start of the pixel's workspace (the matrix is in LDS now)
     for (int i = lane; i < n; i += 64) {
-        pix[i] = A[i * ld + i];
-        pix[n + i] = i + 1 < n ? A[(i + 1) * ld + i] : 0.0;
+        pix[i] = A[tri(i) + i];
+        pix[n + i] = i + 1 < n ? A[tri(i + 1) + i] : 0.0;
         pix[2 * n + i] = y[i];
     }
 }
@@ -224,7 +250,7 @@ __global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, 
     if (npos) npos[o] = ok ? cnt : -1;
 }
 
-size_t eig_smem(int64_t n) { return (size_t)(n * (n + 1) + 3 * n) * sizeof(double); }
+size_t eig_smem(int64_t n) { return (size_t)(n * (n + 1) / 2 + 3 * n) * sizeof(double); }
 
 // pixels per workgroup of the QL kernel: the largest power of two <= 64 whose three LDS
 // columns stay within 48 KiB
