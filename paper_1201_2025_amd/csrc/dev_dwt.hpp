@@ -115,23 +115,34 @@ __device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p
     if constexpr (VEC == 4) {
         const int nv = total >> 2;
         const float4 *s4 = reinterpret_cast<const float4 *>(src);
-#pragma unroll 4
-        for (int v = tid; v < nv; v += 256) {
-            const float4 q = s4[v];
-            const uint32_t e = 4u * (uint32_t)v;
-            const uint32_t r = __umulhi(e, magic_L);
-            const uint32_t col = e - r * (uint32_t)L;
-            float *d = xs + r * LDP + col;
-            d[0] = q.x;
-            d[1] = q.y;
-            d[2] = q.z;
-            d[3] = q.w;
-            if (col < ext) {
-                float *dd = d + L;
-                const float qq[4] = {q.x, q.y, q.z, q.w};
+        // four loads per thread in flight: unconditional (index clamped), then the stores
+        for (int v0 = 0; v0 < nv; v0 += 4 * 256) {
+            float4 qs[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (col + j < ext) dd[j] = qq[j];
+            for (int u = 0; u < 4; ++u) {
+                const int v = v0 + 256 * u + tid;
+                qs[u] = s4[v < nv ? v : nv - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = v0 + 256 * u + tid;
+                if (v >= nv) continue;
+                const float4 q = qs[u];
+                const uint32_t e = 4u * (uint32_t)v;
+                const uint32_t r = __umulhi(e, magic_L);
+                const uint32_t col = e - r * (uint32_t)L;
+                float *d = xs + r * LDP + col;
+                d[0] = q.x;
+                d[1] = q.y;
+                d[2] = q.z;
+                d[3] = q.w;
+                if (col < ext) {
+                    float *dd = d + L;
+                    const float qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (col + j < ext) dd[j] = qq[j];
+                }
             }
         }
     } else {
