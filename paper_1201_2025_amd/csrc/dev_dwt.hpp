@@ -30,12 +30,25 @@ __device__ inline void dwt_cascade_tile(const float *__restrict__ cube, int64_t 
     double *buf1 = lds + (size_t)P * S0;  // P * S1
     const int tid = threadIdx.x;
 
-    // coalesced load of np contiguous spectra
+    // coalesced load of np contiguous spectra, four unconditional loads per thread in
+    // flight (index clamped), then the stores
     const float *src = cube + p0 * (int64_t)L;
     const int total = np * L;
-    for (int t = tid; t < total; t += 256) {
-        const int p = t / L, i = t - p * L;
-        buf0[p * S0 + i] = (double)src[t];
+    for (int t0 = 0; t0 < total; t0 += 4 * 256) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + 256 * u + tid;
+            v[u] = src[t < total ? t : total - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + 256 * u + tid;
+            if (t < total) {
+                const int p = t / L, i = t - p * L;
+                buf0[p * S0 + i] = (double)v[u];
+            }
+        }
     }
     __syncthreads();
 
