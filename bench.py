@@ -18,6 +18,7 @@ printed.  Beside the timed step, the script also measures:
   * the FP64 CPU oracle on the host cores, for the same workload (cpu_baseline);
   * the 64-scene uneven batch through the persistent batch engine;
   * DWEST (eqs. 2-4) at L' = 14 / 28 / 56 on the same cube (inner 3, outer 11);
+  * the paper's image shapes and windows (P1, P2), each detector with and without the DWT;
   * the learned surrogate: exact vs hybrid LRX on a 2048 x 2048 x 224 scene at L' = 14
     and 56, with the change of ROC AUC.
 """
@@ -51,6 +52,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batch measurement")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--no-dwest", action="store_true", help="skip the DWEST measurement")
+    ap.add_argument("--no-paper-shaped", action="store_true", help="skip the paper-shaped P1/P2 runs")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
     ap.add_argument("--surrogate-scenes", type=int, default=200,
                     help="training scenes of 256x256x224 for the surrogate (200 in the full workload)")
@@ -173,6 +175,48 @@ def bench_dwest(cube, dev, log):
         log("dwest L'=%d: %.2f ms" % (Lp, ms))
         del ws
     return {"workload": "512x512x224 cube (C2 recipe) at L' = 14/28/56, inner 3, outer 11", "levels": out}
+
+
+def bench_paper_shaped(dev, log):
+    """The paper's image shapes (Sec. 5.1: 60x100x189 and 100x100x189, J = 5 so L' = 6) with its
+    windows (Sec. 5.2: LRX 15x15 single window; DWRX / DWEST 5x5 or 3x3 inside 13x13), on seeded
+    stand-in scenes.  GPU times of each detector with and without the DWT, beside the paper's
+    own IDL runtimes on Img2 (Table 2, i5-2410M), which are context only."""
+    import torch
+    import paper_1201_2025_amd as hs
+    from paper_1201_2025_amd import synth
+    table2_s = {"LRX": 713.674, "DWT-LRX": 17.071, "DWRX": 637.089, "DWT-DWRX": 19.318,
+                "DWEST": 1091.173, "DWT-DWEST": 20.129}
+    out = {"table2_img2_seconds_idl_cpu": table2_s, "scenes": {}}
+
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    for name in ("P1", "P2"):
+        c = synth.CONFIGS[name]
+        sc = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"],
+                              n_blob=c["n_blob"])
+        cube = torch.from_numpy(sc.cube).to(dev)
+        res = {}
+        for full in (True, False):
+            tag = "" if full else "DWT-"
+
+            def red():
+                return cube if full else hs.hsad_dwt(cube, c["levels"])
+            res[tag + "LRX"] = timed(lambda: hs.hsad_lrx(red(), c["lrx_inner"], c["lrx_outer"], c["load_rel"]))
+            res[tag + "DWRX"] = timed(lambda: hs.hsad_dwrx(red(), c["inner"], c["outer"], c["load_rel"]))
+            res[tag + "DWEST"] = timed(lambda: hs.hsad_dwest(red(), c["inner"], c["outer"]), reps=5)
+        out["scenes"][name] = {"shape": [c["H"], c["W"], c["L"]], "levels": c["levels"], "ms": res}
+        log("%s: %s" % (name, ", ".join("%s %.2f ms" % kv for kv in res.items())))
+    return out
 
 
 def bench_surrogate(args, dev, log):
@@ -484,6 +528,13 @@ def main():
         except Exception as e:     # report, keep the headline line
             dwest = {"error": repr(e)}
 
+    paper_shaped = None
+    if not args.no_paper_shaped:
+        try:
+            paper_shaped = bench_paper_shaped(dev, log)
+        except Exception as e:     # report, keep the headline line
+            paper_shaped = {"error": repr(e)}
+
     surrogate = None
     if not args.no_surrogate:
         try:
@@ -526,6 +577,7 @@ def main():
         "sweep": sweep,
         "batch": batch,
         "dwest": dwest,
+        "paper_shaped": paper_shaped,
         "surrogate": surrogate,
     }
     out.update(result_extra)
