@@ -241,7 +241,10 @@ __global__ __launch_bounds__(256) void batch_chol_group_kernel(const SceneDev *_
                                                                const Item *__restrict__ items, int n,
                                                                double *chunk_ws)
 {
-    const int it = (int)((blockIdx.x * 256 + threadIdx.x) / G);
+    int it = (int)((blockIdx.x * 256 + threadIdx.x) / G);
+    // G = 64: one item per wavefront; saying so lets the item and its scene be read with
+    // scalar loads and keeps L' (the loop bounds) uniform
+    if constexpr (G == 64) it = __builtin_amdgcn_readfirstlane(it);
     const bool active = it < n;
     const Item m = items[active ? it : 0];
     const SceneDev &s = sc[m.scene];

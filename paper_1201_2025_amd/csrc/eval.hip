@@ -103,41 +103,70 @@ __global__ __launch_bounds__(kRedThreads) void thr_merge_mask_kernel(const float
 {
     __shared__ double sh[3 * kRedThreads];
     __shared__ double tau_s;
+    // The thread's first kPF scores and its (at most four) partials are loaded up front,
+    // from clamped indices, so all these round trips overlap each other and the merge.
+    constexpr int kPF = 4;
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * kRedThreads + t, st = (int64_t)gridDim.x * kRedThreads;
+    float sv[kPF];
+#pragma unroll
+    for (int k = 0; k < kPF; ++k) {
+        const int64_t i = i0 + k * st;
+        sv[k] = s[i < n ? i : n - 1];
+    }
+    double pn[4], pm[4], pM[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = t + k * kRedThreads, ic = i < nblk ? i : nblk - 1;
+        pn[k] = part[3 * ic];
+        pm[k] = part[3 * ic + 1];
+        pM[k] = part[3 * ic + 2];
+    }
+    // fixed order: thread t merges partials t, t + 256, t + 512, t + 768, then a pairwise
+    // tree (t with t + w for w = 128 ... 1); the last six levels run inside wavefront 0
     double na = 0.0, ma = 0.0, Ma = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
-        chan_merge(na, ma, Ma, part[3 * i], part[3 * i + 1], part[3 * i + 2]);
-    sh[3 * threadIdx.x] = na;
-    sh[3 * threadIdx.x + 1] = ma;
-    sh[3 * threadIdx.x + 2] = Ma;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (t + k * kRedThreads < nblk) chan_merge(na, ma, Ma, pn[k], pm[k], pM[k]);
+    sh[3 * t] = na;
+    sh[3 * t + 1] = ma;
+    sh[3 * t + 2] = Ma;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            double a = sh[3 * threadIdx.x], b = sh[3 * threadIdx.x + 1], c = sh[3 * threadIdx.x + 2];
-            const int o = 3 * (threadIdx.x + w);
-            chan_merge(a, b, c, sh[o], sh[o + 1], sh[o + 2]);
-            sh[3 * threadIdx.x] = a;
-            sh[3 * threadIdx.x + 1] = b;
-            sh[3 * threadIdx.x + 2] = c;
+    for (int w = kRedThreads / 2; w >= 64; w >>= 1) {
+        if (t < w) {
+            chan_merge(na, ma, Ma, sh[3 * (t + w)], sh[3 * (t + w) + 1], sh[3 * (t + w) + 2]);
+            sh[3 * t] = na;
+            sh[3 * t + 1] = ma;
+            sh[3 * t + 2] = Ma;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double cnt = sh[0], mu = cnt > 0 ? sh[1] : NAN;
-        const double sig = cnt > 0 ? sqrt(sh[2] / cnt) : NAN;
-        tau_s = mu + z * sig;
-        if (blockIdx.x == 0) {
-            stats[0] = cnt;
-            stats[1] = mu;
-            stats[2] = sig;
-            stats[3] = tau_s;
+    if (t < 64) {
+        for (int w = 32; w > 0; w >>= 1) {
+            const double nb = __shfl_down(na, w, 64), mb = __shfl_down(ma, w, 64), Mb = __shfl_down(Ma, w, 64);
+            if (t < w) chan_merge(na, ma, Ma, nb, mb, Mb);
+        }
+        if (t == 0) {
+            const double cnt = na, mu = cnt > 0 ? ma : NAN;
+            const double sig = cnt > 0 ? sqrt(Ma / cnt) : NAN;
+            tau_s = mu + z * sig;
+            if (blockIdx.x == 0) {
+                stats[0] = cnt;
+                stats[1] = mu;
+                stats[2] = sig;
+                stats[3] = tau_s;
+            }
         }
     }
     __syncthreads();
     if (!mask) return;
     const double tau = tau_s;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        mask[i] = ((double)s[i] > tau) ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < kPF; ++k) {
+        const int64_t i = i0 + k * st;
+        if (i < n) mask[i] = ((double)sv[k] > tau) ? 1 : 0;
+    }
+    for (int64_t i = i0 + kPF * st; i < n; i += st) mask[i] = ((double)s[i] > tau) ? 1 : 0;
 }
 
 // ---- AUC ----
