@@ -137,6 +137,7 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_filter", ctypes.c_int, [ctypes.POINTER(ctypes.c_double)]),
     ("hsad_internal_dwt_force", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_chunk", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_box_width", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwt_nt", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwest_solver", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_chol_cb", ctypes.c_int, [ctypes.c_int]),

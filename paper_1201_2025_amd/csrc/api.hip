@@ -294,8 +294,8 @@ int hsad_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp,
     return lrx_dwrx_common("hsad_lrx_dwrx", x, H, W, Lp, p, lrx, dwrx, ws, ws_bytes, stream);
 }
 
-// Workspace of hsad_detect: eq. (12) partials (one per 16 x 16 tile on the box path, else
-// the threshold's blocks) and the fold buffer, 256-byte aligned, then what hsad_lrx_dwrx
+// Workspace of hsad_detect: eq. (12) partials (one per box tile, at most one per 16 x 16
+// tiles, on the box path, else the threshold's blocks) and the fold buffer, 256-byte aligned, then what hsad_lrx_dwrx
 // needs.
 static size_t detect_head_bytes(int64_t H, int64_t W)
 {
@@ -333,8 +333,8 @@ int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_win
         // the box kernel leaves one partial per tile: no separate statistics pass
         rc = box_lrx_dwrx_launch(x, H, W, Lp, w, p->load_rel, lrx, dwrx, stream, part);
         if (rc) return rc;
-        return threshold_from_partials(lrx, n, part, (int64_t)box_tiles(H, W), z_alpha, stats, mask, fold,
-                                       stream);
+        return threshold_from_partials(lrx, n, part, (int64_t)box_tiles_used(H, W, Lp, w), z_alpha, stats, mask,
+                                       fold, stream);
     }
     rc = lrx_dwrx_common("hsad_detect", x, H, W, Lp, p, lrx, dwrx, (char *)ws + head, ws_bytes - head,
                          stream);

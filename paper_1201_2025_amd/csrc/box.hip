@@ -13,8 +13,9 @@
 // is 1e4 times the smallest eigenvalue of C.  This data-dependent cancellation rules
 // out FP32 sums here.
 //
-// Per 16 x 16 output tile (256 threads, one output pixel each):
-//   1. stage the (16+2R)^2 halo tile of the reduced cube in LDS (coalesced).  Pixels
+// Per 32 x 16 output tile (512 threads, one output pixel each; 16 x 16 when the wider
+// tile's LDS does not fit, and in the batch engine):
+//   1. stage the (32+2R) x (16+2R) halo tile of the reduced cube in LDS (coalesced).  Pixels
 //      outside the image or with a non-finite component take the reference value, and
 //      the second kind is flagged;
 //   2. for each feature chunk and each window (inner, then outer): vertical box sums,
@@ -36,16 +37,17 @@
 
 namespace hsad {
 
-template <int LP, int GCMAX>
-__global__ __launch_bounds__(NT) void box_lrx_dwrx_kernel(const float *__restrict__ x, int H,
-                                                          int W, int R, int RI, int has_inner,
-                                                          double load_rel,
-                                                          float *__restrict__ lrx,
-                                                          float *__restrict__ dwrx,
-                                                          double *__restrict__ part)
+template <int LP, int GCMAX, int TXW>
+__global__ __launch_bounds__(TXW * TY) void box_lrx_dwrx_kernel(const float *__restrict__ x, int H,
+                                                                int W, int R, int RI, int has_inner,
+                                                                double load_rel,
+                                                                float *__restrict__ lrx,
+                                                                float *__restrict__ dwrx,
+                                                                double *__restrict__ part)
 {
     extern __shared__ double smem[];
-    box_tile<LP, GCMAX>(x, H, W, R, RI, has_inner, load_rel, lrx, dwrx, blockIdx.y, blockIdx.x, smem, part);
+    box_tile<LP, GCMAX, TXW>(x, H, W, R, RI, has_inner, load_rel, lrx, dwrx, blockIdx.y, blockIdx.x, smem,
+                             part);
 }
 
 static size_t box_smem_lp(int64_t Lp, int R)
@@ -72,27 +74,52 @@ bool box_supported(int64_t Lp, const Windows &w)
 }
 
 static int g_box_gc = 0;   // 0: default feature chunk; 15 / 8 / 5 forced (tuning, tests)
+static int g_box_tx = 0;   // 0: widest tile whose LDS fits; 16 forced (tuning, tests)
+
+// default chunk width: measured fastest on gfx950 at 512 x 512 (5 features keep four
+// 16 x 16 workgroups resident per CU; 8 for L' = 5..7, where 5 spills registers)
+static int box_gc(int Lp) { return g_box_gc ? g_box_gc : ((Lp >= 5 && Lp <= 7) ? 8 : 5); }
+
+template <int LP, int GCMAX> static int box_width(int R)
+{
+    // 32 x 16 tiles: 9-10 % faster than 16 x 16 at L' = 4 and 7 (512^2 and 1024^2, 15 x 15
+    // outer windows), bit-identical sums
+    return g_box_tx != 16 && box_smem<LP, GCMAX, 32>(R) <= kBoxMaxSmem ? 32 : 16;
+}
+
+template <int LP> static int box_width_lp(int R)
+{
+    const int gc = box_gc(LP);
+    return gc == 8 ? box_width<LP, 8>(R) : gc == 15 ? box_width<LP, 15>(R) : box_width<LP, 5>(R);
+}
+
+template <int LP, int GCMAX, int TXW>
+static int box_launch_tw(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
+                         float *lrx, float *dwrx, double *part, hipStream_t s)
+{
+    const size_t sh = box_smem<LP, GCMAX, TXW>(w.ro);
+    if (int rc = allow_lds((const void *)box_lrx_dwrx_kernel<LP, GCMAX, TXW>, sh, "box_lrx_dwrx_kernel"))
+        return rc;
+    dim3 grid((unsigned)((W + TXW - 1) / TXW), (unsigned)((H + TY - 1) / TY)), block(TXW * TY);
+    hipLaunchKernelGGL((box_lrx_dwrx_kernel<LP, GCMAX, TXW>), grid, block, sh, s, x, (int)H, (int)W, w.ro,
+                       w.ri, w.inner > 0 ? 1 : 0, load_rel, lrx, dwrx, part);
+    return check_launch("box_lrx_dwrx_kernel");
+}
 
 template <int LP, int GCMAX>
 static int box_launch_gc(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
                          float *lrx, float *dwrx, double *part, hipStream_t s)
 {
-    const size_t sh = box_smem<LP, GCMAX>(w.ro);
-    if (int rc = allow_lds((const void *)box_lrx_dwrx_kernel<LP, GCMAX>, sh, "box_lrx_dwrx_kernel"))
-        return rc;
-    dim3 grid((unsigned)((W + TX - 1) / TX), (unsigned)((H + TY - 1) / TY)), block(NT);
-    hipLaunchKernelGGL((box_lrx_dwrx_kernel<LP, GCMAX>), grid, block, sh, s, x, (int)H, (int)W, w.ro,
-                       w.ri, w.inner > 0 ? 1 : 0, load_rel, lrx, dwrx, part);
-    return check_launch("box_lrx_dwrx_kernel");
+    if (box_width<LP, GCMAX>(w.ro) == 32)
+        return box_launch_tw<LP, GCMAX, 32>(x, H, W, w, load_rel, lrx, dwrx, part, s);
+    return box_launch_tw<LP, GCMAX, 16>(x, H, W, w, load_rel, lrx, dwrx, part, s);
 }
 
 template <int LP>
 static int box_launch(const float *x, int64_t H, int64_t W, const Windows &w, double load_rel,
                       float *lrx, float *dwrx, double *part, hipStream_t s)
 {
-    // default chunk width: measured fastest on gfx950 at 512 x 512 (5 features keep four
-    // workgroups resident per CU; 8 for L' = 5..7, where 5 spills registers)
-    const int gc = g_box_gc ? g_box_gc : ((LP >= 5 && LP <= 7) ? 8 : 5);
+    const int gc = box_gc(LP);
     switch (gc) {
     case 8: return box_launch_gc<LP, 8>(x, H, W, w, load_rel, lrx, dwrx, part, s);
     case 15: return box_launch_gc<LP, 15>(x, H, W, w, load_rel, lrx, dwrx, part, s);
@@ -105,7 +132,24 @@ int wave_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const
 bool wave_supported(int64_t Lp, const Windows &w);
 int box_variant();
 
-size_t box_tiles(int64_t H, int64_t W) { return (size_t)((H + TY - 1) / TY) * (size_t)((W + TX - 1) / TX); }
+size_t box_tiles(int64_t H, int64_t W) { return (size_t)((H + TY - 1) / TY) * (size_t)((W + 15) / 16); }
+
+size_t box_tiles_used(int64_t H, int64_t W, int64_t Lp, const Windows &w)
+{
+    int tw = 16;
+    switch (Lp) {
+    case 1: tw = box_width_lp<1>(w.ro); break;
+    case 2: tw = box_width_lp<2>(w.ro); break;
+    case 3: tw = box_width_lp<3>(w.ro); break;
+    case 4: tw = box_width_lp<4>(w.ro); break;
+    case 5: tw = box_width_lp<5>(w.ro); break;
+    case 6: tw = box_width_lp<6>(w.ro); break;
+    case 7: tw = box_width_lp<7>(w.ro); break;
+    case 8: tw = box_width_lp<8>(w.ro); break;
+    default: break;
+    }
+    return (size_t)((H + TY - 1) / TY) * (size_t)((W + tw - 1) / tw);
+}
 
 int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                         double load_rel, float *lrx, float *dwrx, hipStream_t s, double *part)
@@ -132,6 +176,13 @@ int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const 
 extern "C" int hsad_internal_box_chunk(int gc)
 {
     hsad::g_box_gc = gc;
+    return 0;
+}
+
+extern "C" int hsad_internal_box_width(int tx)
+{
+    if (tx != 0 && tx != 16) return -1;
+    hsad::g_box_tx = tx;
     return 0;
 }
 

@@ -6,7 +6,9 @@
 
 namespace hsad {
 
-constexpr int TX = 16, TY = 16, NT = TX * TY;
+// Tiles are TXW x 16 output pixels (TXW = 16 or 32), one thread per pixel.  A wider tile
+// spends fewer halo columns per pixel (TXW + 2R columns of vertical sums for TXW outputs).
+constexpr int TY = 16;
 constexpr int RB = 4;                 // output rows per vertical-sum job
 constexpr int NRB = TY / RB;
 
@@ -161,28 +163,35 @@ __device__ __forceinline__ float box_score(const float *__restrict__ x, int H, i
     return lrx_v;
 }
 
-// Deterministic block sum of 256 threads (fixed shuffle tree per wavefront, then the four
-// wavefront sums in order); red holds 4 doubles of LDS; the result is valid in every thread.
-__device__ __forceinline__ double box_block_sum(double v, double *red)
+// Deterministic block sum of NW wavefronts (fixed shuffle tree per wavefront, then the
+// wavefront sums pairwise: (0+1) + (2+3), ...); red holds NW doubles of LDS; the result is
+// valid in every thread.
+template <int NW> __device__ __forceinline__ double box_block_sum(double v, double *red)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    double t[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) t[i] = red[i];
+#pragma unroll
+    for (int w = NW / 2; w >= 1; w /= 2)
+#pragma unroll
+        for (int i = 0; i < w; ++i) t[i] = t[2 * i] + t[2 * i + 1];
     __syncthreads();
-    return t;
+    return t[0];
 }
 
 // (count, mean, centred sum of squares) of the finite values v of a tile's threads, two
 // passes in FP64 -> out[0..2].  The partial statistics of eq. (12) for one tile.
-__device__ inline void box_tile_stats(float v, bool valid, double *out, double *red)
+template <int NW> __device__ inline void box_tile_stats(float v, bool valid, double *out, double *red)
 {
     const bool fin = valid && isfinite(v);
-    const double c = box_block_sum(fin ? 1.0 : 0.0, red);
-    const double sum = box_block_sum(fin ? (double)v : 0.0, red);
+    const double c = box_block_sum<NW>(fin ? 1.0 : 0.0, red);
+    const double sum = box_block_sum<NW>(fin ? (double)v : 0.0, red);
     const double mean = c > 0.0 ? sum / c : 0.0;
     const double d = fin ? (double)v - mean : 0.0;
-    const double m2 = box_block_sum(d * d, red);
+    const double m2 = box_block_sum<NW>(d * d, red);
     if (threadIdx.x == 0) {
         out[0] = c;
         out[1] = mean;
@@ -190,13 +199,14 @@ __device__ inline void box_tile_stats(float v, bool valid, double *out, double *
     }
 }
 
-template <int LP, int GCMAX>
+template <int LP, int GCMAX, int TXW = 16>
 __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R, int RI,
                                 int has_inner, double load_rel, float *__restrict__ lrx,
                                 float *__restrict__ dwrx, int by, int bx, double *smem,
                                 double *__restrict__ part = nullptr)
 {
     using C = BoxCfg<LP, GCMAX>;
+    constexpr int TX = TXW, NT = TXW * TY;
     const int EX = TX + 2 * R, EY = TY + 2 * R;
     double *V = smem;                                                    // TY*EX*GCP
     float *xs = reinterpret_cast<float *>(smem + (size_t)TY * EX * C::GCP);   // EY*EX*LP
@@ -342,14 +352,14 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
         v = box_score<LP, C::GT>(x, H, W, R, RI, has_inner, load_rel, ref, S, sin_lin, in_bad, py, px, lrx,
                                  dwrx);
     // eq. (12) partials of this tile's LRX scores (the LDS tile is free again here)
-    if (part) box_tile_stats(v, inside, part + 3 * ((size_t)by * gridDim.x + bx), smem);
+    if (part) box_tile_stats<NT / 64>(v, inside, part + 3 * ((size_t)by * gridDim.x + bx), smem);
 }
 
 
-template <int LP, int GCMAX = 15> __host__ __device__ inline size_t box_smem(int R)
+template <int LP, int GCMAX = 15, int TXW = 16> __host__ __device__ inline size_t box_smem(int R)
 {
     using C = BoxCfg<LP, GCMAX>;
-    const size_t EX = TX + 2 * R, EY = TY + 2 * R;
+    const size_t EX = TXW + 2 * R, EY = TY + 2 * R;
     return (size_t)TY * EX * C::GCP * sizeof(double) + EY * EX * (LP + 1) * sizeof(float);
 }
 

@@ -44,6 +44,8 @@ int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const 
                         double load_rel, float *lrx, float *dwrx, hipStream_t s,
                         double *part = nullptr);
 size_t box_tiles(int64_t H, int64_t W);
+// tiles of the box kernel as launched for these sizes (at most box_tiles(H, W))
+size_t box_tiles_used(int64_t H, int64_t W, int64_t Lp, const Windows &w);
 
 // ---- eq. (12) from partial statistics (eval.hip) ----
 // Merges nblk (count, mean, M2) partials in a fixed order, writes stats {count, mu, sigma,

@@ -68,20 +68,24 @@ def _box_input(H, W, Lp):
     return np.ascontiguousarray(x, dtype=np.float32)
 
 
-# the box path's tile kernel at feature chunks 5 / 8 / 15 (the default picks 5 or 8), set
-# through the library's internal switches
-BOX_KERNELS = {"tile5": (1, 5), "tile8": (1, 8), "tile15": (1, 15)}
+# the box path's tile kernel at feature chunks 5 / 8 / 15 (the default picks 5 or 8) and
+# tile widths 32 (where its LDS fits; the default) / 16, set through the library's
+# internal switches
+BOX_KERNELS = {"tile5": (1, 5, 0), "tile8": (1, 8, 0), "tile15": (1, 15, 0),
+               "tile5_w16": (1, 5, 16), "tile8_w16": (1, 8, 16), "tile15_w16": (1, 15, 16)}
 
 
 @pytest.fixture(params=sorted(BOX_KERNELS))
 def box_kernel(request):
     L_ = hs.lib()
-    v, gc = BOX_KERNELS[request.param]
+    v, gc, tw = BOX_KERNELS[request.param]
     L_.hsad_internal_box_variant(v, 2)
     L_.hsad_internal_box_chunk(gc)
+    assert L_.hsad_internal_box_width(tw) == 0
     yield request.param
     L_.hsad_internal_box_variant(0, 2)
     L_.hsad_internal_box_chunk(0)
+    L_.hsad_internal_box_width(0)
 
 
 @pytest.mark.parametrize("H,W,Lp,inner,outer", BOX)
@@ -295,7 +299,8 @@ def test_gram_step_against_window_stats(Lp, inner, outer, prec, tol):
 # separate hsad_lrx_dwrx call bit for bit; tau must match the oracle's threshold of the
 # same LRX map to 1e-12 (the box path merges per-tile partials instead of the threshold's
 # own blocks, so only rounding differs); the mask must be exactly lrx > tau.
-@pytest.mark.parametrize("H,W,Lp,inner,outer", [(37, 29, 4, 5, 15), (600, 600, 4, 5, 15),
+# 720 x 900 has more than 1024 box tiles at either width: the partials are folded first.
+@pytest.mark.parametrize("H,W,Lp,inner,outer", [(37, 29, 4, 5, 15), (720, 900, 4, 5, 15),
                                                  (40, 33, 7, 3, 9), (23, 19, 14, 5, 15),
                                                  (20, 21, 5, 0, 9)])
 def test_detect_matches_separate_calls(H, W, Lp, inner, outer):
