@@ -237,7 +237,8 @@ size_t hsad_workspace_bytes(int op, int64_t H, int64_t W, int64_t Lp,
     t_err = keep;
     if (rc) return 0;
     if (op != HSAD_OP_DWEST && exact(p->precision) && box_supported(Lp, w)) return 0;
-    const GramMode mode = op == HSAD_OP_DWEST ? GRAM_DWEST : GRAM_LRX;
+    if (op == HSAD_OP_DWEST) return dwest_ws_bytes(H, W, Lp);
+    const GramMode mode = GRAM_LRX;
     const size_t per = generic_ws_per_pixel(Lp, mode);
     // enough for every pixel in one launch, capped at 1 GiB (larger chunks gain nothing)
     const size_t cap = (size_t)1 << 30;

@@ -45,7 +45,10 @@ __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
 // packed lower triangle (row i at tri(i)): half the LDS of a square, so twice the pixels
 // per CU.  Element (i, j) of the trailing block is read at tri(max) + min; the rank-2 update
 // writes the lower triangle only (a predicated store after an unconditional read).
-__global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ ws, int n, int npix)
+// With dey set, d, e and y go to dey[i * S], dey[(n + i) * S] and dey[(2n + i) * S] (dey is
+// offset to the pixel's column, S the column count), else to the pixel's workspace.
+__global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ ws, int n, int npix,
+                                                           double *__restrict__ dey, int64_t S)
 {
     extern __shared__ double sm[];
     double *A = sm;                       // packed lower triangle, tri(n) doubles
@@ -133,43 +136,61 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
         if (lane == 0) A[tri(k + 1) + k] = alpha;
         __syncthreads();
     }
-    // d, e, y -> the start of the pixel's workspace (the matrix is in LDS now)
+    // d, e, y -> the start of the pixel's workspace (the matrix is in LDS now), or to the
+    // pixel's column of dey
     for (int i = lane; i < n; i += 64) {
-        pix[i] = A[tri(i) + i];
-        pix[n + i] = i + 1 < n ? A[tri(i + 1) + i] : 0.0;
-        pix[2 * n + i] = y[i];
+        const double di = A[tri(i) + i], ei = i + 1 < n ? A[tri(i + 1) + i] : 0.0;
+        if (dey) {
+            double *c = dey + local;
+            c[(int64_t)i * S] = di;
+            c[(int64_t)(n + i) * S] = ei;
+            c[(int64_t)(2 * n + i) * S] = y[i];
+        } else {
+            pix[i] = di;
+            pix[n + i] = ei;
+            pix[2 * n + i] = y[i];
+        }
     }
 }
 
-// lane = pixel; d, e, y of pixel lane in LDS columns (entry i at i * P + lane).
-__global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, int64_t pix0, int P,
-                                float *__restrict__ score, float *__restrict__ literal,
-                                int32_t *__restrict__ npos)
+// The implicit QL iteration of one pixel on its columns d, e, y (entry i at i * st), and
+// the outputs: ok (converged), s2 = sum_P y_i^2, s1 = sum_P |y_i|, cnt = |P|.
+__device__ __forceinline__ void ql_pixel(double *__restrict__ d, double *__restrict__ e, double *__restrict__ y,
+                                         int64_t st, int n, bool &ok, double &s2, double &s1, int &cnt)
 {
-    extern __shared__ double sm[];
-    const int lane = threadIdx.x;
-    const int local = blockIdx.x * P + lane;
-    double *d = sm, *e = sm + (size_t)n * P, *y = sm + (size_t)2 * n * P;
-    const bool act = lane < P && local < npix;
-    if (!act) return;      // no barriers below: lanes are independent
-    const double *pix = ws + (size_t)local * (n + 2) * n;
-    for (int i = 0; i < n; ++i) {
-        d[i * P + lane] = pix[i];
-        e[i * P + lane] = pix[n + i];
-        y[i * P + lane] = pix[2 * n + i];
-    }
-#define D(i) d[(i) * P + lane]
-#define E(i) e[(i) * P + lane]
-#define Y(i) y[(i) * P + lane]
-    bool ok = true;
+#define D(i) d[(int64_t)(i) * st]
+#define E(i) e[(int64_t)(i) * st]
+#define Y(i) y[(int64_t)(i) * st]
+    ok = true;
     E(n - 1) = 0.0;
     for (int l = 0; l < n && ok; ++l) {
         int iter = 0;
         for (;;) {
+            // first m >= l with a negligible e_m (n - 1 if none): eight entries per step,
+            // loaded (clamped) before any is tested
             int m = l;
-            for (; m + 1 < n; ++m) {
-                const double dd = fabs(D(m)) + fabs(D(m + 1));
-                if (fabs(E(m)) <= DBL_EPSILON * dd) break;
+            for (;;) {
+                if (m + 1 >= n) {
+                    m = n - 1;
+                    break;
+                }
+                double ev[8], dv[9];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int t = m + k < n ? m + k : n - 1;
+                    ev[k] = E(t);
+                    dv[k] = D(t);
+                }
+                dv[8] = D(m + 8 < n ? m + 8 : n - 1);
+                int hit = -1;
+#pragma unroll
+                for (int k = 7; k >= 0; --k)
+                    if (m + k + 1 < n && fabs(ev[k]) <= DBL_EPSILON * (fabs(dv[k]) + fabs(dv[k + 1]))) hit = k;
+                if (hit >= 0) {
+                    m += hit;
+                    break;
+                }
+                m += 8;
             }
             if (m == l) break;
             if (++iter > 64) {
@@ -231,11 +252,12 @@ __global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, 
     }
     double emax = 0.0;
     for (int i = 0; i < n; ++i) emax = fmax(emax, fabs(D(i)));
-    double s2 = 0.0, s1 = 0.0;
-    int cnt = 0;
+    s2 = 0.0;
+    s1 = 0.0;
+    cnt = 0;
     for (int i = 0; i < n; ++i) {
+        const double pr = Y(i);     // loaded whatever the branch: no round trip inside it
         if (D(i) > 1e-12 * emax) {
-            const double pr = Y(i);
             s2 += pr * pr;
             s1 += fabs(pr);
             ++cnt;
@@ -244,7 +266,51 @@ __global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, 
 #undef D
 #undef E
 #undef Y
+}
+
+// lane = pixel; d, e, y of pixel lane in LDS columns (entry i at i * P + lane).
+__global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, int64_t pix0, int P,
+                                float *__restrict__ score, float *__restrict__ literal,
+                                int32_t *__restrict__ npos)
+{
+    extern __shared__ double sm[];
+    const int lane = threadIdx.x;
+    const int local = blockIdx.x * P + lane;
+    double *d = sm, *e = sm + (size_t)n * P, *y = sm + (size_t)2 * n * P;
+    const bool act = lane < P && local < npix;
+    if (!act) return;      // no barriers below: lanes are independent
+    const double *pix = ws + (size_t)local * (n + 2) * n;
+    for (int i = 0; i < n; ++i) {
+        d[i * P + lane] = pix[i];
+        e[i * P + lane] = pix[n + i];
+        y[i * P + lane] = pix[2 * n + i];
+    }
+    bool ok;
+    double s2, s1;
+    int cnt;
+    ql_pixel(d + lane, e + lane, y + lane, P, n, ok, s2, s1, cnt);
     const int64_t o = pix0 + local;
+    score[o] = ok ? (float)sqrt(s2) : NAN;
+    if (literal) literal[o] = ok ? (float)s1 : NAN;
+    if (npos) npos[o] = ok ? cnt : -1;
+}
+
+// lane = pixel q of a run of S pixels; d, e, y of pixel q in global columns: dey[i * S + q],
+// dey[(n + i) * S + q], dey[(2n + i) * S + q] (coalesced across a wavefront), updated in
+// place.  No LDS, so a launch holds as many pixels as the registers allow.
+__global__ __launch_bounds__(256) void ql_dwest_global_kernel(double *__restrict__ dey, int n, int64_t S,
+                                                              int64_t pix0, float *__restrict__ score,
+                                                              float *__restrict__ literal,
+                                                              int32_t *__restrict__ npos)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= S) return;
+    double *d = dey + q, *e = dey + (int64_t)n * S + q, *y = dey + (int64_t)2 * n * S + q;
+    bool ok;
+    double s2, s1;
+    int cnt;
+    ql_pixel(d, e, y, S, n, ok, s2, s1, cnt);
+    const int64_t o = pix0 + q;
     score[o] = ok ? (float)sqrt(s2) : NAN;
     if (literal) literal[o] = ok ? (float)s1 : NAN;
     if (npos) npos[o] = ok ? cnt : -1;
@@ -261,13 +327,28 @@ static int ql_pixels(int64_t n)
     return P;
 }
 
-int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score, float *literal,
-                     int32_t *npos, hipStream_t s)
+int ql_lds_pixels(int64_t n) { return ql_pixels(n); }
+
+int tridiag_dwest_launch(double *ws, int64_t n, int npix, double *dey, int64_t S, hipStream_t s)
 {
     const size_t sh = eig_smem(n);
     if (int rc = allow_lds((const void *)tridiag_dwest_kernel, sh, "tridiag_dwest_kernel")) return rc;
-    hipLaunchKernelGGL(tridiag_dwest_kernel, dim3((unsigned)npix), dim3(64), sh, s, ws, (int)n, npix);
-    if (int rc = check_launch("tridiag_dwest_kernel")) return rc;
+    hipLaunchKernelGGL(tridiag_dwest_kernel, dim3((unsigned)npix), dim3(64), sh, s, ws, (int)n, npix, dey, S);
+    return check_launch("tridiag_dwest_kernel");
+}
+
+int ql_dwest_global_launch(double *dey, int64_t n, int64_t S, int64_t pix0, float *score, float *literal,
+                           int32_t *npos, hipStream_t s)
+{
+    hipLaunchKernelGGL(ql_dwest_global_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, s, dey, (int)n, S,
+                       pix0, score, literal, npos);
+    return check_launch("ql_dwest_global_kernel");
+}
+
+int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score, float *literal,
+                     int32_t *npos, hipStream_t s)
+{
+    if (int rc = tridiag_dwest_launch(ws, n, npix, nullptr, 0, s)) return rc;
     const int P = ql_pixels(n);
     const size_t sq = (size_t)(3 * n * P) * sizeof(double);
     hipLaunchKernelGGL(ql_dwest_kernel, dim3((unsigned)((npix + P - 1) / P)), dim3(P), sq, s,

@@ -20,7 +20,14 @@ size_t jacobi_smem(int64_t n);
 size_t eig_smem(int64_t n);
 int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score, float *literal,
                      int32_t *npos, hipStream_t s);
-static int g_dwest_solver = 0;   // 0: Householder + implicit QL, 1: cyclic Jacobi (tests)
+int tridiag_dwest_launch(double *ws, int64_t n, int npix, double *dey, int64_t S, hipStream_t s);
+int ql_dwest_global_launch(double *dey, int64_t n, int64_t S, int64_t pix0, float *score, float *literal,
+                           int32_t *npos, hipStream_t s);
+int ql_lds_pixels(int64_t n);
+// Householder + implicit QL, 0: per chunk with LDS columns or over runs of pixels with
+// global columns, whichever suits L' and the chunk size; 2: per chunk (also the
+// small-workspace fallback); 3: over runs.  1: cyclic Jacobi.
+static int g_dwest_solver = 0;
 int jacobi_launch(const double *ws, int64_t n, int npix, int64_t pix0, float *score,
                   float *literal, int32_t *npos, hipStream_t s);
 
@@ -119,6 +126,41 @@ int generic_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const 
     return HSAD_OK;
 }
 
+// DWEST runs: the tridiagonal form of every pixel of a run (up to kQlRun pixels) is kept in
+// global columns (d, e, y: 3 L' doubles per pixel, pixel-minor) so that one QL launch holds
+// the whole run, a lane per pixel.  Per chunk (8192 pixels at mid L') that launch would be
+// one half-empty wavefront per CU.
+static constexpr int64_t kQlRun = (int64_t)1 << 20;
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Pixels of a run the workspace allows beside the chunk records (0: too small, use the
+// per-chunk path).  Records for 8192 pixels are reserved first; a run shorter than 8192
+// pixels is taken only when it covers the whole image.
+static int64_t ql_run_pixels(int64_t total, int64_t Lp, size_t ws_bytes)
+{
+    const size_t col = (size_t)(3 * Lp) * sizeof(double), rec = generic_ws_per_pixel(Lp, GRAM_DWEST);
+    const int64_t cap = total < kQlRun ? total : kQlRun;
+    int64_t S;
+    if (ws_bytes >= 256 + (rec + col) * 8192)
+        S = (int64_t)((ws_bytes - 256 - rec * 8192) / col);
+    else
+        S = ws_bytes > 256 ? (int64_t)((ws_bytes - 256) / (col + rec)) : 0;
+    if (S > cap) S = cap;
+    return S < cap && S < 8192 ? 0 : S;
+}
+
+size_t dwest_ws_bytes(int64_t H, int64_t W, int64_t Lp)
+{
+    const int64_t total = H * W;
+    const size_t rec = generic_ws_per_pixel(Lp, GRAM_DWEST);
+    size_t want = rec * (size_t)total;
+    const size_t cap = (size_t)1 << 30;
+    if (want > cap) want = (cap / rec) * rec;
+    const int64_t S = total < kQlRun ? total : kQlRun;
+    return align256((size_t)(3 * Lp) * sizeof(double) * (size_t)S) + want;
+}
+
 int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                   float *score, float *literal, int32_t *npos, void *ws, size_t ws_bytes,
                   hipStream_t s)
@@ -127,6 +169,32 @@ int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Window
     if ((jac ? jacobi_smem(Lp) : eig_smem(Lp)) > 160 * 1024 || gram_lds_per_wave(Lp, GP_FP64) > 160 * 1024)
         return fail(HSAD_EUNSUPPORTED, "hsad_dwest: L' above the eigensolver's LDS limit");
     const int64_t total = H * W;
+    // The LDS kernel is the faster one when its workgroups hold 64 pixels (L' <= 32) and a
+    // chunk holds enough of them (measured at 512 x 512: L' = 14 per chunk 5.0 ms, in runs
+    // 5.4 ms; L' = 28 and 56, 8192-30000-pixel chunks: runs 8 % and 43 % faster).
+    const bool chunk_first = ql_lds_pixels(Lp) == 64 &&
+                             chunk_pixels(total, Lp, ws_bytes) >= (total < 65536 ? total : 65536);
+    const bool runs = !jac && (g_dwest_solver == 3 || (g_dwest_solver == 0 && !chunk_first));
+    const int64_t S = runs ? ql_run_pixels(total, Lp, ws_bytes) : 0;
+    if (S > 0) {
+        double *dey = (double *)ws;
+        const size_t colb = align256((size_t)(3 * Lp) * sizeof(double) * (size_t)S);
+        double *rec = (double *)((char *)ws + colb);
+        const int64_t P = chunk_pixels(S, Lp, ws_bytes - colb);
+        if (P < 1) return fail(HSAD_ENOMEM, "hsad_dwest: workspace below one pixel");
+        for (int64_t s0 = 0; s0 < total; s0 += S) {
+            const int64_t sn = (total - s0) < S ? (total - s0) : S;
+            for (int64_t p0 = s0; p0 < s0 + sn; p0 += P) {
+                const int n = (int)((s0 + sn - p0) < P ? (s0 + sn - p0) : P);
+                int rc = gram_launch(x, H, W, Lp, w, GRAM_DWEST, GP_FP64, p0, n, rec, s);
+                if (rc) return rc;
+                rc = tridiag_dwest_launch(rec, Lp, n, dey + (p0 - s0), sn, s);
+                if (rc) return rc;
+            }
+            if (int rc = ql_dwest_global_launch(dey, Lp, sn, s0, score, literal, npos, s)) return rc;
+        }
+        return HSAD_OK;
+    }
     const int64_t P = chunk_pixels(total, Lp, ws_bytes);
     if (P < 1) return fail(HSAD_ENOMEM, "hsad_dwest: workspace below one pixel");
     for (int64_t p0 = 0; p0 < total; p0 += P) {
@@ -163,6 +231,6 @@ extern "C" int hsad_internal_generic_force(int mode)
 
 extern "C" int hsad_internal_dwest_solver(int solver)
 {
-    hsad::g_dwest_solver = solver == 1 ? 1 : 0;
+    hsad::g_dwest_solver = solver >= 1 && solver <= 3 ? solver : 0;
     return 0;
 }

@@ -67,6 +67,9 @@ enum GramPrec { GP_FP64 = 0, GP_FP32 = 1, GP_BF16 = 2, GP_FP16 = 3 };
 
 // Bytes of workspace per pixel and the fixed part for the generic path.
 size_t generic_ws_per_pixel(int64_t Lp, GramMode mode);
+// workspace hsad_workspace_bytes reports for DWEST: the QL columns of one run of pixels and
+// the chunk records
+size_t dwest_ws_bytes(int64_t H, int64_t W, int64_t Lp);
 int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                      double load_rel, GramPrec prec, float *lrx, float *dwrx, void *ws,
                      size_t ws_bytes, hipStream_t s);

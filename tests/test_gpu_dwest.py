@@ -3,8 +3,10 @@
 Scores (||V_P^T m_diff||_2), literal scores (sum_P |v_i^T m_diff|) and the number of
 positive eigenvalues are compared.  The score bound is an elementwise relative error
 <= 1e-3, with a floor of 1e-3 * median.  The positive-eigenvalue counts must match
-exactly.  Both GPU eigensolvers are covered: Householder tridiagonalisation + implicit QL
-(the default) and the cyclic Jacobi solver (selected through an internal switch).
+exactly.  Every GPU eigensolver mode is covered (selected through an internal switch):
+Householder tridiagonalisation + implicit QL over runs of pixels with the tridiagonal forms
+in global columns, the same QL per chunk with LDS columns (the default picks one of the
+two), and the cyclic Jacobi solver.
 """
 import numpy as np
 import pytest
@@ -17,10 +19,13 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-3
 
 
-@pytest.fixture(params=["ql", "jacobi"])
+SOLVERS = {"ql": 0, "jacobi": 1, "ql_chunk": 2, "ql_runs": 3}
+
+
+@pytest.fixture(params=sorted(SOLVERS))
 def solver(request):
     L_ = hs.lib()
-    L_.hsad_internal_dwest_solver(1 if request.param == "jacobi" else 0)
+    L_.hsad_internal_dwest_solver(SOLVERS[request.param])
     yield request.param
     L_.hsad_internal_dwest_solver(0)
 
@@ -88,3 +93,34 @@ def test_dwest_degenerate_and_short_spectra(solver):
     rs, rl, rn = oracle.dwest(x.astype(np.float64), 3, 7)
     assert np.array_equal(gn, rn)
     assert score_rel_err(gs, rs).max() <= TOL
+
+
+@pytest.mark.parametrize("mode", [3, 0])
+def test_dwest_runs_and_chunks_are_invariant(mode):
+    # A workspace that holds the QL columns of 8500 pixels and the records of 8192: a
+    # 100 x 100 image then takes two runs (8500 + 1500 pixels), the first in two Gram /
+    # tridiagonalisation chunks.  Every pixel's arithmetic is the same as in one run, so the
+    # maps must equal the default's bit for bit; sampled pixels of both runs are checked
+    # against the oracle.
+    import torch
+    H, W, Lp = 100, 100, 6
+    x = np.random.default_rng(77).standard_normal((H, W, Lp)).astype(np.float32)
+    x[..., 0] += np.linspace(0.0, 3.0, W, dtype=np.float32)[None, :]
+    t = torch.from_numpy(x).cuda()
+    L_ = hs.lib()
+    L_.hsad_internal_dwest_solver(mode)
+    try:
+        s0, l0, n0 = hs.hsad_dwest(t, 3, 7)
+        rec, col = (Lp + 2) * Lp * 8, 3 * Lp * 8
+        ws = torch.empty(256 + rec * 8192 + col * 8500 + 100, dtype=torch.uint8, device="cuda")
+        s1, l1, n1 = hs.hsad_dwest(t, 3, 7, ws=ws)
+        torch.cuda.synchronize()
+    finally:
+        L_.hsad_internal_dwest_solver(0)
+    assert np.array_equal(s0.cpu().numpy(), s1.cpu().numpy())
+    assert np.array_equal(l0.cpu().numpy(), l1.cpu().numpy())
+    assert np.array_equal(n0.cpu().numpy(), n1.cpu().numpy())
+    idx = np.array([0, 1, 99, 4321, 8191, 8192, 8499, 8500, 8501, 9998, 9999], dtype=np.int64)
+    rs, rl, rn = oracle.dwest(x.astype(np.float64), 3, 7, idx=idx)
+    assert np.array_equal(n1.cpu().numpy().ravel()[idx], rn)
+    assert score_rel_err(s1.cpu().numpy().ravel()[idx], rs).max() <= TOL
