@@ -28,16 +28,14 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <cstdint>
 
 #include "internal.hpp"
+#include "dev_lane.hpp"
 
 namespace hsad {
 
-__device__ __forceinline__ double wave_sum64(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
+
 
 __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
 
