@@ -17,8 +17,8 @@
 //      Bowdler, Martin, Reinsch and Wilkinson); the rotation's 1/r is the hardware
 //      reciprocal square root with two Newton steps.  Each plane rotation of a sweep is also
 //      applied to y, which keeps y = V^T m_diff.  A subdiagonal entry counts as zero once
-//      |e_m| <= eps (|d_m| + |d_m+1|), eps = 2^-52.  At most 64 sweeps per eigenvalue; a
-//      pixel that does not converge gets NaN scores.
+//      |e_m| <= eps max(|d_m| + |d_m+1|, max|d| + max|e| of the initial T), eps = 2^-52.
+//      At most 64 sweeps per eigenvalue; a pixel that does not converge gets NaN scores.
 // Eigenvalues above 1e-12 max|lambda| are "positive".  Outputs:
 //   score   = ||V_P^T m_diff||_2 = sqrt(sum_P y_i^2)
 //   literal = sum_P |y_i|          (eq. 4 with v_i signed so that v_i^T m_diff >= 0)
@@ -161,6 +161,16 @@ __device__ __forceinline__ void ql_pixel(double *__restrict__ d, double *__restr
 #define Y(i) y[(int64_t)(i) * st]
     ok = true;
     E(n - 1) = 0.0;
+    // deflation floor: eps times a bound of ||T|| (the iteration keeps the spectrum, so the
+    // bound of the initial T holds throughout).  Near-zero eigenvalues, which a rank-deficient
+    // C_diff has when a window holds fewer samples than bands, meet it; the pair test alone
+    // would never call their subdiagonal negligible.
+    double dnm = 0.0, enm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        dnm = fmax(dnm, fabs(D(i)));
+        enm = fmax(enm, fabs(E(i)));
+    }
+    const double tst = DBL_EPSILON * (dnm + enm);
     for (int l = 0; l < n && ok; ++l) {
         int iter = 0;
         for (;;) {
@@ -183,7 +193,8 @@ __device__ __forceinline__ void ql_pixel(double *__restrict__ d, double *__restr
                 int hit = -1;
 #pragma unroll
                 for (int k = 7; k >= 0; --k)
-                    if (m + k + 1 < n && fabs(ev[k]) <= DBL_EPSILON * (fabs(dv[k]) + fabs(dv[k + 1]))) hit = k;
+                    if (m + k + 1 < n && fabs(ev[k]) <= fmax(DBL_EPSILON * (fabs(dv[k]) + fabs(dv[k + 1])), tst))
+                        hit = k;
                 if (hit >= 0) {
                     m += hit;
                     break;

@@ -135,17 +135,19 @@ static constexpr int64_t kQlRun = (int64_t)1 << 20;
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Pixels of a run the workspace allows beside the chunk records (0: too small, use the
-// per-chunk path).  Records for 8192 pixels are reserved first; a run shorter than 8192
-// pixels is taken only when it covers the whole image.
+// per-chunk path).  Records for a chunk are reserved first: 8192 pixels, or what 1 GiB
+// holds for long spectra (the record cap of the reported workspace).  A run shorter than
+// 8192 pixels is taken only when it covers the whole image.
 static int64_t ql_run_pixels(int64_t total, int64_t Lp, size_t ws_bytes)
 {
     const size_t col = (size_t)(3 * Lp) * sizeof(double), rec = generic_ws_per_pixel(Lp, GRAM_DWEST);
     const int64_t cap = total < kQlRun ? total : kQlRun;
-    int64_t S;
-    if (ws_bytes >= 256 + (rec + col) * 8192)
-        S = (int64_t)((ws_bytes - 256 - rec * 8192) / col);
-    else
-        S = ws_bytes > 256 ? (int64_t)((ws_bytes - 256) / (col + rec)) : 0;
+    int64_t rp = 8192;
+    const int64_t rcap = (int64_t)(((size_t)1 << 30) / rec);
+    if (rp > rcap) rp = rcap > 0 ? rcap : 1;
+    if (rp > total) rp = total;
+    if (ws_bytes < 256 + rec * (size_t)rp + col) return 0;
+    int64_t S = (int64_t)((ws_bytes - 256 - rec * (size_t)rp) / col);
     if (S > cap) S = cap;
     return S < cap && S < 8192 ? 0 : S;
 }
