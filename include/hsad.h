@@ -156,8 +156,11 @@ int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_win
  * Householder tridiagonalisation followed by the implicit QL iteration, with every
  * transform also applied to m_diff (the eigenvectors are never formed); the eigenvalues
  * > 1e-12 * max|eigenvalue| are "positive".  A pixel whose QL iteration does not converge
- * within 64 sweeps per eigenvalue gets NaN scores and npos = -1.  Outputs, each a device
- * [y][x] array:
+ * within 64 sweeps per eigenvalue gets NaN scores and npos = -1.  With the workspace
+ * hsad_workspace_bytes reports, the tridiagonal forms of up to 2^20 pixels are kept in it
+ * (3 L' doubles each) so that one QL launch covers them all; a smaller workspace (down to
+ * the 1 x 1 minimum) runs the same arithmetic chunk by chunk.
+ * Outputs, each a device [y][x] array:
  *   scores         : ||V_P^T m_diff||_2 (invariant to eigenvector signs), float32
  *   scores_literal : sum_P |v_i^T m_diff| (eq. 4 with each v_i signed so that its
  *                    projection is >= 0), float32, may be NULL
