@@ -138,6 +138,7 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_dwt_force", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_chunk", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_width", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_feat_cfg", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwt_nt", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwest_solver", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_chol_cb", ctypes.c_int, [ctypes.c_int]),

@@ -73,13 +73,20 @@ FEAT = [(37, 29, 14, 5, 15), (20, 23, 5, 0, 9), (16, 40, 2, 1, 13), (45, 50, 7, 
         (70, 66, 3, 5, 63), (1, 1, 4, 0, 3), (3, 2, 14, 1, 3), (33, 31, 56, 3, 11)]
 
 
+# tile width: 32 where its LDS fits (the default) or 16, through the library's internal switch
+@pytest.mark.parametrize("tile", ["default", "w16"])
 @pytest.mark.parametrize("H,W,Lp,inner,outer", FEAT)
-def test_features_parity(H, W, Lp, inner, outer):
-    print("features", H, W, Lp, inner, outer, flush=True)
+def test_features_parity(H, W, Lp, inner, outer, tile):
+    print("features", H, W, Lp, inner, outer, tile, flush=True)
     import torch
     x, _ = _reduced(300 + Lp, H, W, Lp)
-    f = hs.hsad_surrogate_features(_t(x), inner, outer)
-    torch.cuda.synchronize()
+    L_ = hs.lib()
+    L_.hsad_internal_feat_cfg(1 if tile == "w16" else 0)
+    try:
+        f = hs.hsad_surrogate_features(_t(x), inner, outer)
+        torch.cuda.synchronize()
+    finally:
+        L_.hsad_internal_feat_cfg(0)
     got = f.cpu().numpy()
     idx = sample_pixels(H, W, 400, seed=Lp)
     ref = mlp.features(x.astype(np.float64), inner, outer, idx)
