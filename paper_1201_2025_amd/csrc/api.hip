@@ -237,7 +237,7 @@ size_t hsad_workspace_bytes(int op, int64_t H, int64_t W, int64_t Lp,
     t_err = keep;
     if (rc) return 0;
     if (op != HSAD_OP_DWEST && exact(p->precision) && box_supported(Lp, w)) return 0;
-    if (op == HSAD_OP_DWEST) return dwest_ws_bytes(H, W, Lp);
+    if (op == HSAD_OP_DWEST) return dwest_ws_bytes(H, W, Lp, w);
     const GramMode mode = GRAM_LRX;
     const size_t per = generic_ws_per_pixel(Lp, mode);
     // enough for every pixel in one launch, capped at 1 GiB (larger chunks gain nothing)

@@ -225,10 +225,13 @@ __device__ inline void bg_stage_all(const float *__restrict__ x, int H, int W, i
 // One tile: writes the raw records of its pixels (rows y0.., columns x0..) to
 // rec + (pixel - pix0) * rec_stride, or, with pix0 < 0, to rec + (ty * 16 + tx) * rec_stride
 // (tile-local records, as the batch engine allocates them).
+// With inner_rec set (DWEST), rows L'+3 .. 2L'+2 of the record also take the inner-window
+// second moments R_in,ij = (1/n_i) sum_inner f_i f_j (j >= i; diagonal NaN when the inner
+// window holds a flagged sample), so the record holds both covariances of eqs. 2-3.
 template <int RB = BG_RB>
 __device__ inline void boxg_tile(const float *__restrict__ x, int H, int W, int Lp, int R, int RI, int has_inner,
                                  double *__restrict__ rec, int64_t pix0, int64_t rec_stride, int by, int bx,
-                                 unsigned char *smem, int resident_kb)
+                                 unsigned char *smem, int resident_kb, int inner_rec = 0)
 {
     const int EX = BG_TX + 2 * R, EY = BG_TY + 2 * R;
     const int Lpad = bg_lpad(Lp);
@@ -349,6 +352,11 @@ __device__ inline void boxg_tile(const float *__restrict__ x, int H, int W, int 
                             double v = (S_out[4 * a + q] - S_in[4 * a + q]) * inv_na;
                             if (i == j && ann_bad) v = __builtin_nan("");
                             r[(size_t)i * Lp + j] = v;
+                            if (inner_rec) {
+                                double u = S_in[4 * a + q] * inv_ni;
+                                if (i == j && in_bad) u = __builtin_nan("");
+                                r[(size_t)(Lp + 3 + i) * Lp + j] = u;
+                            }
                         }
                     }
             }

@@ -45,8 +45,14 @@ __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
 // writes the lower triangle only (a predicated store after an unconditional read).
 // With dey set, d, e and y go to dey[i * S], dey[(n + i) * S] and dey[(2n + i) * S] (dey is
 // offset to the pixel's column, S the column count), else to the pixel's workspace.
+// rec_stride: doubles per pixel record.  raw = 0: a Gram record (rows 0..n-1 = C_diff,
+// row n = m_diff).  raw = 1: a box-statistics record with inner moments (rows 0..n-1 the
+// annulus moments R (j >= i), row n+1 m = m_inner - mu_ann, row n+2 mu_ann, rows n+3..2n+2
+// the inner moments R_in (j >= i), all of f = x - ref): C_diff = (R_in - mu_in mu_in^T) -
+// (R - mu_ann mu_ann^T) with mu_in = m + mu_ann, and m_diff = m.
 __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ ws, int n, int npix,
-                                                           double *__restrict__ dey, int64_t S)
+                                                           double *__restrict__ dey, int64_t S,
+                                                           int64_t rec_stride, int raw)
 {
     extern __shared__ double sm[];
     double *A = sm;                       // packed lower triangle, tri(n) doubles
@@ -56,25 +62,53 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
     const int lane = threadIdx.x;
     const int local = blockIdx.x;
     if (local >= npix) return;
-    double *pix = ws + (size_t)local * (n + 2) * n;
+    double *pix = ws + (size_t)local * rec_stride;
 
     // load: unconditional reads (index clamped) four at a time, predicated LDS stores
     const int nn = n * n;
-    for (int t0 = 0; t0 < nn; t0 += 4 * 64) {
-        double val[4];
+    if (!raw) {
+        for (int t0 = 0; t0 < nn; t0 += 4 * 64) {
+            double val[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int t = t0 + 64 * u + lane;
-            val[u] = pix[t < nn ? t : nn - 1];
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + 64 * u + lane;
+                val[u] = pix[t < nn ? t : nn - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + 64 * u + lane;
+                const int i = t / n, j = t - i * n;
+                if (t < nn && j <= i) A[tri(i) + j] = val[u];
+            }
         }
+        for (int i = lane; i < n; i += 64) y[i] = pix[(size_t)n * n + i];
+    } else {
+        // v <- mu_ann, q <- mu_in, y <- m first; then the upper triangles of R and R_in
+        for (int i = lane; i < n; i += 64) {
+            const double m = pix[(size_t)(n + 1) * n + i], mu = pix[(size_t)(n + 2) * n + i];
+            v[i] = mu;
+            q[i] = m + mu;
+            y[i] = m;
+        }
+        __syncthreads();
+        const double *rin = pix + (size_t)(n + 3) * n;
+        for (int t0 = 0; t0 < nn; t0 += 2 * 64) {
+            double ra[2], ri[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int t = t0 + 64 * u + lane;
-            const int i = t / n, j = t - i * n;
-            if (t < nn && j <= i) A[tri(i) + j] = val[u];
+            for (int u = 0; u < 2; ++u) {
+                const int t = t0 + 64 * u + lane, tc = t < nn ? t : nn - 1;
+                ra[u] = pix[tc];
+                ri[u] = rin[tc];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = t0 + 64 * u + lane;
+                const int r = t / n, c = t - r * n;   // stored at (r, c), c >= r: element (c, r)
+                if (t < nn && c >= r)
+                    A[tri(c) + r] = (ri[u] - q[r] * q[c]) - (ra[u] - v[r] * v[c]);
+            }
         }
     }
-    for (int i = lane; i < n; i += 64) y[i] = pix[(size_t)n * n + i];
     __syncthreads();
 
     for (int k = 0; k + 2 < n; ++k) {
@@ -280,7 +314,7 @@ __device__ __forceinline__ void ql_pixel(double *__restrict__ d, double *__restr
 // lane = pixel; d, e, y of pixel lane in LDS columns (entry i at i * P + lane).
 __global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, int64_t pix0, int P,
                                 float *__restrict__ score, float *__restrict__ literal,
-                                int32_t *__restrict__ npos)
+                                int32_t *__restrict__ npos, int64_t rec_stride)
 {
     extern __shared__ double sm[];
     const int lane = threadIdx.x;
@@ -288,7 +322,7 @@ __global__ void ql_dwest_kernel(const double *__restrict__ ws, int n, int npix, 
     double *d = sm, *e = sm + (size_t)n * P, *y = sm + (size_t)2 * n * P;
     const bool act = lane < P && local < npix;
     if (!act) return;      // no barriers below: lanes are independent
-    const double *pix = ws + (size_t)local * (n + 2) * n;
+    const double *pix = ws + (size_t)local * rec_stride;
     for (int i = 0; i < n; ++i) {
         d[i * P + lane] = pix[i];
         e[i * P + lane] = pix[n + i];
@@ -338,11 +372,13 @@ static int ql_pixels(int64_t n)
 
 int ql_lds_pixels(int64_t n) { return ql_pixels(n); }
 
-int tridiag_dwest_launch(double *ws, int64_t n, int npix, double *dey, int64_t S, hipStream_t s)
+int tridiag_dwest_launch(double *ws, int64_t n, int npix, double *dey, int64_t S, hipStream_t s, int raw)
 {
     const size_t sh = eig_smem(n);
     if (int rc = allow_lds((const void *)tridiag_dwest_kernel, sh, "tridiag_dwest_kernel")) return rc;
-    hipLaunchKernelGGL(tridiag_dwest_kernel, dim3((unsigned)npix), dim3(64), sh, s, ws, (int)n, npix, dey, S);
+    const int64_t stride = raw ? (int64_t)((2 * n + 3) * n) : (int64_t)((n + 2) * n);
+    hipLaunchKernelGGL(tridiag_dwest_kernel, dim3((unsigned)npix), dim3(64), sh, s, ws, (int)n, npix, dey, S, stride,
+                       raw);
     return check_launch("tridiag_dwest_kernel");
 }
 
@@ -355,13 +391,14 @@ int ql_dwest_global_launch(double *dey, int64_t n, int64_t S, int64_t pix0, floa
 }
 
 int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score, float *literal,
-                     int32_t *npos, hipStream_t s)
+                     int32_t *npos, hipStream_t s, int raw)
 {
-    if (int rc = tridiag_dwest_launch(ws, n, npix, nullptr, 0, s)) return rc;
+    if (int rc = tridiag_dwest_launch(ws, n, npix, nullptr, 0, s, raw)) return rc;
     const int P = ql_pixels(n);
     const size_t sq = (size_t)(3 * n * P) * sizeof(double);
+    const int64_t stride = raw ? (int64_t)((2 * n + 3) * n) : (int64_t)((n + 2) * n);
     hipLaunchKernelGGL(ql_dwest_kernel, dim3((unsigned)((npix + P - 1) / P)), dim3(P), sq, s,
-                       (const double *)ws, (int)n, npix, pix0, P, score, literal, npos);
+                       (const double *)ws, (int)n, npix, pix0, P, score, literal, npos, stride);
     return check_launch("ql_dwest_kernel");
 }
 

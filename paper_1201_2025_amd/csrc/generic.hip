@@ -15,12 +15,12 @@ size_t chol_smem(int64_t Lp);
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
                 float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img, int raw);
 int boxg_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, int tile_row0, int ntile_rows,
-                double *rec, hipStream_t s);
+                double *rec, hipStream_t s, int inner_rec = 0);
 size_t jacobi_smem(int64_t n);
 size_t eig_smem(int64_t n);
 int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score, float *literal,
-                     int32_t *npos, hipStream_t s);
-int tridiag_dwest_launch(double *ws, int64_t n, int npix, double *dey, int64_t S, hipStream_t s);
+                     int32_t *npos, hipStream_t s, int raw = 0);
+int tridiag_dwest_launch(double *ws, int64_t n, int npix, double *dey, int64_t S, hipStream_t s, int raw = 0);
 int ql_dwest_global_launch(double *dey, int64_t n, int64_t S, int64_t pix0, float *score, float *literal,
                            int32_t *npos, hipStream_t s);
 int ql_lds_pixels(int64_t n);
@@ -54,9 +54,9 @@ static int64_t chunk_pixels(int64_t total, int64_t Lp, size_t ws_bytes)
 
 // Tile-row bands per chunk of the box-statistics path: as many as the workspace holds, at
 // most what keeps ~4096 tiles (16 per CU) in flight, within 8 GiB of records.
-int64_t boxg_chunk_bands(int64_t H, int64_t W, int64_t Lp, size_t ws_bytes)
+int64_t boxg_chunk_bands(int64_t H, int64_t W, int64_t Lp, size_t ws_bytes, int inner_rec)
 {
-    const int64_t band_bytes = (int64_t)(boxg_record_doubles(Lp) * sizeof(double)) * 16 * W;
+    const int64_t band_bytes = (int64_t)(boxg_record_doubles(Lp, inner_rec) * sizeof(double)) * 16 * W;
     const int64_t total = (H + 15) / 16, tiles_per_band = (W + 15) / 16;
     int64_t want = (4096 + tiles_per_band - 1) / tiles_per_band;
     const int64_t cap = ((int64_t)8 << 30) / band_bytes;
@@ -152,7 +152,16 @@ static int64_t ql_run_pixels(int64_t total, int64_t Lp, size_t ws_bytes)
     return S < cap && S < 8192 ? 0 : S;
 }
 
-size_t dwest_ws_bytes(int64_t H, int64_t W, int64_t Lp)
+// Tile rows per DWEST run on the box-statistics path (a run is a whole number of tile rows).
+static int64_t dwest_run_rows(int64_t H, int64_t W)
+{
+    const int64_t ntr = (H + 15) / 16;
+    int64_t rt = kQlRun / (16 * W);
+    if (rt < 1) rt = 1;
+    return rt < ntr ? rt : ntr;
+}
+
+size_t dwest_ws_bytes(int64_t H, int64_t W, int64_t Lp, const Windows &w)
 {
     const int64_t total = H * W;
     const size_t rec = generic_ws_per_pixel(Lp, GRAM_DWEST);
@@ -160,7 +169,70 @@ size_t dwest_ws_bytes(int64_t H, int64_t W, int64_t Lp)
     const size_t cap = (size_t)1 << 30;
     if (want > cap) want = (cap / rec) * rec;
     const int64_t S = total < kQlRun ? total : kQlRun;
-    return align256((size_t)(3 * Lp) * sizeof(double) * (size_t)S) + want;
+    size_t bytes = align256((size_t)(3 * Lp) * sizeof(double) * (size_t)S) + want;
+    if (boxg_supported(Lp, w)) {
+        // box statistics: the columns of one run of tile rows and records for the bands
+        const int64_t rt = dwest_run_rows(H, W);
+        int64_t bands = boxg_chunk_bands(H, W, Lp, (size_t)-1 / 2, 1);
+        if (bands > rt) bands = rt;
+        const int64_t rows = rt * 16 < H ? rt * 16 : H;
+        const size_t b2 = align256((size_t)(3 * Lp) * sizeof(double) * (size_t)(rows * W)) +
+                          (size_t)bands * 16 * (size_t)W * boxg_record_doubles(Lp, 1) * sizeof(double);
+        if (b2 > bytes) bytes = b2;
+    }
+    return bytes;
+}
+
+static int g_dwest_stats = 0;   // 0: box statistics where supported, 1: matrix-core Gram (tests)
+
+// DWEST from box statistics: the box kernel writes, per band of tile rows, records with the
+// annulus and the inner-window moments; the tridiagonalisation forms C_diff from them.
+// Returns 1 when the workspace is too small for this path (the caller takes the Gram path).
+static int dwest_boxg(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w, float *score,
+                      float *literal, int32_t *npos, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int64_t total = H * W, ntr = (H + 15) / 16;
+    const int64_t all_bands = boxg_chunk_bands(H, W, Lp, ws_bytes, 1);
+    const bool chunk_first = g_dwest_solver == 2 ||
+                             (g_dwest_solver == 0 && ql_lds_pixels(Lp) == 64 &&
+                              all_bands * 16 * W >= (total < 65536 ? total : 65536));
+    if (chunk_first) {
+        if (all_bands < 1) return 1;
+        double *recs = (double *)ws;
+        for (int64_t b0 = 0; b0 < ntr; b0 += all_bands) {
+            const int64_t nb = ntr - b0 < all_bands ? ntr - b0 : all_bands;
+            int rc = boxg_launch(x, H, W, Lp, w, (int)b0, (int)nb, recs, s, 1);
+            if (rc) return rc;
+            const int64_t y1 = (b0 + nb) * 16 < H ? (b0 + nb) * 16 : H;
+            const int64_t p0 = b0 * 16 * W, n = y1 * W - p0;
+            rc = eig_dwest_launch(recs, Lp, (int)n, p0, score, literal, npos, s, 1);
+            if (rc) return rc;
+        }
+        return HSAD_OK;
+    }
+    const int64_t rt = dwest_run_rows(H, W);
+    const int64_t rows = rt * 16 < H ? rt * 16 : H;
+    const size_t colb = align256((size_t)(3 * Lp) * sizeof(double) * (size_t)(rows * W));
+    if (ws_bytes <= colb) return 1;
+    int64_t bands = boxg_chunk_bands(H, W, Lp, ws_bytes - colb, 1);
+    if (bands > rt) bands = rt;
+    if (bands < 1) return 1;
+    double *dey = (double *)ws, *recs = (double *)((char *)ws + colb);
+    for (int64_t tr0 = 0; tr0 < ntr; tr0 += rt) {
+        const int64_t tr1 = tr0 + rt < ntr ? tr0 + rt : ntr;
+        const int64_t s0 = tr0 * 16 * W, s1 = (tr1 * 16 < H ? tr1 * 16 : H) * W, sn = s1 - s0;
+        for (int64_t b0 = tr0; b0 < tr1; b0 += bands) {
+            const int64_t nb = tr1 - b0 < bands ? tr1 - b0 : bands;
+            int rc = boxg_launch(x, H, W, Lp, w, (int)b0, (int)nb, recs, s, 1);
+            if (rc) return rc;
+            const int64_t y1 = (b0 + nb) * 16 < H ? (b0 + nb) * 16 : H;
+            const int64_t p0 = b0 * 16 * W, n = y1 * W - p0;
+            rc = tridiag_dwest_launch(recs, Lp, (int)n, dey + (p0 - s0), sn, s, 1);
+            if (rc) return rc;
+        }
+        if (int rc = ql_dwest_global_launch(dey, Lp, sn, s0, score, literal, npos, s)) return rc;
+    }
+    return HSAD_OK;
 }
 
 int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
@@ -170,6 +242,10 @@ int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Window
     const bool jac = g_dwest_solver == 1;
     if ((jac ? jacobi_smem(Lp) : eig_smem(Lp)) > 160 * 1024 || gram_lds_per_wave(Lp, GP_FP64) > 160 * 1024)
         return fail(HSAD_EUNSUPPORTED, "hsad_dwest: L' above the eigensolver's LDS limit");
+    if (!jac && g_dwest_stats == 0 && boxg_supported(Lp, w)) {
+        const int rc = dwest_boxg(x, H, W, Lp, w, score, literal, npos, ws, ws_bytes, s);
+        if (rc != 1) return rc;
+    }
     const int64_t total = H * W;
     // The LDS kernel is the faster one when its workgroups hold 64 pixels (L' <= 32) and a
     // chunk holds enough of them (measured at 512 x 512: L' = 14 per chunk 5.0 ms, in runs
@@ -234,5 +310,11 @@ extern "C" int hsad_internal_generic_force(int mode)
 extern "C" int hsad_internal_dwest_solver(int solver)
 {
     hsad::g_dwest_solver = solver >= 1 && solver <= 3 ? solver : 0;
+    return 0;
+}
+
+extern "C" int hsad_internal_dwest_stats(int gram)
+{
+    hsad::g_dwest_stats = gram ? 1 : 0;
     return 0;
 }

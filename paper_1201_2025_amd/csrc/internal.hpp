@@ -57,8 +57,8 @@ int threshold_from_partials(const float *scores, int64_t n, const double *part, 
 
 // ---- box-sum statistics for mid-size L' (boxg.hip) ----
 bool boxg_supported(int64_t Lp, const Windows &w);
-size_t boxg_record_doubles(int64_t Lp);
-int64_t boxg_chunk_bands(int64_t H, int64_t W, int64_t Lp, size_t ws_bytes);
+size_t boxg_record_doubles(int64_t Lp, int inner_rec = 0);
+int64_t boxg_chunk_bands(int64_t H, int64_t W, int64_t Lp, size_t ws_bytes, int inner_rec = 0);
 int boxg_resident_kb();
 
 // ---- generic Gram + factorisation path (gram.hip, chol.hip, jacobi.hip) ----
@@ -69,7 +69,7 @@ enum GramPrec { GP_FP64 = 0, GP_FP32 = 1, GP_BF16 = 2, GP_FP16 = 3 };
 size_t generic_ws_per_pixel(int64_t Lp, GramMode mode);
 // workspace hsad_workspace_bytes reports for DWEST: the QL columns of one run of pixels and
 // the chunk records
-size_t dwest_ws_bytes(int64_t H, int64_t W, int64_t Lp);
+size_t dwest_ws_bytes(int64_t H, int64_t W, int64_t Lp, const Windows &w);
 int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                      double load_rel, GramPrec prec, float *lrx, float *dwrx, void *ws,
                      size_t ws_bytes, hipStream_t s);

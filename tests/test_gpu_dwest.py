@@ -6,7 +6,8 @@ positive eigenvalues are compared.  The score bound is an elementwise relative e
 exactly.  Every GPU eigensolver mode is covered (selected through an internal switch):
 Householder tridiagonalisation + implicit QL over runs of pixels with the tridiagonal forms
 in global columns, the same QL per chunk with LDS columns (the default picks one of the
-two), and the cyclic Jacobi solver.
+two), and the cyclic Jacobi solver; the window statistics from box sums (the default where
+supported) or from the matrix-core Gram.
 """
 import numpy as np
 import pytest
@@ -19,15 +20,20 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-3
 
 
-SOLVERS = {"ql": 0, "jacobi": 1, "ql_chunk": 2, "ql_runs": 3}
+# (solver switch, statistics: 0 box sums where supported / 1 matrix-core Gram)
+SOLVERS = {"ql": (0, 0), "jacobi": (1, 0), "ql_chunk": (2, 0), "ql_runs": (3, 0), "ql_gram": (0, 1),
+           "ql_runs_gram": (3, 1)}
 
 
 @pytest.fixture(params=sorted(SOLVERS))
 def solver(request):
     L_ = hs.lib()
-    L_.hsad_internal_dwest_solver(SOLVERS[request.param])
+    sv, st = SOLVERS[request.param]
+    L_.hsad_internal_dwest_solver(sv)
+    L_.hsad_internal_dwest_stats(st)
     yield request.param
     L_.hsad_internal_dwest_solver(0)
+    L_.hsad_internal_dwest_stats(0)
 
 
 def _gpu(x, inner, outer):
@@ -95,13 +101,15 @@ def test_dwest_degenerate_and_short_spectra(solver):
     assert score_rel_err(gs, rs).max() <= TOL
 
 
+@pytest.mark.parametrize("stats", [1, 0])
 @pytest.mark.parametrize("mode", [3, 0])
-def test_dwest_runs_and_chunks_are_invariant(mode):
-    # A workspace that holds the QL columns of 8500 pixels and the records of 8192: a
-    # 100 x 100 image then takes two runs (8500 + 1500 pixels), the first in two Gram /
-    # tridiagonalisation chunks.  Every pixel's arithmetic is the same as in one run, so the
-    # maps must equal the default's bit for bit; sampled pixels of both runs are checked
-    # against the oracle.
+def test_dwest_runs_and_chunks_are_invariant(mode, stats):
+    # A small workspace: with the Gram statistics it holds the QL columns of 8500 pixels and
+    # the records of 8192, so a 100 x 100 image takes two runs (8500 + 1500 pixels), the first
+    # in two Gram / tridiagonalisation chunks; with box statistics it holds one run of the
+    # whole image and records of two bands of tile rows at a time.  Every pixel's arithmetic
+    # is the same as with the default workspace, so the maps must equal the default's bit
+    # for bit; sampled pixels of both runs are checked against the oracle.
     import torch
     H, W, Lp = 100, 100, 6
     x = np.random.default_rng(77).standard_normal((H, W, Lp)).astype(np.float32)
@@ -109,6 +117,7 @@ def test_dwest_runs_and_chunks_are_invariant(mode):
     t = torch.from_numpy(x).cuda()
     L_ = hs.lib()
     L_.hsad_internal_dwest_solver(mode)
+    L_.hsad_internal_dwest_stats(stats)
     try:
         s0, l0, n0 = hs.hsad_dwest(t, 3, 7)
         rec, col = (Lp + 2) * Lp * 8, 3 * Lp * 8
@@ -117,6 +126,7 @@ def test_dwest_runs_and_chunks_are_invariant(mode):
         torch.cuda.synchronize()
     finally:
         L_.hsad_internal_dwest_solver(0)
+        L_.hsad_internal_dwest_stats(0)
     assert np.array_equal(s0.cpu().numpy(), s1.cpu().numpy())
     assert np.array_equal(l0.cpu().numpy(), l1.cpu().numpy())
     assert np.array_equal(n0.cpu().numpy(), n1.cpu().numpy())
