@@ -35,6 +35,7 @@ __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_re
     double *panel = sm;                        // rows x NB (row stride NB+1)
     double *red = sm + (size_t)rows * (NB + 1);
     double &bad = red[6];                      // 0/1 flag shared by the workgroup
+    double *pinv = red + 8;                    // NB reciprocal pivots of the current panel
     const int tid = threadIdx.x, nt = blockDim.x;
     if (raw) {
         const double *mu = A + (size_t)(Lp + 2) * Lp;
@@ -64,26 +65,27 @@ __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_re
             panel[(size_t)r * (NB + 1) + c] = A[(size_t)(kb + r) * Lp + kb + c];
         }
         __syncthreads();
-        // unblocked factorisation of the panel
+        // unblocked factorisation of the panel, one barrier per column: column j is left
+        // unscaled during its step and the rank-1 update takes a_rj a_cj / d_j; the panel's
+        // columns are scaled by 1/sqrt(d_j) in one pass at the end.  Thread (tid & 31, tid >> 5)
+        // updates column j+1+(tid & 31), rows j+1+(tid >> 5) + k (nt / 32).
+        const int cl = tid & 31, rg = tid >> 5, nrg = nt >> 5;
         for (int j = 0; j < nb; ++j) {
             const double d = panel[(size_t)j * (NB + 1) + j];
             if (!(d > 0.0) && tid == 0) bad = 1.0;
-            const double inv = 1.0 / sqrt(d);
-            __syncthreads();
-            for (int r = j + tid; r < prow; r += nt) panel[(size_t)r * (NB + 1) + j] *= inv;
-            __syncthreads();
-            // rank-1 update of panel columns j+1..nb-1, rows >= column
-            const int ncol = nb - j - 1;
-            if (ncol > 0) {
-                const int nrow = prow - j - 1;
-                for (int t = tid; t < nrow * ncol; t += nt) {
-                    const int r = j + 1 + t / ncol, c = j + 1 + t % ncol;
-                    if (c <= r) panel[(size_t)r * (NB + 1) + c] -=
-                        panel[(size_t)r * (NB + 1) + j] * panel[(size_t)c * (NB + 1) + j];
-                }
+            const int c = j + 1 + cl;
+            if (c < nb) {
+                const double acj = panel[(size_t)c * (NB + 1) + j] / d;
+                for (int r = j + 1 + rg; r < prow; r += nrg)
+                    if (c <= r) panel[(size_t)r * (NB + 1) + c] -= panel[(size_t)r * (NB + 1) + j] * acj;
             }
             __syncthreads();
         }
+        if (tid < nb) pinv[tid] = 1.0 / sqrt(panel[(size_t)tid * (NB + 1) + tid]);
+        __syncthreads();
+        if (cl < nb)
+            for (int r = cl + rg; r < prow; r += nrg) panel[(size_t)r * (NB + 1) + cl] *= pinv[cl];
+        __syncthreads();
         // write the factored panel back (only the part the later panels / scores read)
         for (int t = tid; t < prow * nb; t += nt) {
             const int r = t / nb, c = t - r * nb;
@@ -145,7 +147,7 @@ __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_re
 }
 
 
-__host__ __device__ inline size_t chol_smem_doubles(int Lp) { return (size_t)(Lp + 2) * (NB + 1) + 8; }
+__host__ __device__ inline size_t chol_smem_doubles(int Lp) { return (size_t)(Lp + 2) * (NB + 1) + 8 + NB; }
 
 }  // namespace hsad
 
