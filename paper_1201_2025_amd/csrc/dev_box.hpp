@@ -310,25 +310,49 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
                 }
             }
             __syncthreads();
-            // 2b. running (prefix) sums along each tile row, in place: V[ty][c] becomes
-            //     sum_{c' <= c} V[ty][c'], one thread per (row, feature)
-            for (int job = tid; job < TY * C::GC; job += NT) {
-                const int r = job / C::GC, gg = job - r * C::GC;
-                double run = 0.0;
-                double *v = V + (size_t)r * EX * C::GCP + gg;
-                for (int c = 0; c < EX; ++c) {
-                    run += v[(size_t)c * C::GCP];
-                    v[(size_t)c * C::GCP] = run;
+            // 2b. horizontal window sums: one job per (row, feature, segment of HS outputs).
+            //     The segment's first sum is taken directly (2h+1 terms, four chains), the
+            //     rest slide by one column; the results wait in registers for a barrier and
+            //     then overwrite the row's first TX columns.  A dependency chain of about
+            //     HS + 4 adds per job where a running sum along the row was EX long.
+            constexpr int HS = TY * C::GC * (TX / 8) <= NT ? 8 : TY * C::GC * (TX / 16) <= NT ? 16 : 32;
+            constexpr int NSEG = TX / HS;
+            static_assert(TY * C::GC * NSEG <= NT, "one horizontal job per thread");
+            double hv[HS];
+            const bool hjob = tid < TY * C::GC * NSEG;
+            const int hr = tid / (C::GC * NSEG), hrem = tid - hr * (C::GC * NSEG);
+            const int hg = hrem / NSEG, hx0 = (hrem - hg * NSEG) * HS;
+            if (hjob) {
+                const double *v = V + ((size_t)hr * EX + hx0 + eoff) * C::GCP + hg;
+                double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+                int k = 0;
+                for (; k + 3 <= 2 * h; k += 4) {
+                    r0 += v[(size_t)k * C::GCP];
+                    r1 += v[(size_t)(k + 1) * C::GCP];
+                    r2 += v[(size_t)(k + 2) * C::GCP];
+                    r3 += v[(size_t)(k + 3) * C::GCP];
+                }
+                for (; k <= 2 * h; ++k) r0 += v[(size_t)k * C::GCP];
+                double run = (r0 + r1) + (r2 + r3);
+                hv[0] = run;
+#pragma unroll
+                for (int q = 1; q < HS; ++q) {
+                    run += v[(size_t)(q + 2 * h) * C::GCP] - v[(size_t)(q - 1) * C::GCP];
+                    hv[q] = run;
                 }
             }
             __syncthreads();
-            // 2c. horizontal box sum of this thread's pixel = difference of two prefixes
-            const int c_hi = tx + eoff + 2 * h, c_lo = tx + eoff - 1;
-            const double *vhi = V + ((size_t)ty * EX + c_hi) * C::GCP;
-            const double *vlo = V + ((size_t)ty * EX + (c_lo < 0 ? 0 : c_lo)) * C::GCP;
+            if (hjob) {
+                double *o = V + ((size_t)hr * EX + hx0) * C::GCP + hg;
+#pragma unroll
+                for (int q = 0; q < HS; ++q) o[(size_t)q * C::GCP] = hv[q];
+            }
+            __syncthreads();
+            // 2c. this thread's pixel: its window sums are now at column tx of row ty
+            const double *vh = V + ((size_t)ty * EX + tx) * C::GCP;
             double hsum[C::GC];
 #pragma unroll
-            for (int gg = 0; gg < C::GC; ++gg) hsum[gg] = vhi[gg] - (c_lo < 0 ? 0.0 : vlo[gg]);
+            for (int gg = 0; gg < C::GC; ++gg) hsum[gg] = vh[gg];
 #pragma unroll
             for (int gg = 0; gg < C::GC; ++gg) {
                 const int g = g0 + gg;
