@@ -119,17 +119,29 @@ __device__ inline void bg_window_sums(const Feat &feat, int EX, int R, int RI, i
             }
         }
         __syncthreads();
-        for (int job = tid; job < BG_TY * NF; job += BG_NT) {
-            const int r = job / NF, g = job - r * NF;
-            const double *v = V + (size_t)r * EX * BG_VS + g;
-            double run = 0.0;
-#pragma unroll 4
-            for (int c = eoff; c <= eoff + 2 * h; ++c) run += v[(size_t)c * BG_VS];
-            double *hs = Hs + (size_t)r * BG_TX * 8 + g;
+        // horizontal: one job per (row, feature, HSG outputs); the segment's first sum
+        // directly (four chains), the rest sliding
+        constexpr int HSG = BG_TY * NF * (BG_TX / 8) <= BG_NT ? 8 : 16;
+        constexpr int NSG = BG_TX / HSG;
+        for (int job = tid; job < BG_TY * NF * NSG; job += BG_NT) {
+            const int r = job / (NF * NSG), rem = job - r * (NF * NSG);
+            const int g = rem / NSG, x0 = (rem - g * NSG) * HSG;
+            const double *v = V + ((size_t)r * EX + x0 + eoff) * BG_VS + g;
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+            int k = 0;
+            for (; k + 3 <= 2 * h; k += 4) {
+                r0 += v[(size_t)k * BG_VS];
+                r1 += v[(size_t)(k + 1) * BG_VS];
+                r2 += v[(size_t)(k + 2) * BG_VS];
+                r3 += v[(size_t)(k + 3) * BG_VS];
+            }
+            for (; k <= 2 * h; ++k) r0 += v[(size_t)k * BG_VS];
+            double run = (r0 + r1) + (r2 + r3);
+            double *hs = Hs + ((size_t)r * BG_TX + x0) * 8 + g;
             hs[0] = run;
-#pragma unroll 5
-            for (int q = 1; q < BG_TX; ++q) {
-                run += v[(size_t)(q + eoff + 2 * h) * BG_VS] - v[(size_t)(q + eoff - 1) * BG_VS];
+#pragma unroll
+            for (int q = 1; q < HSG; ++q) {
+                run += v[(size_t)(q + 2 * h) * BG_VS] - v[(size_t)(q - 1) * BG_VS];
                 hs[(size_t)q * 8] = run;
             }
         }
