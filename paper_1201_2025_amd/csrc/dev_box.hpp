@@ -269,9 +269,11 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
             // win 0: inner window (half RI), win 1: outer window (half R)
             const int h = win == 0 ? RI : R;
             const int eoff = R - h;            // first extended row/col of the window
-            // 2a. vertical sums: job = (column c, row block rb)
-            for (int job = tid; job < EX * NRB; job += NT) {
-                const int rb = job / EX, c = job - rb * EX;
+            // 2a. vertical sums: job = (column c, row block rb), for the TX + 2h columns the
+            //     window's horizontal sums read (eoff .. eoff + TX + 2h - 1)
+            const int EW = TX + 2 * h;
+            for (int job = tid; job < EW * NRB; job += NT) {
+                const int rb = job / EW, c = eoff + (job - rb * EW);
                 const int r0 = rb * RB;
                 double acc[C::GC];
 #pragma unroll

@@ -88,8 +88,10 @@ __device__ inline void bg_window_sums(const Feat &feat, int EX, int R, int RI, i
     for (int g = 0; g < NF; ++g) S_in[g] = 0.0;
     for (int win = has_inner ? 0 : 1; win < 2; ++win) {
         const int h = win == 0 ? RI : R, eoff = R - h;
-        for (int job = tid; job < EX * (BG_TY / RB); job += BG_NT) {
-            const int rb = job / EX, c = job - rb * EX, r0 = rb * RB;
+        // vertical: only the BG_TX + 2h columns this window's horizontal sums read
+        const int EW = BG_TX + 2 * h;
+        for (int job = tid; job < EW * (BG_TY / RB); job += BG_NT) {
+            const int rb = job / EW, c = eoff + (job - rb * EW), r0 = rb * RB;
             double acc[NF];
 #pragma unroll
             for (int g = 0; g < NF; ++g) acc[g] = 0.0;
