@@ -327,8 +327,8 @@ def bench_surrogate(args, dev, log):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the per-GPU "
-              "workload is the whole cube; see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the workload is "
+              "the whole cube on one GPU; --gpus must be 1).", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1201_2025_amd as hs
