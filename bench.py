@@ -18,7 +18,7 @@ printed.  Beside the timed step, the script also measures:
   * the FP64 CPU oracle on the host cores, for the same workload (cpu_baseline);
   * the 64-scene uneven batch through the persistent batch engine;
   * DWEST (eqs. 2-4) at L' = 14 / 28 / 56 on the same cube (inner 3, outer 11);
-  * the paper's image shapes and windows (P1, P2), each detector with and without the DWT;
+  * the paper's image shapes and windows (60x100x189, 100x100x189), each detector with and without the DWT;
   * the learned surrogate: exact vs hybrid LRX on a 2048 x 2048 x 224 scene at L' = 14
     and 56, with the change of ROC AUC.
 """
@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batch measurement")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--no-dwest", action="store_true", help="skip the DWEST measurement")
-    ap.add_argument("--no-paper-shaped", action="store_true", help="skip the paper-shaped P1/P2 runs")
+    ap.add_argument("--no-paper-shaped", action="store_true", help="skip the paper-shaped 60x100x189 and 100x100x189 runs")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate measurement")
     ap.add_argument("--surrogate-scenes", type=int, default=200,
                     help="training scenes of 256x256x224 for the surrogate (200 in the full workload)")
@@ -174,7 +174,7 @@ def bench_dwest(cube, dev, log):
                     "nominal_fp64_tflops": nominal / (ms * 1e-3) / 1e12})
         log("dwest L'=%d: %.2f ms" % (Lp, ms))
         del ws
-    return {"workload": "512x512x224 cube (C2 recipe) at L' = 14/28/56, inner 3, outer 11", "levels": out}
+    return {"workload": "512x512x224 cube (150 singles + 50 blobs) at L' = 14/28/56, inner 3, outer 11", "levels": out}
 
 
 def bench_paper_shaped(dev, log):
@@ -200,7 +200,7 @@ def bench_paper_shaped(dev, log):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    for name in ("P1", "P2"):
+    for name in ("img1_60x100x189", "img2_100x100x189"):
         c = synth.CONFIGS[name]
         sc = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"],
                               n_blob=c["n_blob"])
@@ -228,7 +228,7 @@ def bench_surrogate(args, dev, log):
     import torch
     import paper_1201_2025_amd as hs
     from paper_1201_2025_amd import synth
-    ct, ci = synth.CONFIGS["C5_train"], synth.CONFIGS["C5_infer"]
+    ct, ci = synth.CONFIGS["surrogate_train_256x256x224"], synth.CONFIGS["surrogate_use_2048x2048x224"]
     inner, outer, load = ct["inner"], ct["outer"], ct["load_rel"]
     t0 = time.perf_counter()
     cube, truth, _ = synth.make_scene_torch(ci["seed"], ci["H"], ci["W"], 224, K=ci["K"],
@@ -338,7 +338,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    c = synth.CONFIGS["C2"]
+    c = synth.CONFIGS["cube_512x512x224"]
     H, W, L = c["H"], c["W"], c["L"]
     J = hs.hsad_levels_for(L, 4) if args.level is None else args.level
     Lp = hs.hsad_dwt_out_len(L, J)

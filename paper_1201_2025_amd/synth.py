@@ -162,23 +162,23 @@ def random_cube(seed: int, H: int, W: int, L: int, scale: float = 1.0) -> np.nda
 # Named workloads.  Window sizes are (inner, outer); levels is the DWT depth.
 CONFIGS = {
     # plain method, parity-sized
-    "C1": dict(seed=1201, H=64, W=64, L=224, K=4, n_single=12, n_blob=0, levels=6,
+    "small_64x64x224": dict(seed=1201, H=64, W=64, L=224, K=4, n_single=12, n_blob=0, levels=6,
                inner=3, outer=9, load_rel=1e-6),
     # headline cube: levels 0 (full band) .. 6
-    "C2": dict(seed=1202, H=512, W=512, L=224, K=8, n_single=150, n_blob=50, levels=6,
+    "cube_512x512x224": dict(seed=1202, H=512, W=512, L=224, K=8, n_single=150, n_blob=50, levels=6,
                inner=5, outer=15, load_rel=1e-6),
-    # DWEST on the C2 cube at L' = 14 / 28 / 56
-    "C3": dict(seed=1202, H=512, W=512, L=224, K=8, n_single=150, n_blob=50,
+    # DWEST on the 512 x 512 x 224 cube at L' = 14 / 28 / 56
+    "dwest_512x512x224": dict(seed=1202, H=512, W=512, L=224, K=8, n_single=150, n_blob=50,
                levels=(4, 3, 2), inner=3, outer=11),
     # surrogate: training scenes (seed 1205 + i) and the inference scene
-    "C5_train": dict(seed=1205, H=256, W=256, L=224, K=8, n_single=40, n_blob=10,
+    "surrogate_train_256x256x224": dict(seed=1205, H=256, W=256, L=224, K=8, n_single=40, n_blob=10,
                      levels=4, inner=5, outer=15, load_rel=1e-6, n_scenes=200),
-    "C5_infer": dict(seed=1299, H=2048, W=2048, L=224, K=8, n_single=2560, n_blob=640,
+    "surrogate_use_2048x2048x224": dict(seed=1299, H=2048, W=2048, L=224, K=8, n_single=2560, n_blob=640,
                      levels=4, inner=5, outer=15, load_rel=1e-6),
     # stand-ins for the paper's Img1 / Img2 shapes (Sec. 5.1, windows of Sec. 5.2)
-    "P1": dict(seed=1301, H=60, W=100, L=189, K=6, n_single=10, n_blob=4, levels=5,
+    "img1_60x100x189": dict(seed=1301, H=60, W=100, L=189, K=6, n_single=10, n_blob=4, levels=5,
                lrx_inner=1, lrx_outer=15, inner=5, outer=13, load_rel=1e-6),
-    "P2": dict(seed=1302, H=100, W=100, L=189, K=6, n_single=30, n_blob=2, levels=5,
+    "img2_100x100x189": dict(seed=1302, H=100, W=100, L=189, K=6, n_single=30, n_blob=2, levels=5,
                lrx_inner=1, lrx_outer=15, inner=3, outer=13, load_rel=1e-6),
 }
 

@@ -65,7 +65,7 @@ def test_dwest_parity(H, W, levels, inner, outer, solver):
 def test_dwest_full_size_sampled(levels):
     import torch
     from paper_1201_2025_amd import synth
-    c = synth.CONFIGS["C3"]
+    c = synth.CONFIGS["dwest_512x512x224"]
     s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"],
                          n_blob=c["n_blob"])
     t = torch.from_numpy(s.cube).cuda()
@@ -76,7 +76,7 @@ def test_dwest_full_size_sampled(levels):
     ra = oracle.dwt_approx(s.cube, levels)
     rs, rl, rn = oracle.dwest(ra, c["inner"], c["outer"], idx=idx)
     e = score_rel_err(gs.cpu().numpy().ravel()[idx], rs)
-    print("C3 level", levels, err_summary(e), flush=True)
+    print("dwest 512x512x224 level", levels, err_summary(e), flush=True)
     assert e.max() <= TOL
     assert np.array_equal(gn.cpu().numpy().ravel()[idx], rn)
 
@@ -158,7 +158,7 @@ def test_dwest_full_band_paper_shape_sampled():
     # pixels must match the oracle.
     import torch
     from paper_1201_2025_amd import synth
-    c = synth.CONFIGS["P1"]
+    c = synth.CONFIGS["img1_60x100x189"]
     sc = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"],
                           n_blob=c["n_blob"])
     t = torch.from_numpy(sc.cube).cuda()
@@ -169,6 +169,6 @@ def test_dwest_full_band_paper_shape_sampled():
     idx = sample_pixels(c["H"], c["W"], 40, seed=189)
     rs, rl, rn = oracle.dwest(sc.cube.astype(np.float64), c["inner"], c["outer"], idx=idx)
     e = score_rel_err(gs[idx], rs)
-    print("P1 full band", err_summary(e), "npos mismatches", int((gn[idx] != rn).sum()), flush=True)
+    print("img1 60x100x189 full band", err_summary(e), "npos mismatches", int((gn[idx] != rn).sum()), flush=True)
     assert np.array_equal(gn[idx], rn)
     assert e.max() <= TOL

@@ -67,7 +67,7 @@ def test_dwt_full_size_sampled(levels):
     import torch
     print("dwt full size", levels, flush=True)
     from paper_1201_2025_amd import synth
-    c = synth.CONFIGS["C2"]
+    c = synth.CONFIGS["cube_512x512x224"]
     s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"],
                          n_blob=c["n_blob"])
     got = _gpu_dwt(s.cube, levels).reshape(-1, hs.hsad_dwt_out_len(224, levels))

@@ -157,7 +157,7 @@ def test_window_stats_counts_at_border():
 
 def test_dwt_then_lrx_on_generated_scene():
     # sanity on the generator: with the DWT reduction the implanted targets stand out
-    cfg = synth.CONFIGS["C1"]
+    cfg = synth.CONFIGS["small_64x64x224"]
     s = synth.make_scene(cfg["seed"], cfg["H"], cfg["W"], cfg["L"], K=cfg["K"],
                          n_single=cfg["n_single"], n_blob=cfg["n_blob"])
     a = oracle.dwt_approx(s.cube, cfg["levels"])
