@@ -58,22 +58,18 @@ def forward(X, params, Dp: int):
     return h2 @ w3 + b3
 
 
-def loss_and_grad(X, tgt, params, Dp: int, masks=None):
-    """(loss, gradient vector) of the mean squared error over the rows of X.
-
-    masks: optional (m1, m2) boolean arrays (rows x 128) holding the ReLU decisions
-    a1 > 0 and a2 > 0.  The derivative of ReLU jumps at zero, so when a result is to be
-    compared with arithmetic that decides these signs in another precision, the caller
-    passes that precision's decisions here; every value is still computed in FP64."""
+def loss_and_grad(X, tgt, params, Dp: int):
+    """(loss, gradient vector) of the mean squared error over the rows of X.  The ReLU
+    decisions a > 0 are taken on the FP64 pre-activations."""
     W1, b1, W2, b2, w3, b3 = unpack(params, Dp)
     X = np.asarray(X, dtype=np.float64)
     t = np.asarray(tgt, dtype=np.float64)
     B = X.shape[0]
     a1 = X @ W1 + b1
-    m1 = a1 > 0 if masks is None else np.asarray(masks[0], dtype=bool)
+    m1 = a1 > 0
     h1 = np.where(m1, a1, 0.0)
     a2 = h1 @ W2 + b2
-    m2 = a2 > 0 if masks is None else np.asarray(masks[1], dtype=bool)
+    m2 = a2 > 0
     h2 = np.where(m2, a2, 0.0)
     y = h2 @ w3 + b3
     ok = ~np.isnan(t)

@@ -19,7 +19,15 @@ Recipe (numpy PCG64, fully determined by the seed):
   distance > 2 between objects.  Each object draws one fraction f ~ U(0.3, 0.7) and
   every pixel of the object becomes f t + (1 - f) b  (eq. 10).
 * Noise: i.i.d. N(0, noise^2) on every band, noise = 0.01 by default.
-* Truth mask: 1 on anomaly pixels.
+* Adjacency (eq. 11, optional, off by default): with adjacency_w = w > 0, every
+  background pixel z_i within Chebyshev distance 1 of an object (the paper applies the
+  effect "at a spatial distance of one") becomes
+  exp(-rho_i^2 / w^2) f t + (1 - exp(-rho_i^2 / w^2) f) b_i, where rho_i is the Euclidean
+  distance from z_i to the object's nearest pixel (1 for edge neighbours, sqrt(2) for
+  corner neighbours) and f is the object's fraction.  Objects are more than 2 pixels
+  apart, so no background pixel touches two objects.  It draws no random numbers, so a
+  scene with the effect has the same spectra, objects, fractions and noise as without.
+* Truth mask: 1 on anomaly pixels (the adjacency ring stays background).
 """
 from __future__ import annotations
 
@@ -28,7 +36,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Scene", "make_spectra", "make_scene", "make_scene_torch", "CONFIGS",
-           "batch_scene_specs", "random_cube"]
+           "batch_scene_specs", "random_cube", "adjacency_ring"]
 
 
 @dataclass
@@ -73,9 +81,23 @@ def _place_objects(rng, H, W, n_single, n_blob, max_tries=200000):
     return objs
 
 
+def adjacency_ring(H: int, W: int, y: int, x: int, sz: int):
+    """Background pixels at Chebyshev distance 1 from the sz x sz object at (y, x), with
+    rho, the Euclidean distance to the object's nearest pixel: a list of (yy, xx, rho)."""
+    out = []
+    for yy in range(max(0, y - 1), min(H, y + sz + 1)):
+        for xx in range(max(0, x - 1), min(W, x + sz + 1)):
+            if y <= yy < y + sz and x <= xx < x + sz:
+                continue
+            dy = (y - yy) if yy < y else (yy - (y + sz - 1) if yy >= y + sz else 0)
+            dx = (x - xx) if xx < x else (xx - (x + sz - 1) if xx >= x + sz else 0)
+            out.append((yy, xx, float(np.hypot(dy, dx))))
+    return out
+
+
 def make_scene(seed: int, H: int, W: int, L: int, K: int = 8, n_single: int = 12,
                n_blob: int = 0, noise: float = 0.01, f_range=(0.3, 0.7),
-               chunk_rows: int = 64) -> Scene:
+               chunk_rows: int = 64, adjacency_w: float = 0.0) -> Scene:
     rng = np.random.Generator(np.random.PCG64(seed))
     spectra = make_spectra(rng, K + 1, L)
     bg_spec, target = spectra[:K], spectra[K]
@@ -106,17 +128,23 @@ def make_scene(seed: int, H: int, W: int, L: int, K: int = 8, n_single: int = 12
         blk = cube[y:y + sz, x:x + sz].astype(np.float64)
         cube[y:y + sz, x:x + sz] = (f * target + (1.0 - f) * blk).astype(np.float32)
         truth[y:y + sz, x:x + sz] = 1
+        if adjacency_w > 0:
+            for yy, xx, rho in adjacency_ring(H, W, y, x, sz):
+                e = np.exp(-rho * rho / (adjacency_w * adjacency_w)) * f
+                cube[yy, xx] = (e * target + (1.0 - e) * cube[yy, xx].astype(np.float64)).astype(np.float32)
     return Scene(cube=cube, truth=truth, spectra=spectra, fractions=fr, objects=objs)
 
 
 def make_scene_torch(seed: int, H: int, W: int, L: int, K: int = 8, n_single: int = 12,
                      n_blob: int = 0, noise: float = 0.01, f_range=(0.3, 0.7),
-                     device="cuda", chunk_rows: int = 256):
+                     device="cuda", chunk_rows: int = 256, adjacency_w: float = 0.0):
     """The same recipe as make_scene with the per-pixel arrays built by torch on `device`,
     for workloads of many gigabytes.  Spectra, endmember centres and widths, object
     positions and fractions come from the same numpy stream as make_scene, so for a given
     seed they are identical.  Only the noise differs: it comes from torch's generator
-    seeded with `seed`.  Returns (cube tensor H x W x L float32, truth uint8 numpy, spectra)."""
+    seeded with `seed`.  The implants (eq. 10) and the adjacency ring (eq. 11) are applied
+    to all objects at once by gathers and scatters on `device`.
+    Returns (cube tensor H x W x L float32, truth uint8 numpy, spectra)."""
     import torch
     rng = np.random.Generator(np.random.PCG64(seed))
     spectra = make_spectra(rng, K + 1, L)
@@ -146,10 +174,27 @@ def make_scene_torch(seed: int, H: int, W: int, L: int, K: int = 8, n_single: in
             bg += torch.randn(bg.shape, generator=gen, dtype=torch.float64, device=device) * noise
         cube[r0:r1] = bg.to(torch.float32)
     truth = np.zeros((H, W), dtype=np.uint8)
+    # eq. (10) on every object pixel, eq. (11) on every ring pixel, as two batched updates
+    # (objects are more than 2 pixels apart, so no pixel is written twice)
+    pix, fpix, rpix, frng, erng = [], [], [], [], []
     for (y, x, sz), f in zip(objs, fr):
-        blk = cube[y:y + sz, x:x + sz].to(torch.float64)
-        cube[y:y + sz, x:x + sz] = (f * target + (1.0 - f) * blk).to(torch.float32)
+        for yy in range(y, y + sz):
+            for xx in range(x, x + sz):
+                pix.append(yy * W + xx)
+                fpix.append(f)
         truth[y:y + sz, x:x + sz] = 1
+        if adjacency_w > 0:
+            for yy, xx, rho in adjacency_ring(H, W, y, x, sz):
+                rpix.append(yy * W + xx)
+                erng.append(np.exp(-rho * rho / (adjacency_w * adjacency_w)) * f)
+    flat = cube.view(H * W, L)
+    for ids, coef in ((pix, fpix), (rpix, erng)):
+        if not ids:
+            continue
+        it = torch.tensor(ids, dtype=torch.int64, device=device)
+        c = torch.tensor(coef, dtype=torch.float64, device=device)[:, None]
+        b = flat.index_select(0, it).to(torch.float64)
+        flat.index_copy_(0, it, (c * target[None, :] + (1.0 - c) * b).to(torch.float32))
     return cube, truth, spectra
 
 

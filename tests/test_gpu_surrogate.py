@@ -3,14 +3,15 @@
 Bounds:
   features (FP64 sums, FP32 output)   rtol 1e-5, atol 1e-6
   packing and the BF16 weight copy    bitwise (same FP32 operations, round to nearest even)
-  network forward / gradient          normwise relative 2e-2 / 1e-2 per parameter block:
-                                      the kernels round the hidden activations and the
-                                      back-propagated errors to BF16 (unit roundoff 2^-9)
-                                      before each product and accumulate in FP32; the
-                                      oracle is FP64 on the same BF16 weights and inputs.
-                                      The ReLU derivative jumps at zero, so for the
-                                      gradient both sides take the sign decisions in the
-                                      kernels' precision (BF16 operands, FP32 sums)
+  network forward / gradient          elementwise: the kernels' rounding points (BF16 h1,
+                                      h2 and back-propagated errors, FP32 sums) carried
+                                      through the layers as absolute error bounds from the
+                                      oracle's FP64 values (see _bounds); the oracle takes
+                                      every ReLU decision in FP64, and a unit whose FP64
+                                      pre-activation lies inside its error band also
+                                      allows the derivative's jump.  Dyadic inputs make
+                                      the pre-activations exact (same decisions by
+                                      construction) and are checked normwise to 2^-6 too
   Adam step on a given gradient       each stage (moments, update) against FP64 applied to
                                       the GPU's inputs of that stage, within 2^-21 times
                                       the operand magnitudes (a few FP32 units)
@@ -164,6 +165,84 @@ def test_sync_layout(Dp):
     assert np.array_equal(w[n1 + 16384:].reshape(128, 128), _bf16_bits(W2.astype(np.float32)))
 
 
+# ---------------------------------------------------------------------------------------
+# Error bounds of the network kernels, propagated from their rounding points.
+#
+# The kernels take BF16 inputs and BF16 weights (exact operands of the FP64 oracle, which
+# is given the same rounded weights), accumulate every product in FP32, and round h1, h2,
+# dL/da2 and dL/da1 to BF16.  Each rounding to BF16 is within U_BF of its value, each FP32
+# sum of n terms within (n + 2) E32 of the sum of the absolute terms.  The bounds below
+# carry these absolute errors through the layers in FP64 from the oracle's own values.
+# ReLU is 1-Lipschitz, so the forward bound holds whatever either side decides at zero.
+# The ReLU derivative jumps at zero: where the oracle's FP64 pre-activation lies inside
+# its error band, the kernel may decide the other way, and the bound of that unit's
+# back-propagated error then also covers the full jump.  The oracle takes every decision
+# in FP64 by itself.
+# ---------------------------------------------------------------------------------------
+U_BF = 2.0 ** -8
+E32 = 2.0 ** -24
+
+
+def _bounds(X, tgt, p, Dp, exact_preact=False):
+    """Oracle values and elementwise error bounds of y and of every gradient block.
+    exact_preact: the inputs are dyadic so that a1 and a2 are exact in the kernels' FP32
+    sums (no error, no undecided unit)."""
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(p, Dp)
+    X = np.asarray(X, dtype=np.float64)
+    aW1, aW2, aw3 = np.abs(W1), np.abs(W2), np.abs(w3)
+    n = X.shape[0]
+    a1 = X @ W1 + b1
+    h1 = np.maximum(a1, 0.0)
+    a2 = h1 @ W2 + b2
+    h2 = np.maximum(a2, 0.0)
+    y = h2 @ w3 + b3
+    if exact_preact:
+        E_a1 = np.zeros_like(a1)
+        E_h1 = np.zeros_like(h1)
+        E_a2 = np.zeros_like(a2)
+    else:
+        E_a1 = (Dp + 2) * E32 * (np.abs(X) @ aW1 + np.abs(b1))
+        E_h1 = E_a1 + U_BF * (h1 + E_a1)
+        E_a2 = E_h1 @ aW2 + (128 + 2) * E32 * ((h1 + E_h1) @ aW2 + np.abs(b2))
+    E_h2 = E_a2 + U_BF * (h2 + E_a2)
+    E_y = E_h2 @ aw3 + (128 + 2) * E32 * ((h2 + E_h2) @ aw3 + abs(b3))
+    out = {"y": y, "E_y": E_y}
+    if tgt is None:
+        return out
+    t = np.asarray(tgt, dtype=np.float64)
+    ok = ~np.isnan(t)
+    r = np.where(ok, y - np.where(ok, t, 0.0), 0.0)
+    dy = 2.0 * r / n
+    E_dy = np.where(ok, 2.0 * (E_y + 2 * E32 * np.abs(r)) / n, 0.0)
+    m1, m2 = a1 > 0, a2 > 0
+    und1 = np.zeros_like(m1) if exact_preact else np.abs(a1) <= E_a1
+    und2 = np.zeros_like(m2) if exact_preact else np.abs(a2) <= E_a2
+    d2 = np.outer(dy, w3) * m2
+    jump2 = np.outer(np.abs(dy) + E_dy, aw3)
+    E_d2 = np.where(m2 | und2, np.outer(E_dy, aw3) + U_BF * jump2, 0.0) + np.where(und2, jump2, 0.0)
+    c1 = d2 @ W2.T
+    E_c1 = E_d2 @ aW2.T + (128 + 2) * E32 * ((np.abs(d2) + E_d2) @ aW2.T)
+    d1 = c1 * m1
+    jump1 = np.abs(c1) + E_c1
+    E_d1 = np.where(m1 | und1, E_c1 + U_BF * jump1, 0.0) + np.where(und1, jump1, 0.0)
+    gB = (n + 2) * E32
+    aX = np.abs(X)
+    ah1, ad1, ad2 = h1 + E_h1, np.abs(d1) + E_d1, np.abs(d2) + E_d2
+    E_h2b = E_h2 + U_BF * (h2 + E_h2)            # h2 is rounded to BF16 for dw3
+    out.update({
+        "loss": float(np.sum(r * r) / n),
+        "E_loss": float(np.sum(2 * np.abs(r) * (E_y + 2 * E32 * np.abs(r))) / n + gB * np.sum(r * r) / n),
+        "W1": (X.T @ d1, aX.T @ E_d1 + gB * (aX.T @ ad1)),
+        "b1": (d1.sum(0), E_d1.sum(0) + gB * ad1.sum(0)),
+        "W2": (h1.T @ d2, h1.T @ E_d2 + E_h1.T @ ad2 + gB * (ah1.T @ ad2)),
+        "b2": (d2.sum(0), E_d2.sum(0) + gB * ad2.sum(0)),
+        "w3": (h2.T @ dy, E_h2b.T @ np.abs(dy) + (h2 + E_h2b).T @ E_dy + gB * ((h2 + E_h2b).T @ np.abs(dy))),
+        "b3": (np.array([dy.sum()]), np.array([E_dy.sum() + gB * np.abs(dy).sum()])),
+        "undecided": (int(und1.sum()), int(und2.sum())),
+    })
+    return out
+
+
 @pytest.mark.parametrize("Dp,n", [(32, 1), (64, 15), (64, 17), (192, 1000), (256, 4099), (64, 70001)])
 def test_infer_parity(Dp, n):
     print("infer", Dp, n, flush=True)
@@ -176,22 +255,14 @@ def test_infer_parity(Dp, n):
     y = hs.hsad_mlp_infer(X, P, wbf)
     torch.cuda.synchronize()
     got = y.cpu().numpy().astype(np.float64)
-    ref = mlp.forward(Xf.astype(np.float64), _as_kernel_sees(p, Dp), Dp)
-    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print("infer normwise", err, flush=True)
-    assert err <= 2e-2
+    b = _bounds(Xf, None, _as_kernel_sees(p, Dp), Dp)
+    ref, E = b["y"], b["E_y"]
+    err = np.abs(got - ref)
+    print("infer max err %.3g, max err/bound %.3g, normwise %.3g" % (
+        err.max(), (err / E).max(), np.linalg.norm(got - ref) / np.linalg.norm(ref)), flush=True)
     assert np.all(np.isfinite(got))
-
-
-def _kernel_masks(Xf, p, Dp):
-    """ReLU decisions taken in the kernels' precision: BF16 operands, FP32 sums, h1 rounded
-    to BF16 before the second product."""
-    W1, b1, W2, b2, _, _ = mlp.unpack(p, Dp)
-    X32 = np.asarray(Xf, dtype=np.float32)
-    a1 = X32 @ _bf16_round(W1.astype(np.float32)) + b1.astype(np.float32)
-    h1 = _bf16_round(np.maximum(a1, 0))
-    a2 = h1 @ _bf16_round(W2.astype(np.float32)) + b2.astype(np.float32)
-    return a1 > 0, a2 > 0
+    assert np.all(err <= 1.05 * E + 1e-7 * np.abs(ref).max())
+    assert np.linalg.norm(got - ref) <= 2e-2 * np.linalg.norm(ref)
 
 
 def _blocks(g, Dp):
@@ -199,8 +270,25 @@ def _blocks(g, Dp):
     return {"W1": W1, "b1": b1, "W2": W2, "b2": b2, "w3": w3, "b3": np.array([b3])}
 
 
+def _check_gradient(g, b, Dp, normwise):
+    assert abs(g[-1] - b["loss"]) <= 1.05 * b["E_loss"] + 1e-7 * b["loss"]
+    gb = _blocks(g[:-1], Dp)
+    for k, got in gb.items():
+        ref, E = b[k]
+        err = np.abs(got - ref)
+        scale = np.abs(ref).max()
+        print("grad block %s: max err %.3g, max err/bound %.3g, normwise %.3g" % (
+            k, err.max(), (err / np.maximum(E, 1e-300)).max(),
+            np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)), flush=True)
+        assert np.all(err <= 1.05 * E + 1e-7 * scale), k
+        if normwise is not None:
+            assert np.linalg.norm(got - ref) <= normwise * max(np.linalg.norm(ref), 1e-30), k
+    assert np.all(g[-4:-1] == 0)
+
+
 @pytest.mark.parametrize("Dp,batch,nrows", [(64, 64, 500), (64, 1000, 3000), (192, 777, 2000), (32, 5, 9)])
 def test_gradient_parity(Dp, batch, nrows):
+    """Gaussian inputs: the oracle decides every ReLU in FP64; elementwise bounds."""
     print("gradient", Dp, batch, nrows, flush=True)
     import torch
     r = np.random.default_rng(7 * Dp + batch)
@@ -213,15 +301,54 @@ def test_gradient_parity(Dp, batch, nrows):
     g = hs.hsad_mlp_gradient(_t(_bf16_bits(Xf)), _t(tgt), _t(rows), P, wbf)
     torch.cuda.synchronize()
     g = g.cpu().numpy().astype(np.float64)
-    loss, gr = mlp.loss_and_grad(Xf[rows].astype(np.float64), tgt[rows].astype(np.float64),
-                                 _as_kernel_sees(p, Dp), Dp, masks=_kernel_masks(Xf[rows], p, Dp))
-    assert abs(g[-1] - loss) <= 1e-2 * loss
-    gb, rb = _blocks(g[:-1], Dp), _blocks(gr, Dp)
-    for k in gb:
-        e = np.linalg.norm(gb[k] - rb[k]) / max(np.linalg.norm(rb[k]), 1e-30)
-        print("grad block", k, e, flush=True)
-        assert e <= 1e-2, k
-    assert np.all(g[-4:-1] == 0)
+    b = _bounds(Xf[rows], tgt[rows], _as_kernel_sees(p, Dp), Dp)
+    print("undecided units (layer 1, layer 2):", b["undecided"], flush=True)
+    _check_gradient(g, b, Dp, None)
+
+
+def _dyadic_net(seed, Dp, D):
+    """Weights in {-1, 0, 1}/4 and biases in multiples of 1/16: with inputs in {-1, 0, 1}
+    every pre-activation of both hidden layers is a multiple of 1/16 below 2^11, exact in
+    the kernels' FP32 sums, and h1 (a multiple of 1/4 below 2^6 with at most 8 significant
+    bits) is exact in BF16."""
+    r = np.random.default_rng(seed)
+    W1 = np.zeros((Dp, 128))
+    W1[:D] = r.integers(-1, 2, (D, 128)) / 4.0
+    b1 = r.integers(-4, 5, 128) / 4.0
+    W2 = r.integers(-1, 2, (128, 128)) / 4.0
+    b2 = r.integers(-16, 17, 128) / 16.0
+    w3 = r.standard_normal(128) * np.sqrt(1.0 / 128)
+    return mlp.pack(W1, b1, W2, b2, w3, 0.05).astype(np.float32)
+
+
+@pytest.mark.parametrize("Dp,batch,nrows", [(64, 64, 300), (64, 1000, 2000), (256, 640, 1000)])
+def test_gradient_parity_exact_decisions(Dp, batch, nrows):
+    """Dyadic inputs and weights make a1 and a2 exact on both sides, so both take the same
+    ReLU decisions by construction (the oracle in FP64 on its own values); what is left is
+    the BF16 rounding of h2 and of the back-propagated errors: elementwise bounds, and
+    normwise within 2^-6 per block."""
+    print("gradient exact decisions", Dp, batch, nrows, flush=True)
+    import torch
+    r = np.random.default_rng(11 * Dp + batch)
+    D = Dp - 5
+    p = _dyadic_net(Dp + batch, Dp, D)
+    Xf = np.zeros((nrows, Dp), dtype=np.float32)
+    Xf[:, :D] = r.integers(-1, 2, (nrows, D))
+    tgt = (r.standard_normal(nrows) * 3.0).astype(np.float32)
+    rows = r.choice(nrows, batch, replace=False).astype(np.int32)
+    q = _as_kernel_sees(p, Dp)
+    assert np.array_equal(q, p.astype(np.float64))          # weights already BF16 values
+    W1, b1, W2, b2, _, _ = mlp.unpack(q, Dp)
+    a1 = Xf.astype(np.float64) @ W1 + b1
+    a2 = np.maximum(a1, 0) @ W2 + b2
+    assert np.abs(a1).max() < 64 and np.abs(a2).max() < 2048
+    assert 0.2 < (a1 > 0).mean() < 0.8 and 0.2 < (a2 > 0).mean() < 0.8
+    P, wbf = _model(p, Dp)
+    g = hs.hsad_mlp_gradient(_t(_bf16_bits(Xf)), _t(tgt), _t(rows), P, wbf)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    b = _bounds(Xf[rows], tgt[rows], q, Dp, exact_preact=True)
+    _check_gradient(g, b, Dp, 2.0 ** -6)
 
 
 def test_train_step_is_gradient_plus_adam():

@@ -28,6 +28,7 @@ def _brute_dwest(x, inner, outer):
     ro, ri = outer // 2, inner // 2
     yy, xx = np.mgrid[0:H, 0:W]
     score = np.zeros(H * W)
+    literal = np.zeros(H * W)
     npos = np.zeros(H * W, dtype=int)
     for p in range(H * W):
         py, px = divmod(p, W)
@@ -38,18 +39,36 @@ def _brute_dwest(x, inner, outer):
         md = I.mean(0) - A.mean(0)
         e, V = np.linalg.eigh(Cd)
         keep = e > 1e-12 * np.abs(e).max()
-        score[p] = np.linalg.norm(V[:, keep].T @ md)
+        proj = V[:, keep].T @ md
+        score[p] = np.linalg.norm(proj)
+        # eq. (4) summed over the positive eigenvectors, each signed so that its
+        # projection is non-negative: the sum of the absolute projections
+        literal[p] = np.abs(proj).sum()
         npos[p] = keep.sum()
-    return score, npos
+    return score, literal, npos
 
 
 @pytest.mark.parametrize("H,W,L,inner,outer", [(7, 6, 3, 3, 5), (6, 8, 5, 3, 7), (5, 5, 2, 1, 3)])
 def test_dwest_bruteforce(H, W, L, inner, outer):
     x = synth.random_cube(H + W + L, H, W, L).astype(np.float64)
     s, lit, npos = oracle.dwest(x, inner, outer)
-    bs, bn = _brute_dwest(x, inner, outer)
+    bs, bl, bn = _brute_dwest(x, inner, outer)
     assert np.allclose(s, bs, rtol=1e-9, atol=1e-12)
+    assert np.allclose(lit, bl, rtol=1e-9, atol=1e-12)
     assert np.array_equal(npos, bn)
+
+
+def test_dwest_literal_bruteforce_larger_bands():
+    """The literal score against LAPACK's eigenvectors on a scene cube with L' = 9 bands
+    and a 3 x 3 / 9 x 9 window, where several eigenvalues are positive per pixel."""
+    s = synth.make_scene(77, 12, 11, 9, K=3, n_single=2)
+    x = s.cube.astype(np.float64)
+    sc, lit, npos = oracle.dwest(x, 3, 9)
+    bs, bl, bn = _brute_dwest(x, 3, 9)
+    assert np.array_equal(npos, bn)
+    assert (npos >= 2).mean() > 0.5
+    assert np.allclose(sc, bs, rtol=1e-8, atol=1e-12 * np.abs(bs).max())
+    assert np.allclose(lit, bl, rtol=1e-8, atol=1e-12 * np.abs(bl).max())
 
 
 def test_dwest_invariances_and_bounds():
