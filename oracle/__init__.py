@@ -22,7 +22,8 @@ from .evaluate import auc, auc_counts, mask, threshold
 
 __all__ = [
     "DB4", "daubechies_lowpass", "highpass", "build", "set_threads", "dwt_out_len",
-    "levels_for", "dwt_level", "dwt_approx", "dwt_full", "idwt_full", "window_stats",
+    "levels_for", "dwt_level", "dwt_approx", "dwt_full", "idwt_full", "dwt_full_len",
+    "dwt_full_cube", "idwt_full_cube", "global_rx", "window_stats",
     "loading", "cholesky", "lrx_dwrx", "jacobi_eig", "dwest", "threshold", "mask", "auc",
     "auc_counts", "evaluate",
 ]
@@ -78,22 +79,62 @@ def dwt_approx(cube: np.ndarray, levels: int, h=None) -> np.ndarray:
     return out
 
 
+def dwt_full_len(L: int, levels: int) -> int:
+    """Length of [a_J d_J ... d_1] (Sec. 3): n_J + sum_j n_j with n_j = ceil(n_{j-1}/2);
+    -1 when a level input would be < 2."""
+    return int(lib().orc_dwt_full_len(int(L), int(levels)))
+
+
 def dwt_full(x: np.ndarray, levels: int, h=None) -> np.ndarray:
-    """[a_J d_J ... d_1] of a 1-D signal (even length at every level)."""
+    """[a_J d_J ... d_1] of a 1-D signal (Sec. 3, Fig. 1); odd level inputs are extended by
+    repeating their last sample."""
     h, nt = _filt(h)
     x = np.ascontiguousarray(x, dtype=np.float64)
-    out = np.empty_like(x)
-    if lib().orc_dwt_full(ptr(x, _D), len(x), int(levels), ptr(h, _D), nt, ptr(out, _D)):
-        raise ValueError("full DWT needs even lengths at every level")
+    n = dwt_full_len(len(x), levels)
+    if n < 0:
+        raise ValueError("levels too deep for this length")
+    out = np.empty(n)
+    lib().orc_dwt_full(ptr(x, _D), len(x), int(levels), ptr(h, _D), nt, ptr(out, _D))
     return out
 
 
-def idwt_full(c: np.ndarray, levels: int, h=None) -> np.ndarray:
+def idwt_full(c: np.ndarray, levels: int, h=None, n: int | None = None) -> np.ndarray:
+    """Inverse of dwt_full for a signal of length n (default: len(c), an even chain)."""
     h, nt = _filt(h)
     c = np.ascontiguousarray(c, dtype=np.float64)
-    out = np.empty_like(c)
-    if lib().orc_idwt_full(ptr(c, _D), len(c), int(levels), ptr(h, _D), nt, ptr(out, _D)):
-        raise ValueError("full DWT needs even lengths at every level")
+    n = len(c) if n is None else int(n)
+    if dwt_full_len(n, levels) != len(c):
+        raise ValueError("coefficient count does not match n and levels")
+    out = np.empty(n)
+    lib().orc_idwt_full(ptr(c, _D), n, int(levels), ptr(h, _D), nt, ptr(out, _D))
+    return out
+
+
+def dwt_full_cube(cube: np.ndarray, levels: int, h=None) -> np.ndarray:
+    """Full decomposition of every pixel spectrum of a (..., L) float32 cube; float64
+    result of shape (..., dwt_full_len(L, levels))."""
+    h, nt = _filt(h)
+    c = np.ascontiguousarray(cube, dtype=np.float32)
+    L = c.shape[-1]
+    n = dwt_full_len(L, levels)
+    if n < 0:
+        raise ValueError("levels too deep for L=%d" % L)
+    out = np.empty(c.shape[:-1] + (n,))
+    lib().orc_dwt_full_cube(ptr(c, ctypes.c_float), c.size // L, L, int(levels), ptr(h, _D), nt,
+                            ptr(out, _D))
+    return out
+
+
+def idwt_full_cube(coef: np.ndarray, L: int, levels: int, h=None) -> np.ndarray:
+    """Inverse of dwt_full_cube from float32 coefficients; float64 (..., L) result."""
+    h, nt = _filt(h)
+    c = np.ascontiguousarray(coef, dtype=np.float32)
+    n = dwt_full_len(L, levels)
+    if n < 0 or c.shape[-1] != n:
+        raise ValueError("coefficient count does not match L and levels")
+    out = np.empty(c.shape[:-1] + (int(L),))
+    lib().orc_idwt_full_cube(ptr(c, ctypes.c_float), c.size // n, int(L), int(levels), ptr(h, _D), nt,
+                             ptr(out, _D))
     return out
 
 
@@ -157,6 +198,20 @@ def lrx_dwrx(x: np.ndarray, inner: int, outer: int, load_rel: float = 1e-6, idx=
     lib().orc_lrx_dwrx(ptr(x, _D), H, W, Lp, inner, outer, float(load_rel),
                        ptr(idx, ctypes.c_int64), idx.size, ptr(lrx, _D), ptr(dwrx, _D))
     return lrx, dwrx
+
+
+def global_rx(x: np.ndarray, load_rel: float = 1e-6, idx=None, stats: bool = False):
+    """Global RX (Sec. 2.1, eq. 1 with all pixels as background) at pixels idx (flat).
+    Returns the scores, or (scores, mu, C) with stats=True (C before loading)."""
+    x = _cube64(x)
+    H, W, Lp = x.shape
+    idx = _idx(H, W, idx)
+    s = np.empty(idx.size)
+    mu = np.empty(Lp) if stats else None
+    C = np.empty((Lp, Lp)) if stats else None
+    lib().orc_global_rx(ptr(x, _D), H * W, Lp, float(load_rel), ptr(idx, ctypes.c_int64), idx.size,
+                        ptr(s, _D), ptr(mu, _D), ptr(C, _D))
+    return (s, mu, C) if stats else s
 
 
 def jacobi_eig(A: np.ndarray, tol_rel: float = 1e-14, max_sweeps: int = 100):

@@ -50,6 +50,17 @@ def lib():
             L.orc_dwt_approx.restype = ctypes.c_int64
             L.orc_dwt_approx.argtypes = [_f, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _d,
                                          ctypes.c_int, _d]
+            L.orc_dwt_full_len.restype = ctypes.c_int64
+            L.orc_dwt_full_len.argtypes = [ctypes.c_int64, ctypes.c_int]
+            L.orc_dwt_full_cube.restype = ctypes.c_int64
+            L.orc_dwt_full_cube.argtypes = [_f, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _d,
+                                            ctypes.c_int, _d]
+            L.orc_idwt_full_cube.restype = ctypes.c_int
+            L.orc_idwt_full_cube.argtypes = [_f, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _d,
+                                             ctypes.c_int, _d]
+            L.orc_global_rx.restype = None
+            L.orc_global_rx.argtypes = [_d, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _i64,
+                                        ctypes.c_int64, _d, _d, _d]
             L.orc_dwt_full.restype = ctypes.c_int
             L.orc_dwt_full.argtypes = [_d, ctypes.c_int64, ctypes.c_int, _d, ctypes.c_int, _d]
             L.orc_idwt_full.restype = ctypes.c_int

@@ -122,24 +122,38 @@ int64_t orc_dwt_approx(const float *cube, int64_t npix, int64_t L, int levels,
     return Lp;
 }
 
-/* Full decomposition, concatenated as [a_J d_J d_{J-1} ... d_1] (Sec. 3, last paragraph).
- * Only for chains whose every level input has even length.  Returns 0 or -1. */
+/* Length of the full decomposition [a_J d_J d_{J-1} ... d_1] (Sec. 3, last paragraph):
+ * level j maps its input of length n_{j-1} to a_j and d_j of n_j = ceil(n_{j-1}/2) samples
+ * each (an odd input is first extended by repeating its last sample, as for the
+ * approximation), so the total is n_J + n_J + n_{J-1} + ... + n_1.  -1 if a level input
+ * would be shorter than 2. */
+int64_t orc_dwt_full_len(int64_t L, int levels)
+{
+    if (L < 1 || levels < 0) return -1;
+    int64_t n = L, tot = 0;
+    for (int j = 0; j < levels; ++j) {
+        if (n < 2) return -1;
+        n = (n + 1) / 2;
+        tot += n;
+    }
+    return tot + n;
+}
+
+/* Full decomposition of one signal of length n into out (orc_dwt_full_len values):
+ * a_J first, then d_J, d_{J-1}, ..., d_1.  Returns 0 or -1. */
 int orc_dwt_full(const double *x, int64_t n, int levels, const double *h, int ntaps,
                  double *out)
 {
-    int64_t len = n;
-    for (int j = 0; j < levels; ++j) {
-        if (len < 2 || (len & 1)) return -1;
-        len /= 2;
-    }
-    double *cur = (double *)malloc(sizeof(double) * (size_t)n);
-    double *a = (double *)malloc(sizeof(double) * (size_t)n);
+    const int64_t tot = orc_dwt_full_len(n, levels);
+    if (tot < 0) return -1;
+    double *cur = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *a = (double *)malloc(sizeof(double) * (size_t)(n + 1));
     memcpy(cur, x, sizeof(double) * (size_t)n);
-    len = n;
+    int64_t len = n, end = tot;           /* d_j is written just below `end` */
     for (int j = 0; j < levels; ++j) {
-        int64_t m = len / 2;
-        /* details of level j+1 go right after the slot reserved for coarser levels */
-        orc_dwt_level(cur, len, h, ntaps, a, out + m);
+        const int64_t m = (len + 1) / 2;
+        orc_dwt_level(cur, len, h, ntaps, a, out + end - m);
+        end -= m;
         memcpy(cur, a, sizeof(double) * (size_t)m);
         len = m;
     }
@@ -149,8 +163,8 @@ int orc_dwt_full(const double *x, int64_t n, int levels, const double *h, int nt
     return 0;
 }
 
-/* Synthesis: the adjoint of one analysis level (x = A^T a + D^T d).  Equal to the inverse
- * exactly when the analysis matrix is orthogonal, which the tests check. */
+/* Synthesis of one level: the adjoint of the (orthogonal, for an even length n) analysis
+ * matrix, x = A^T a + D^T d, with a and d of n/2 samples each. */
 static void orc_level_adjoint(const double *a, const double *d, int64_t n, const double *h,
                               int ntaps, double *x)
 {
@@ -164,26 +178,70 @@ static void orc_level_adjoint(const double *a, const double *d, int64_t n, const
     }
 }
 
+/* Inverse of orc_dwt_full for a signal of length n: level by level from the coarsest,
+ * synthesis by the adjoint of the orthogonal level on the extended (even) length, then the
+ * repeated sample of an odd level input is dropped.  Returns 0 or -1. */
 int orc_idwt_full(const double *c, int64_t n, int levels, const double *h, int ntaps,
                   double *out)
 {
-    int64_t len = n;
-    for (int j = 0; j < levels; ++j) {
-        if (len < 2 || (len & 1)) return -1;
-        len /= 2;
-    }
-    double *cur = (double *)malloc(sizeof(double) * (size_t)n);
-    double *nxt = (double *)malloc(sizeof(double) * (size_t)n);
-    memcpy(cur, c, sizeof(double) * (size_t)len);
-    for (int j = levels - 1; j >= 0; --j) {
-        int64_t m = len;              /* current approximation length */
-        orc_level_adjoint(cur, c + m, 2 * m, h, ntaps, nxt);
-        len = 2 * m;
-        memcpy(cur, nxt, sizeof(double) * (size_t)len);
+    const int64_t tot = orc_dwt_full_len(n, levels);
+    if (tot < 0) return -1;
+    int64_t lens[64];
+    lens[0] = n;
+    for (int j = 0; j < levels; ++j) lens[j + 1] = (lens[j] + 1) / 2;
+    double *cur = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *nxt = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    int64_t off = lens[levels];           /* d_J starts after a_J */
+    memcpy(cur, c, sizeof(double) * (size_t)lens[levels]);
+    for (int j = levels; j >= 1; --j) {
+        const int64_t m = lens[j];
+        orc_level_adjoint(cur, c + off, 2 * m, h, ntaps, nxt);
+        off += m;
+        memcpy(cur, nxt, sizeof(double) * (size_t)lens[j - 1]);   /* drops an extension */
     }
     memcpy(out, cur, sizeof(double) * (size_t)n);
     free(cur);
     free(nxt);
+    return 0;
+}
+
+/* Full decomposition of every pixel spectrum of a cube (npix x L, float) into out
+ * (npix x orc_dwt_full_len(L, levels) doubles).  Returns the output length or -1. */
+int64_t orc_dwt_full_cube(const float *cube, int64_t npix, int64_t L, int levels, const double *h,
+                          int ntaps, double *out)
+{
+    const int64_t tot = orc_dwt_full_len(L, levels);
+    if (tot < 0) return -1;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)L);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < npix; ++p) {
+            for (int64_t i = 0; i < L; ++i) buf[i] = (double)cube[p * L + i];
+            orc_dwt_full(buf, L, levels, h, ntaps, out + p * tot);
+        }
+        free(buf);
+    }
+    return tot;
+}
+
+/* Inverse of orc_dwt_full_cube: npix rows of orc_dwt_full_len(L, levels) coefficients
+ * (float) back to npix x L doubles.  Returns 0 or -1. */
+int orc_idwt_full_cube(const float *coef, int64_t npix, int64_t L, int levels, const double *h,
+                       int ntaps, double *out)
+{
+    const int64_t tot = orc_dwt_full_len(L, levels);
+    if (tot < 0) return -1;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)tot);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < npix; ++p) {
+            for (int64_t i = 0; i < tot; ++i) buf[i] = (double)coef[p * tot + i];
+            orc_idwt_full(buf, L, levels, h, ntaps, out + p * L);
+        }
+        free(buf);
+    }
     return 0;
 }
 
@@ -344,6 +402,64 @@ void orc_lrx_dwrx(const double *x, int64_t H, int64_t W, int64_t Lp, int inner, 
         }
         free(mu); free(C); free(mi); free(Ci); free(d); free(z);
     }
+}
+
+/* Global RX (Sec. 2.1, eq. 1 with the background defined by all the image pixels):
+ * mu and C = (1/N) sum (x - mu)(x - mu)^T over the N pixels (two passes, exact centring),
+ * loading lambda = load_rel tr(C)/L' (floor 1e-30), and the score of each listed pixel.
+ * The sums run over 64 fixed pixel ranges added in order, so the result does not depend
+ * on the thread count.  mu_out (Lp) and C_out (Lp*Lp, before loading) may be NULL.
+ * A covariance that is not positive definite after loading gives +inf everywhere. */
+void orc_global_rx(const double *x, int64_t npix, int64_t Lp, double load_rel, const int64_t *idx,
+                   int64_t nidx, double *scores, double *mu_out, double *C_out)
+{
+    enum { NR = 64 };
+    const size_t l2 = (size_t)(Lp * Lp);
+    double *mu = calloc((size_t)Lp, sizeof(double)), *C = calloc(l2, sizeof(double));
+    double *pm = calloc((size_t)NR * (size_t)Lp, sizeof(double));
+    double *pc = calloc((size_t)NR * l2, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < NR; ++r) {
+        const int64_t p0 = npix * r / NR, p1 = npix * (r + 1) / NR;
+        for (int64_t p = p0; p < p1; ++p)
+            for (int64_t i = 0; i < Lp; ++i) pm[(size_t)r * Lp + i] += x[p * Lp + i];
+    }
+    for (int r = 0; r < NR; ++r)
+        for (int64_t i = 0; i < Lp; ++i) mu[i] += pm[(size_t)r * Lp + i];
+    for (int64_t i = 0; i < Lp; ++i) mu[i] /= (double)npix;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < NR; ++r) {
+        const int64_t p0 = npix * r / NR, p1 = npix * (r + 1) / NR;
+        double *c = malloc(sizeof(double) * (size_t)Lp);
+        double *acc = pc + (size_t)r * l2;
+        for (int64_t p = p0; p < p1; ++p) {
+            for (int64_t i = 0; i < Lp; ++i) c[i] = x[p * Lp + i] - mu[i];
+            for (int64_t i = 0; i < Lp; ++i)
+                for (int64_t j = 0; j < Lp; ++j) acc[i * Lp + j] += c[i] * c[j];
+        }
+        free(c);
+    }
+    for (int r = 0; r < NR; ++r)
+        for (size_t e = 0; e < l2; ++e) C[e] += pc[(size_t)r * l2 + e];
+    for (size_t e = 0; e < l2; ++e) C[e] /= (double)npix;
+    if (mu_out) memcpy(mu_out, mu, sizeof(double) * (size_t)Lp);
+    if (C_out) memcpy(C_out, C, sizeof(double) * l2);
+    const double lam = orc_loading(C, Lp, load_rel);
+    for (int64_t i = 0; i < Lp; ++i) C[i * Lp + i] += lam;
+    const int ok = orc_cholesky(C, Lp) == 0;
+#pragma omp parallel
+    {
+        double *d = malloc(sizeof(double) * (size_t)Lp), *z = malloc(sizeof(double) * (size_t)Lp);
+#pragma omp for schedule(static)
+        for (int64_t t = 0; t < nidx; ++t) {
+            const double *r = x + idx[t] * Lp;
+            for (int64_t i = 0; i < Lp; ++i) d[i] = r[i] - mu[i];
+            scores[t] = ok ? orc_quad_form(C, Lp, d, z) : INFINITY;
+        }
+        free(d);
+        free(z);
+    }
+    free(mu); free(C); free(pm); free(pc);
 }
 
 /* ------------------------------------------------------------------------------------ */

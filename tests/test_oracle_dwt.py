@@ -173,3 +173,102 @@ def test_out_len_rules():
     assert oracle.dwt_out_len(1, 1) == -1
     assert oracle.dwt_out_len(3, 2) == 1
     assert oracle.dwt_out_len(3, 3) == -1
+
+
+# ---------------------------------------------------------------------------------------
+# Other Daubechies orders (Fig. 2 uses a 16-vanishing-moment filter) and the full
+# transform on odd-length chains
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 6, 8, 10, 12, 16])
+def test_daubechies_family_defining_conditions(N):
+    """The defining equations hold to rounding and the filter has extremal (minimum)
+    phase.  Together they determine the filter."""
+    h = daubechies_lowpass(N)
+    n = 2 * N
+    tol = 1e-14
+    assert len(h) == n
+    assert abs(h.sum() - sqrt(2.0)) < tol
+    for m in range(N):
+        s = float(np.dot(h[: n - 2 * m], h[2 * m:]))
+        assert abs(s - (1.0 if m == 0 else 0.0)) < tol, m
+    g = highpass(h)
+    k = np.arange(n, dtype=np.float64)
+    for p in range(N):
+        assert abs(np.sum(k ** p * g)) < tol * max(1.0, np.abs(k ** p * g).sum()), p
+    if N > 1:
+        # sum h[n] w^n (w = 1/z) has an N-fold zero at w = -1, which rounding splits into a
+        # small cluster, and N - 1 further zeros, all outside the unit circle
+        r = np.roots(h[::-1])
+        far, near = r[np.abs(r) > 1.3], r[np.abs(r) <= 1.3]
+        assert len(far) == N - 1 and len(near) == N
+        assert np.max(np.abs(near + 1.0)) < 0.25
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("n,levels", [(224, 5), (64, 2), (96, 5)])
+def test_family_orthogonality_on_even_chains(N, n, levels):
+    h = daubechies_lowpass(N)
+    rng = np.random.default_rng(N * 100 + n)
+    x = rng.standard_normal(n)
+    c = oracle.dwt_full(x, levels, h)
+    assert len(c) == n
+    assert abs(np.sum(c ** 2) - np.sum(x ** 2)) < 1e-12 * np.sum(x ** 2)
+    assert np.max(np.abs(oracle.idwt_full(c, levels, h) - x)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("n,levels", [(224, 6), (189, 5), (7, 2), (33, 5), (100, 5)])
+def test_full_transform_odd_chains_reconstruct(N, n, levels):
+    """Odd level inputs are extended by their last sample (the approximation's rule applied
+    to both branches), so the transform is injective and the inverse recovers x."""
+    h = daubechies_lowpass(N)
+    rng = np.random.default_rng(N + n + levels)
+    x = rng.standard_normal(n).astype(np.float32).astype(np.float64)
+    c = oracle.dwt_full(x, levels, h)
+    lens, m = [], n
+    for _ in range(levels):
+        m = (m + 1) // 2
+        lens.append(m)
+    assert len(c) == lens[-1] + sum(lens) == oracle.dwt_full_len(n, levels)
+    assert np.array_equal(c[:lens[-1]], oracle.dwt_approx(x[None, :].astype(np.float32), levels, h)[0])
+    xr = oracle.idwt_full(c, levels, h, n=n)
+    assert np.max(np.abs(xr - x)) < 1e-12
+
+
+def test_full_transform_odd_level_equals_extended_even_level():
+    # one level of an odd signal = one level of the signal with its last sample repeated,
+    # whose energy is preserved (orthogonal level)
+    rng = np.random.default_rng(5)
+    for N in (1, 4, 16):
+        h = daubechies_lowpass(N)
+        x = rng.standard_normal(37)
+        xe = np.concatenate([x, x[-1:]])
+        c = oracle.dwt_full(x, 1, h)
+        ce = oracle.dwt_full(xe, 1, h)
+        assert np.array_equal(c, ce)
+        assert abs(np.sum(ce ** 2) - np.sum(xe ** 2)) < 1e-12 * np.sum(xe ** 2)
+
+
+def test_full_transform_layout_and_haar_closed_form():
+    # Haar (h = [1, 1]/sqrt 2, g = [1, -1]/sqrt 2) with eq. (9)'s periodic index pairs
+    # x[2k] with x[2k - 1]: level 1 on [x0..x3] gives a1 = ((x0+x3), (x2+x1))/sqrt 2 and
+    # d1 = ((x0-x3), (x2-x1))/sqrt 2; level 2 gives a2 = (x0+x1+x2+x3)/2 and
+    # d2 = (a1[0] - a1[1])/sqrt 2.  Output order [a2 d2 d1].
+    x = np.array([1.0, 2.0, 4.0, 8.0])
+    c = oracle.dwt_full(x, 2, daubechies_lowpass(1))
+    r2 = sqrt(2.0)
+    want = [7.5, (x[0] + x[3] - x[2] - x[1]) / 2, (x[0] - x[3]) / r2, (x[2] - x[1]) / r2]
+    assert np.allclose(c, want, rtol=0, atol=1e-14)
+
+
+def test_full_cube_forms_match_signal_forms():
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((3, 4, 45)).astype(np.float32)
+    h = daubechies_lowpass(8)
+    c = oracle.dwt_full_cube(x, 3, h)
+    assert c.shape == (3, 4, oracle.dwt_full_len(45, 3))
+    for p in range(12):
+        v = x.reshape(12, 45)[p].astype(np.float64)
+        assert np.array_equal(c.reshape(12, -1)[p], oracle.dwt_full(v, 3, h))
+    xr = oracle.idwt_full_cube(c.astype(np.float32), 45, 3, h)
+    assert xr.shape == x.shape and np.max(np.abs(xr - x)) < 1e-5

@@ -163,3 +163,53 @@ def test_dwt_then_lrx_on_generated_scene():
     a = oracle.dwt_approx(s.cube, cfg["levels"])
     l, _ = oracle.lrx_dwrx(a, cfg["inner"], cfg["outer"], cfg["load_rel"])
     assert oracle.auc(l, s.truth) > 0.95
+
+
+# ---------------------------------------------------------------------------------------
+# Global RX (Sec. 2.1, eq. 1 with every pixel as background)
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("rel", [0.0, 1e-6, 0.05])
+def test_global_rx_is_whole_image_window_lrx(rel):
+    # the global background is the local one with a window covering the image and no
+    # guard window: two independent routes in the oracle
+    H, W, L = 7, 9, 4
+    x = _cube(31, H, W, L)
+    g = oracle.global_rx(x, rel)
+    lrx, _ = oracle.lrx_dwrx(x, 0, 2 * max(H, W) + 1, load_rel=rel)
+    assert np.allclose(g, lrx, rtol=1e-11, atol=1e-13)
+
+
+def test_global_rx_mean_and_loading_closed_forms():
+    H, W, L = 40, 37, 9
+    x = _cube(32, H, W, L, scale=3.0) + 5.0
+    assert abs(oracle.global_rx(x, 0.0).mean() - L) < 1e-10
+    rel = 0.02
+    X = x.reshape(-1, L)
+    C = np.cov(X.T, bias=True)
+    e = np.linalg.eigvalsh(C)
+    lam = rel * np.trace(C) / L
+    assert abs(oracle.global_rx(x, rel).mean() - np.sum(e / (e + lam))) < 1e-10
+
+
+def test_global_rx_stats_and_leave_one_out():
+    H, W, L = 12, 10, 5
+    x = _cube(33, H, W, L)
+    s, mu, C = oracle.global_rx(x, 0.0, stats=True)
+    X = x.reshape(-1, L)
+    assert np.allclose(mu, X.mean(0), rtol=1e-14, atol=1e-15)
+    assert np.allclose(C, np.cov(X.T, bias=True), rtol=1e-13, atol=1e-15)
+    N = H * W
+    loo, _ = oracle.lrx_dwrx(x, 1, 2 * max(H, W) + 1, load_rel=0.0)
+    assert np.allclose(loo, N * s / (N - 1 - s), rtol=1e-10)
+
+
+def test_global_rx_affine_invariance_and_subset():
+    H, W, L = 15, 14, 6
+    x = _cube(34, H, W, L)
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((L, L)) + 2 * np.eye(L)
+    y = x @ A.T + rng.standard_normal(L)
+    g1, g2 = oracle.global_rx(x, 0.0), oracle.global_rx(y, 0.0)
+    assert np.allclose(g1, g2, rtol=1e-8)
+    idx = np.array([0, 17, H * W - 1, 17])
+    assert np.array_equal(oracle.global_rx(x, 1e-6, idx=idx), oracle.global_rx(x, 1e-6)[idx])
