@@ -151,6 +151,26 @@ int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_win
                 double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,
                 size_t ws_bytes, hipStream_t stream);
 
+/* Size of the static device array hsad_detect_noalloc takes its workspace from. */
+#define HSAD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hsad_detect with the same arguments
+ * and results, except that the workspace is a static device array of
+ * HSAD_NOALLOC_SCRATCH_BYTES bytes instead of a caller buffer.  Each GPU the library runs
+ * on holds its own copy of the array from the first load of the library until the process
+ * ends; its address is looked up once per device on the first call there.  The call
+ * allocates and frees nothing (no hipMalloc, hipFree or allocating library routine).
+ * The array keeps what the last call left in it; nothing in it needs clearing.  All calls
+ * on one GPU share the array, so calls that overlap on one GPU (from any stream or
+ * thread) race and must be serialised by the caller.
+ * Errors: as hsad_detect; HSAD_ENOMEM (with the sizes in the message) when the smallest
+ * workspace hsad_detect accepts for these arguments exceeds HSAD_NOALLOC_SCRATCH_BYTES
+ * (nothing is enqueued then). */
+int hsad_detect_noalloc(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                        double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask,
+                        hipStream_t stream);
+
 /* DWEST, eqs. (2)-(4): C_diff = C_inner - C_annulus, m_diff = m_inner - m_annulus.
  * The eigenvalues of C_diff and the projections v_i^T m_diff come from an FP64
  * Householder tridiagonalisation followed by the implicit QL iteration, with every

@@ -87,6 +87,8 @@ SIGNATURES = [
     ("hsad_detect_workspace_bytes", ctypes.c_size_t, [_i64, _i64, _i64, _P]),
     ("hsad_detect", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.c_double, _vp, _vp, _vp, _vp, _vp,
                                    ctypes.c_size_t, _vp]),
+    ("hsad_detect_noalloc", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.c_double, _vp, _vp, _vp, _vp,
+                                           _vp]),
     ("hsad_dwest", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_threshold_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("hsad_threshold", ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -355,6 +357,38 @@ def hsad_detect(x, inner: int, outer: int, load_rel: float = 1e-6, z_alpha: floa
                            _ptr_or_null(mask, "mask", torch.uint8), _dev(ws, "ws"),
                            ws.numel() * ws.element_size(), _stream(stream))
     _check("hsad_detect", rc)
+    return lrx, dwrx, stats, mask
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # HSAD_NOALLOC_SCRATCH_BYTES
+
+
+def hsad_detect_noalloc(x, inner: int, outer: int, load_rel: float = 1e-6, z_alpha: float = 3.0,
+                        precision: int = HSAD_PREC_AUTO, lrx=None, dwrx=True, stats=None, mask=True,
+                        stream=None):
+    """hsad_detect with the library's static device scratch as workspace (no workspace
+    argument).  Output tensors are allocated here unless passed in; the C call itself
+    allocates nothing.  Returns (lrx, dwrx or None, stats, mask or None)."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    p = _params(inner, outer, load_rel, precision)
+    dev = x.device
+    lrx = torch.empty((H, W), dtype=torch.float32, device=dev) if lrx is None else lrx
+    if dwrx is True:
+        dwrx = torch.empty((H, W), dtype=torch.float32, device=dev)
+    elif dwrx is False:
+        dwrx = None
+    if mask is True:
+        mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    elif mask is False:
+        mask = None
+    stats = torch.empty(4, dtype=torch.float64, device=dev) if stats is None else stats
+    rc = lib().hsad_detect_noalloc(px, H, W, Lp, ctypes.byref(p), float(z_alpha),
+                                   _dev(lrx, "lrx", torch.float32), _ptr_or_null(dwrx, "dwrx", torch.float32),
+                                   _dev(stats, "stats", torch.float64), _ptr_or_null(mask, "mask", torch.uint8),
+                                   _stream(stream))
+    _check("hsad_detect_noalloc", rc)
     return lrx, dwrx, stats, mask
 
 

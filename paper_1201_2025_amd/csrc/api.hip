@@ -307,6 +307,24 @@ static size_t detect_head_bytes(int64_t H, int64_t W)
     return (b + 255) & ~(size_t)255;
 }
 
+}  // extern "C"
+
+// Smallest workspace hsad_detect accepts for these arguments (0 when they are invalid; the
+// calling thread's error message is left as it was).
+size_t hsad::detect_min_bytes(int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p, bool with_dwrx)
+{
+    Windows w;
+    std::string keep = t_err;
+    int rc = check_windows("hsad_detect", p, H, W, Lp, with_dwrx, &w);
+    t_err = keep;
+    if (rc) return 0;
+    size_t b = detect_head_bytes(H, W);
+    if (!(exact(p->precision) && box_supported(Lp, w))) b += generic_ws_per_pixel(Lp, GRAM_LRX);
+    return b;
+}
+
+extern "C" {
+
 size_t hsad_detect_workspace_bytes(int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p)
 {
     if (H < 1 || W < 1) return 0;

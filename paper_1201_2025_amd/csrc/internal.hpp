@@ -76,6 +76,8 @@ int generic_lrx_dwrx(const float *x, int64_t H, int64_t W, int64_t Lp, const Win
 int generic_lrx_dwrx_at(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                         double load_rel, GramPrec prec, const int32_t *idx, int64_t nidx, float *lrx,
                         float *dwrx, void *ws, size_t ws_bytes, hipStream_t s);
+// smallest workspace hsad_detect accepts (api.hip); 0 for invalid arguments
+size_t detect_min_bytes(int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p, bool with_dwrx);
 int generic_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                   float *score, float *literal, int32_t *npos, void *ws, size_t ws_bytes,
                   hipStream_t s);

@@ -147,6 +147,25 @@ def test_detect_arguments_and_workspace():
                          None) == hs.HSAD_EINVAL                       # DWRX needs an inner window
 
 
+def test_detect_noalloc_rejects_before_any_launch():
+    # validation and the static-scratch limit are checked on the host before anything is
+    # enqueued, so these calls never touch a device
+    L = hs.lib()
+    p = _p(5, 15)
+    assert hs.NOALLOC_SCRATCH_BYTES == 64 << 20
+    stats = FAKE
+    assert L.hsad_detect_noalloc(FAKE, 8, 8, 4, ctypes.byref(_p(3, 4)), 3.0, FAKE, FAKE, stats, FAKE,
+                                 None) == hs.HSAD_EINVAL
+    assert "outer" in hs.hsad_last_error()
+    assert L.hsad_detect_noalloc(FAKE, 8, 8, 4, ctypes.byref(p), 3.0, None, FAKE, stats, FAKE,
+                                 None) == hs.HSAD_EINVAL
+    # a 65536 x 65536 image needs 2^24 tile partials (402 MB): more than the scratch holds
+    rc = L.hsad_detect_noalloc(FAKE, 65536, 65536, 4, ctypes.byref(p), 3.0, FAKE, FAKE, stats, FAKE, None)
+    assert rc == hs.HSAD_ENOMEM
+    msg = hs.hsad_last_error()
+    assert "static scratch" in msg and str(64 << 20) in msg
+
+
 def test_surrogate_dims_match_oracle():
     from oracle import mlp
     for Lp in (1, 4, 7, 14, 28, 56, 85):
