@@ -100,6 +100,43 @@ int hsad_levels_for(int64_t L, int target);
 int hsad_dwt(const float *cube, int64_t H, int64_t W, int64_t L, int levels, float *approx,
              hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Full transform: approximation and every detail band (Sec. 3, Fig. 1), its inverse, and
+ * the Daubechies family of any order (Fig. 2 shows the db16 scaling function)
+ * -------------------------------------------------------------------------------------*/
+/* Host only.  h (2 * order doubles) receives the minimum-phase Daubechies scaling filter
+ * with `order` vanishing moments (order 1 is Haar, 4 the db4 of hsad_dwt), in the time
+ * order of eq. (9), sum h = sqrt 2.  The library designs it by a spectral factorisation of
+ * Daubechies' polynomial polished on its defining equations (orthonormal even shifts and
+ * `order` vanishing moments of the high-pass) in long double.
+ * Errors: HSAD_EINVAL (order outside 1..16, NULL h). */
+int hsad_wavelet_filter(int order, double *h);
+
+/* Length of [a_J d_J d_{J-1} ... d_1] after `levels` levels of a length-L signal: level j
+ * maps n_{j-1} samples to a_j and d_j of n_j = ceil(n_{j-1}/2) samples each (the odd-length
+ * extension of hsad_dwt applied to both branches), so n = n_J + sum_j n_j; L for levels 0.
+ * Errors: HSAD_EINVAL (L < 1, levels < 0, a level input shorter than 2). */
+int hsad_dwt_full_len(int64_t L, int levels, int64_t *n);
+
+/* Full periodised DWT of every pixel spectrum with the order-`order` Daubechies pair:
+ * level by level a_j[k] = sum_t h_t x[(2k - t) mod n_e], d_j[k] = sum_t g_t x[(2k - t) mod n_e]
+ * with g_t = (-1)^t h_{2 order - 1 - t} (eqs. 8-9) after the odd-length extension (n_e the
+ * even, extended length).  FP64 arithmetic, FP32 storage.
+ *   cube : device, npix * L float32, [p][band]
+ *   coef : device, npix * n float32 (n from hsad_dwt_full_len), [p][a_J d_J ... d_1]
+ * Errors: HSAD_EINVAL (NULL, npix < 1, order outside 1..16, bad levels), HSAD_EUNSUPPORTED
+ * (L > 4096), HSAD_EHIP. */
+int hsad_dwt_full(const float *cube, int64_t npix, int64_t L, int levels, int order, float *coef,
+                  hipStream_t stream);
+
+/* Inverse of hsad_dwt_full: from the coarsest level, each level's synthesis is the
+ * transpose of its analysis on the even length n_e (an orthogonal matrix), and the repeated
+ * sample of an odd level input is dropped, so hsad_idwt_full(hsad_dwt_full(x)) = x up to
+ * rounding for every L.  Same arguments as hsad_dwt_full with the roles of the buffers
+ * exchanged.  Errors as hsad_dwt_full. */
+int hsad_idwt_full(const float *coef, int64_t npix, int64_t L, int levels, int order, float *cube,
+                   hipStream_t stream);
+
 /* Device workspace in bytes for `op` on an H x W x Lp reduced cube with these windows
  * (0 if none is needed).  Passing more lets the detectors process larger pixel chunks
  * per launch; passing less than this value but at least the minimum returned for a
@@ -190,6 +227,27 @@ int hsad_detect_noalloc(const float *x, int64_t H, int64_t W, int64_t Lp, const 
 int hsad_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
                float *scores, float *scores_literal, int32_t *npos, void *ws,
                size_t ws_bytes, hipStream_t stream);
+
+/* Device workspace of hsad_global_rx (bytes; 0 for npix < 1, L' < 1 or L' > 256). */
+size_t hsad_global_rx_workspace_bytes(int64_t npix, int64_t Lp);
+
+/* Global RX: eq. (1) of Sec. 2.1 with the background formed by all npix pixels of the
+ * image (the detector the paper's local variants start from).
+ *   mu = (1/N) sum_p x_p,  C = (1/N) sum_p (x_p - mu)(x_p - mu)^T  (two passes, exact centring),
+ *   score_p = (x_p - mu)^T (C + lambda I)^-1 (x_p - mu),  lambda = load_rel tr(C)/L' (>= 1e-30).
+ * FP64 sums (the Gram on FP64 matrix cores), an FP64 Cholesky of C + lambda I and its
+ * inverse, then every score as the squared norm of L^-1 (x_p - mu), also on matrix cores.
+ * All reductions run in a fixed order (deterministic).  If C + lambda I is not
+ * numerically positive definite (or the cube holds a non-finite value) every score is +inf.
+ *   x      : device, npix * L' float32, [p][k] (any image of npix pixels, e.g. H * W)
+ *   scores : device, npix float32
+ *   mean   : device, L' doubles written (mu), or NULL
+ *   cov    : device, L' * L' doubles written (C before loading, row-major), or NULL
+ *   ws     : device workspace of at least hsad_global_rx_workspace_bytes(npix, L')
+ * Errors: HSAD_EINVAL (NULL x / scores, npix or L' < 1, load_rel < 0 or not finite),
+ * HSAD_EUNSUPPORTED (L' > 256, npix > 2^31), HSAD_ENOMEM, HSAD_EHIP. */
+int hsad_global_rx(const float *x, int64_t npix, int64_t Lp, double load_rel, float *scores,
+                   double *mean, double *cov, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Device workspace for hsad_threshold (bytes; independent of the caller's stream). */
 size_t hsad_threshold_workspace_bytes(int64_t n);

@@ -80,6 +80,10 @@ SIGNATURES = [
     ("hsad_dwt_out_len", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(_i64)]),
     ("hsad_levels_for", ctypes.c_int, [_i64, ctypes.c_int]),
     ("hsad_dwt", ctypes.c_int, [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp]),
+    ("hsad_wavelet_filter", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    ("hsad_dwt_full_len", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(_i64)]),
+    ("hsad_dwt_full", ctypes.c_int, [_vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    ("hsad_idwt_full", ctypes.c_int, [_vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     ("hsad_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64, _i64, _i64, _P]),
     ("hsad_lrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_dwrx", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -90,6 +94,9 @@ SIGNATURES = [
     ("hsad_detect_noalloc", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.c_double, _vp, _vp, _vp, _vp,
                                            _vp]),
     ("hsad_dwest", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    ("hsad_global_rx_workspace_bytes", ctypes.c_size_t, [_i64, _i64]),
+    ("hsad_global_rx", ctypes.c_int, [_vp, _i64, _i64, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                      _vp]),
     ("hsad_threshold_workspace_bytes", ctypes.c_size_t, [_i64]),
     ("hsad_threshold", ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_auc_workspace_bytes", ctypes.c_size_t, [_i64]),
@@ -358,6 +365,73 @@ def hsad_detect(x, inner: int, outer: int, load_rel: float = 1e-6, z_alpha: floa
                            ws.numel() * ws.element_size(), _stream(stream))
     _check("hsad_detect", rc)
     return lrx, dwrx, stats, mask
+
+
+def hsad_wavelet_filter(order: int):
+    """The library's order-`order` Daubechies scaling filter (2 order taps, host)."""
+    import numpy as np
+    h = (ctypes.c_double * (2 * int(order)))() if order >= 1 else (ctypes.c_double * 1)()
+    _check("hsad_wavelet_filter", lib().hsad_wavelet_filter(int(order), h))
+    return np.array(h[:], dtype=np.float64)
+
+
+def hsad_dwt_full_len(L: int, levels: int) -> int:
+    n = _i64()
+    _check("hsad_dwt_full_len", lib().hsad_dwt_full_len(int(L), int(levels), ctypes.byref(n)))
+    return int(n.value)
+
+
+def hsad_dwt_full(cube, levels: int, order: int = 4, out=None, stream=None):
+    """cube (..., L) float32 GPU tensor -> (..., n) coefficients [a_J d_J ... d_1]."""
+    torch = _torch()
+    pc = _dev(cube, "cube", torch.float32)
+    L = int(cube.shape[-1])
+    n = hsad_dwt_full_len(L, levels)
+    npix = cube.numel() // L
+    if out is None:
+        out = torch.empty(tuple(cube.shape[:-1]) + (n,), dtype=torch.float32, device=cube.device)
+    _check("hsad_dwt_full", lib().hsad_dwt_full(pc, npix, L, int(levels), int(order),
+                                                _dev(out, "out", torch.float32), _stream(stream)))
+    return out
+
+
+def hsad_idwt_full(coef, L: int, levels: int, order: int = 4, out=None, stream=None):
+    """coef (..., n) float32 GPU tensor of hsad_dwt_full -> (..., L) signals."""
+    torch = _torch()
+    pc = _dev(coef, "coef", torch.float32)
+    n = hsad_dwt_full_len(L, levels)
+    if int(coef.shape[-1]) != n:
+        raise ValueError("coef must have %d values per pixel" % n)
+    npix = coef.numel() // n
+    if out is None:
+        out = torch.empty(tuple(coef.shape[:-1]) + (int(L),), dtype=torch.float32, device=coef.device)
+    _check("hsad_idwt_full", lib().hsad_idwt_full(pc, npix, int(L), int(levels), int(order),
+                                                  _dev(out, "out", torch.float32), _stream(stream)))
+    return out
+
+
+def hsad_global_rx_workspace_bytes(npix: int, Lp: int) -> int:
+    return int(lib().hsad_global_rx_workspace_bytes(int(npix), int(Lp)))
+
+
+def hsad_global_rx(x, load_rel: float = 1e-6, stats: bool = False, out=None, ws=None, stream=None):
+    """Global RX (eq. 1 with every pixel as background) of a cube x (..., L').  Returns the
+    score map (x.shape[:-1]), or (scores, mean, cov) with stats=True (FP64 device tensors)."""
+    torch = _torch()
+    px = _dev(x, "x", torch.float32)
+    Lp = int(x.shape[-1])
+    npix = x.numel() // Lp if Lp else 0
+    dev = x.device
+    out = torch.empty(tuple(x.shape[:-1]), dtype=torch.float32, device=dev) if out is None else out
+    mean = torch.empty(Lp, dtype=torch.float64, device=dev) if stats else None
+    cov = torch.empty((Lp, Lp), dtype=torch.float64, device=dev) if stats else None
+    if ws is None:
+        ws = torch.empty(max(1, hsad_global_rx_workspace_bytes(npix, Lp)), dtype=torch.uint8, device=dev)
+    rc = lib().hsad_global_rx(px, npix, Lp, float(load_rel), _dev(out, "out", torch.float32),
+                              _ptr_or_null(mean, "mean", torch.float64), _ptr_or_null(cov, "cov", torch.float64),
+                              _dev(ws, "ws"), ws.numel() * ws.element_size(), _stream(stream))
+    _check("hsad_global_rx", rc)
+    return (out, mean, cov) if stats else out
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # HSAD_NOALLOC_SCRATCH_BYTES

@@ -56,6 +56,42 @@ def test_library_filter_matches_oracle_derivation():
     assert np.max(np.abs(np.array(h[:]) - oracle.DB4)) < 2e-16
 
 
+@pytest.mark.parametrize("order", list(range(1, 17)))
+def test_library_daubechies_family_matches_oracle(order):
+    # the library factorises Daubechies' polynomial by the cepstrum and polishes in long
+    # double; the oracle takes the roots of the polynomial and polishes in 80-digit decimals
+    h = hs.hsad_wavelet_filter(order)
+    ref = oracle.daubechies_lowpass(order)
+    assert h.shape == (2 * order,)
+    assert np.max(np.abs(h - ref)) <= 4e-16
+    if order == 4:
+        lib4 = (ctypes.c_double * 8)()
+        assert hs.lib().hsad_internal_filter(lib4) == 0
+        assert np.max(np.abs(h - np.array(lib4[:]))) <= 2e-16
+
+
+def test_full_transform_lengths_and_arguments():
+    for L in (1, 2, 3, 7, 64, 100, 189, 224, 430):
+        for lv in range(0, 10):
+            try:
+                want = oracle.dwt_full_len(L, lv)
+            except ValueError:
+                want = -1
+            if want < 0:
+                with pytest.raises(hs.HsadError):
+                    hs.hsad_dwt_full_len(L, lv)
+            else:
+                assert hs.hsad_dwt_full_len(L, lv) == want
+    L = hs.lib()
+    assert L.hsad_wavelet_filter(0, (ctypes.c_double * 2)()) == hs.HSAD_EINVAL
+    assert L.hsad_wavelet_filter(17, (ctypes.c_double * 34)()) == hs.HSAD_EINVAL
+    assert L.hsad_dwt_full(FAKE, 4, 64, 3, 0, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_dwt_full(FAKE, 4, 64, 7, 4, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_dwt_full(None, 4, 64, 3, 4, FAKE, None) == hs.HSAD_EINVAL
+    assert L.hsad_dwt_full(FAKE, 4, 5000, 3, 4, FAKE, None) == hs.HSAD_EUNSUPPORTED
+    assert L.hsad_idwt_full(FAKE, 0, 64, 3, 4, FAKE, None) == hs.HSAD_EINVAL
+
+
 def _p(inner, outer, load=1e-6, prec=0, reserved=0):
     return hs.WindowParams(inner, outer, load, prec, reserved)
 
@@ -164,6 +200,21 @@ def test_detect_noalloc_rejects_before_any_launch():
     assert rc == hs.HSAD_ENOMEM
     msg = hs.hsad_last_error()
     assert "static scratch" in msg and str(64 << 20) in msg
+
+
+def test_global_rx_arguments():
+    L = hs.lib()
+    assert L.hsad_global_rx_workspace_bytes(0, 4) == 0
+    assert L.hsad_global_rx_workspace_bytes(100, 257) == 0
+    n = L.hsad_global_rx_workspace_bytes(512 * 512, 224)
+    assert n > 224 * 224 * 8 * 2
+    assert L.hsad_global_rx(None, 10, 4, 1e-6, FAKE, None, None, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    assert L.hsad_global_rx(FAKE, 10, 4, 1e-6, None, None, None, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    assert L.hsad_global_rx(FAKE, 0, 4, 1e-6, FAKE, None, None, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    assert L.hsad_global_rx(FAKE, 10, 257, 1e-6, FAKE, None, None, FAKE, 1 << 20, None) == hs.HSAD_EUNSUPPORTED
+    assert L.hsad_global_rx(FAKE, 10, 4, -1.0, FAKE, None, None, FAKE, 1 << 20, None) == hs.HSAD_EINVAL
+    need = L.hsad_global_rx_workspace_bytes(10, 4)
+    assert L.hsad_global_rx(FAKE, 10, 4, 1e-6, FAKE, None, None, FAKE, need - 1, None) == hs.HSAD_ENOMEM
 
 
 def test_surrogate_dims_match_oracle():
