@@ -393,6 +393,8 @@ typedef struct hsad_surrogate_options {
     double audit_frac;      /* fraction of pixels audited (seeded, uniform), 0..1 */
     double fallback_factor; /* exact fallback when the audit RMSE > fallback_factor * rmse_val */
     uint64_t seed;          /* audit stream seed */
+    double band_quantile;   /* 0, or widen the band to this quantile of the audited |error|, [0, 1) */
+    double max_exact_frac;  /* exact fallback when more than this fraction would be recomputed, (0, 1] */
 } hsad_surrogate_options;
 
 typedef struct hsad_surrogate_report {
@@ -406,6 +408,9 @@ typedef struct hsad_surrogate_report {
     double tau;          /* eq. (12) threshold of the final map */
     int32_t fallback;    /* 1 when the whole map was recomputed exactly */
     int32_t reserved;
+    double band_width;   /* half-width of the recomputed band, log1p space */
+    int64_t audit_flips; /* audited pixels whose predicted and exact scores lie on different
+                            sides of the predicted map's eq. (12) threshold */
 } hsad_surrogate_report;
 
 /* Sizes for a reduced band count: D = 3 L', Dp, nparams (FP32) and nbf16 (BF16) counts.
@@ -492,9 +497,13 @@ size_t hsad_surrogate_workspace_bytes(int64_t H, int64_t W, int64_t Lp, int32_t 
 /* Hybrid LRX map of the reduced cube x: features, predictions, eq. (12) on the predicted
  * scores expm1(yhat), selection (hsad_surrogate_select with band = band_k * rmse_val),
  * exact LRX at the selected pixels, audit statistics, and, when the audit RMSE exceeds
- * fallback_factor * rmse_val, exact LRX of the whole map.  Then eq. (12) and the mask
- * (if mask != NULL) of the final map.  scores: device, H*W float32 (exact at the selected
- * pixels, expm1(prediction) elsewhere).  rep: host.  Synchronises `stream` three times.
+ * fallback_factor * rmse_val, exact LRX of the whole map.  With band_quantile > 0 the
+ * audit's |error| histogram (bins of 1/256 in log1p space) sets a wider band when its
+ * band_quantile quantile exceeds band_k * rmse_val; the pixels of that band are also
+ * recomputed exactly, and when the band and the audit together exceed max_exact_frac of
+ * the pixels the whole map is recomputed instead.  Then eq. (12) and the mask (if mask !=
+ * NULL) of the final map.  scores: device, H*W float32 (exact at the selected pixels,
+ * expm1(prediction) elsewhere).  rep: host.  Synchronises `stream` up to five times.
  * Errors: HSAD_EINVAL (arguments, model/cube mismatch), HSAD_ENOMEM, HSAD_EHIP. */
 int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
                        const hsad_mlp_model *model, const hsad_surrogate_options *opt, float *scores,

@@ -53,14 +53,16 @@ class MlpModel(ctypes.Structure):
 class SurrogateOptions(ctypes.Structure):
     _fields_ = [("z_alpha", ctypes.c_double), ("band_k", ctypes.c_double),
                 ("audit_frac", ctypes.c_double), ("fallback_factor", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("band_quantile", ctypes.c_double),
+                ("max_exact_frac", ctypes.c_double)]
 
 
 class SurrogateReport(ctypes.Structure):
     _fields_ = [("pixels", ctypes.c_int64), ("selected", ctypes.c_int64), ("band", ctypes.c_int64),
                 ("audit", ctypes.c_int64), ("audit_rmse", ctypes.c_double),
                 ("audit_max", ctypes.c_double), ("tau_pred", ctypes.c_double), ("tau", ctypes.c_double),
-                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("band_width", ctypes.c_double), ("audit_flips", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -797,7 +799,7 @@ def hsad_surrogate_workspace_bytes(H: int, W: int, Lp: int, Dp: int, inner: int,
 def hsad_surrogate_run(x, inner: int, outer: int, load_rel: float, params, wbf, norm, rmse_val: float,
                        z_alpha: float = 3.0, band_k: float = 3.0, audit_frac: float = 0.01,
                        fallback_factor: float = 2.0, seed: int = 0, scores=None, mask=True, ws=None,
-                       stream=None):
+                       stream=None, band_quantile: float = 0.999, max_exact_frac: float = 0.25):
     """Hybrid LRX map of the reduced cube x; returns (scores, mask or None, report dict)."""
     torch = _torch()
     px = _dev(x, "x", torch.float32, 3)
@@ -809,7 +811,7 @@ def hsad_surrogate_run(x, inner: int, outer: int, load_rel: float, params, wbf, 
     _dev(wbf, "wbf", torch.int16)
     _dev(norm, "norm", torch.float32)
     opt = SurrogateOptions(float(z_alpha), float(band_k), float(audit_frac), float(fallback_factor),
-                           int(seed) & ((1 << 64) - 1))
+                           int(seed) & ((1 << 64) - 1), float(band_quantile), float(max_exact_frac))
     scores = torch.empty((H, W), dtype=torch.float32, device=x.device) if scores is None else scores
     if mask is True:
         mask = torch.empty((H, W), dtype=torch.uint8, device=x.device)

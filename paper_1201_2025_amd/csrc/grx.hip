@@ -11,8 +11,9 @@
 //   grx_gram_kernel     centred samples staged in LDS, upper 16 x 16 tiles of the Gram on
 //                       FP64 matrix cores (v_mfma_f64_16x16x4f64), one partial per range
 //   grx_gram_reduce     partials summed in range order, / N, mirrored into the padded matrix
-//   grx_factor_kernel   loading, blocked Cholesky (16-column blocks) and the blocked inverse
-//                       W = L^-1, one workgroup, matrix in the workspace (L2-resident)
+//   grx_factor_kernel   loading and the blocked Cholesky (16-column blocks), one workgroup,
+//                       matrix in the workspace (L2-resident); inverses of the diagonal blocks
+//   grx_inverse_kernel  W = L^-1 by blocked forward substitution, one workgroup per column block
 //   grx_score_kernel<T> Z = D W^T on matrix cores, 16 pixels per wavefront with their centred
 //                       samples held in registers, W staged in LDS one 16-row block at a time,
 //                       score = row sums of Z^2
@@ -62,18 +63,35 @@ __global__ __launch_bounds__(256) void grx_mean_kernel(const float *__restrict__
     }
 }
 
+// fixed-order sum of the 256 values in red (a pairwise tree), result in red[0]
+__device__ inline void grx_tree256(double *red)
+{
+    const int t = threadIdx.x;
+    for (int h = 128; h > 0; h >>= 1) {
+        __syncthreads();
+        if (t < h) red[t] += red[t + h];
+    }
+    __syncthreads();
+}
+
+// one workgroup per band b < Lpad: thread t sums the ranges t, t + 256, ... in order, then
+// a fixed tree over the threads
 __global__ __launch_bounds__(256) void grx_mean_final(const double *__restrict__ part, int nblk, int Lp, int Lpad,
                                                       int64_t npix, double *__restrict__ mu,
                                                       double *__restrict__ mean_out)
 {
-    const int b = threadIdx.x;
-    if (b >= Lpad) return;
+    __shared__ double red[256];
+    const int b = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
     if (b < Lp)
-        for (int k = 0; k < nblk; ++k) s += part[(size_t)k * Lp + b];
-    const double m = b < Lp ? s / (double)npix : 0.0;
-    mu[b] = m;
-    if (mean_out && b < Lp) mean_out[b] = m;
+        for (int k = t; k < nblk; k += 256) s += part[(size_t)k * Lp + b];
+    red[t] = s;
+    grx_tree256(red);
+    if (t == 0) {
+        const double m = b < Lp ? red[0] / (double)npix : 0.0;
+        mu[b] = m;
+        if (mean_out && b < Lp) mean_out[b] = m;
+    }
 }
 
 // ---- Gram ----------------------------------------------------------------------------
@@ -160,18 +178,26 @@ __global__ __launch_bounds__(256) void grx_gram_kernel(const float *__restrict__
     }
 }
 
-// one workgroup per tile: sum the S partials in order, scale by 1/N and write the tile and
-// its mirror into the padded Lpad x Lpad matrix (identity on the padding)
-__global__ __launch_bounds__(256) void grx_gram_reduce(const double *__restrict__ part, int S, int Lp, int Lpad,
-                                                       int64_t npix, double *__restrict__ A,
-                                                       double *__restrict__ cov_out)
+// one workgroup of 1024 threads per tile: group g = thread / 256 sums the partials
+// g, g + 4, ... of element q = thread % 256 in order, the four groups are added in order;
+// then scale by 1/N and write the tile and its mirror into the padded Lpad x Lpad matrix
+// (identity on the padding)
+__global__ __launch_bounds__(1024) void grx_gram_reduce(const double *__restrict__ part, int S, int Lp, int Lpad,
+                                                        int64_t npix, double *__restrict__ A,
+                                                        double *__restrict__ cov_out)
 {
+    __shared__ double red[4][256];
     const int T = Lpad / 16, ntiles = T * (T + 1) / 2;
-    const int tile = blockIdx.x, q = threadIdx.x;
+    const int tile = blockIdx.x, q = threadIdx.x & 255, grp = threadIdx.x >> 8;
     int bi, bj;
     grx_tile_of(tile, T, bi, bj);
-    double s = 0.0;
-    for (int k = 0; k < S; ++k) s += part[((size_t)k * ntiles + tile) * 256 + q];
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = grp; k < S; k += 4) acc += part[((size_t)k * ntiles + tile) * 256 + q];
+    red[grp][q] = acc;
+    __syncthreads();
+    if (grp) return;
+    const double s = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
     const int e = q >> 6, lane = q & 63;
     // FP64 16x16x4: output element e of lane l is row 4e + (l >> 4), column l & 15
     const int r = 16 * bi + 4 * e + (lane >> 4), c = 16 * bj + (lane & 15);
@@ -190,12 +216,12 @@ __global__ __launch_bounds__(256) void grx_gram_reduce(const double *__restrict_
     }
 }
 
-// ---- loading, blocked Cholesky and inverse (one workgroup of 1024 threads) -------------
+// ---- loading and blocked Cholesky (one workgroup of 1024 threads) ----------------------
 __global__ __launch_bounds__(1024) void grx_factor_kernel(double *__restrict__ A, double *__restrict__ Wm, int Lp,
                                                           int Lpad, double load_rel, double *__restrict__ flag)
 {
     __shared__ double Dl[16][17], Di[16][17];
-    __shared__ double P[kGrxMaxLp][17];     // panel of the current block column, later S blocks
+    __shared__ double P[kGrxMaxLp][17];     // panel of the current block column
     __shared__ double red[16];
     __shared__ int bad;
     const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
@@ -314,28 +340,48 @@ __global__ __launch_bounds__(1024) void grx_factor_kernel(double *__restrict__ A
         }
         __syncthreads();
     }
-    // blocked inverse: W_ib,jb = -Di_ib sum_{kb = jb}^{ib-1} L_ib,kb W_kb,jb  (jb < ib)
-    for (int ib = 1; ib < T; ++ib) {
-        const int i0 = 16 * ib;
-        for (int e = t; e < ib * 256; e += nt) {
-            const int jb = e >> 8, r = (e >> 4) & 15, c = e & 15;
-            const double *lrow = A + (size_t)(i0 + r) * Lpad;
-            double s = 0.0;
-            for (int k = 16 * jb; k < i0; ++k) s += lrow[k] * Wm[(size_t)k * Lpad + 16 * jb + c];
-            P[16 * jb + r][c] = s;
-        }
-        if (t < 256) Di[t >> 4][t & 15] = Wm[(size_t)(i0 + (t >> 4)) * Lpad + i0 + (t & 15)];
-        __syncthreads();
-        for (int e = t; e < ib * 256; e += nt) {
-            const int jb = e >> 8, r = (e >> 4) & 15, c = e & 15;
-            double s = 0.0;
-            for (int q = 0; q <= r; ++q) s += Di[r][q] * P[16 * jb + q][c];
-            Wm[(size_t)(i0 + r) * Lpad + 16 * jb + c] = -s;
-        }
-        __syncthreads();
-    }
     if (t == 0) flag[0] = bad ? 1.0 : 0.0;
 }
+
+// ---- inverse W = L^-1, one workgroup per 16-column block jb -----------------------------
+// Forward substitution over the row blocks below the diagonal:
+//   W_ib,jb = -Di_ib sum_{kb = jb}^{ib - 1} L_ib,kb W_kb,jb   (ib > jb),  W_jb,jb = Di_jb,
+// with Di_ib = L_ib,ib^-1 (written by the factorisation).  The workgroup keeps its column
+// block of W in LDS and stages each row block of L (columns jb .. ib - 1) before using it.
+// LDS (doubles): Wc [Lpad][16], Lr [16][Lpad + 1], S [16][17], Di [16][17].
+__global__ __launch_bounds__(256) void grx_inverse_kernel(const double *__restrict__ A, double *__restrict__ Wm,
+                                                          int Lpad)
+{
+    extern __shared__ double sh[];
+    const int ldl = Lpad + 1;
+    double *Wc = sh, *Lr = Wc + (size_t)Lpad * 16, *Sb = Lr + (size_t)16 * ldl, *Db = Sb + 16 * 17;
+    const int T = Lpad / 16, jb = blockIdx.x, j0 = 16 * jb, t = threadIdx.x;
+    const int r = t >> 4, c = t & 15;
+    Wc[(size_t)(j0 + r) * 16 + c] = Wm[(size_t)(j0 + r) * Lpad + j0 + c];
+    for (int ib = jb + 1; ib < T; ++ib) {
+        const int i0 = 16 * ib, w = i0 - j0;
+        for (int e = t; e < 16 * w; e += 256) {
+            const int rr = e / w, k = e - rr * w;
+            Lr[(size_t)rr * ldl + k] = A[(size_t)(i0 + rr) * Lpad + j0 + k];
+        }
+        Db[r * 17 + c] = Wm[(size_t)(i0 + r) * Lpad + i0 + c];
+        __syncthreads();
+        double acc = 0.0;
+        for (int k = 0; k < w; ++k) acc = fma(Lr[(size_t)r * ldl + k], Wc[(size_t)(j0 + k) * 16 + c], acc);
+        Sb[r * 17 + c] = acc;
+        __syncthreads();
+        double v = 0.0;
+        for (int q = 0; q <= r; ++q) v = fma(Db[r * 17 + q], Sb[q * 17 + c], v);
+        Wc[(size_t)(i0 + r) * 16 + c] = -v;
+        __syncthreads();
+    }
+    for (int e = t; e < (Lpad - j0) * 16; e += 256) {
+        const int rr = j0 + (e >> 4), cc = e & 15;
+        Wm[(size_t)rr * Lpad + j0 + cc] = Wc[(size_t)rr * 16 + cc];
+    }
+}
+
+static size_t grx_inverse_lds(int Lpad) { return ((size_t)Lpad * 16 + 16 * (size_t)(Lpad + 1) + 2 * 16 * 17) * sizeof(double); }
 
 // ---- scores --------------------------------------------------------------------------
 // 8 wavefronts x 16 pixels per workgroup.  Lane l supplies the centred sample of pixel
@@ -420,8 +466,9 @@ static GrxPlan grx_plan(int64_t npix, int64_t Lp)
     int P = (int)((64 * 1024 / sizeof(double) - g.Lpad) / ld) & ~3;
     g.P = std::max(4, std::min(256, P));
     g.G = (g.ntiles + 4 * kGrxTilesPerWave - 1) / (4 * kGrxTilesPerWave);
-    const int64_t chunks = (npix + g.P - 1) / g.P;
-    g.S = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + g.G - 1) / g.G, chunks));
+    // pixel ranges: enough workgroups to fill the GPU, at least 2048 pixels each
+    const int64_t ranges = std::max<int64_t>(1, npix / 2048);
+    g.S = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + g.G - 1) / g.G, ranges));
     size_t o = 0;
     g.off_mu = o;    o += al32((size_t)g.Lpad);
     g.off_part = o;  o += al32((size_t)g.nblk * g.Lp);
@@ -471,18 +518,26 @@ extern "C" int hsad_global_rx(const float *x, int64_t npix, int64_t Lp, double l
 
     hipLaunchKernelGGL(grx_mean_kernel, dim3(g.nblk), dim3(256), 0, stream, x, npix, g.Lp, g.nblk, part);
     if (int rc = check_launch("grx_mean_kernel")) return rc;
-    hipLaunchKernelGGL(grx_mean_final, dim3(1), dim3(256), 0, stream, part, g.nblk, g.Lp, g.Lpad, npix, mu, mean);
+    hipLaunchKernelGGL(grx_mean_final, dim3((unsigned)g.Lpad), dim3(256), 0, stream, part, g.nblk, g.Lp, g.Lpad,
+                       npix, mu, mean);
     if (int rc = check_launch("grx_mean_final")) return rc;
     const size_t sh = ((size_t)g.P * grx_lds_stride(g.Lpad) + g.Lpad) * sizeof(double);
     if (int rc = allow_lds((const void *)grx_gram_kernel, sh, "grx_gram_kernel")) return rc;
     hipLaunchKernelGGL(grx_gram_kernel, dim3((unsigned)(g.S * g.G)), dim3(256), sh, stream, x, npix, g.Lp, g.Lpad,
                        (const double *)mu, g.S, g.G, g.P, gpart);
     if (int rc = check_launch("grx_gram_kernel")) return rc;
-    hipLaunchKernelGGL(grx_gram_reduce, dim3((unsigned)g.ntiles), dim3(256), 0, stream, (const double *)gpart, g.S,
+    hipLaunchKernelGGL(grx_gram_reduce, dim3((unsigned)g.ntiles), dim3(1024), 0, stream, (const double *)gpart, g.S,
                        g.Lp, g.Lpad, npix, A, cov);
     if (int rc = check_launch("grx_gram_reduce")) return rc;
     hipLaunchKernelGGL(grx_factor_kernel, dim3(1), dim3(1024), 0, stream, A, Wm, g.Lp, g.Lpad, load_rel, flag);
     if (int rc = check_launch("grx_factor_kernel")) return rc;
+    if (g.T > 1) {
+        const size_t shi = grx_inverse_lds(g.Lpad);
+        if (int rc = allow_lds((const void *)grx_inverse_kernel, shi, "grx_inverse_kernel")) return rc;
+        hipLaunchKernelGGL(grx_inverse_kernel, dim3((unsigned)(g.T - 1)), dim3(256), shi, stream,
+                           (const double *)A, Wm, g.Lpad);
+        if (int rc = check_launch("grx_inverse_kernel")) return rc;
+    }
     switch (g.T) {
 #define HSAD_GRX_T(n) \
     case n: return launch_score<n>(x, npix, g.Lp, mu, Wm, flag, scores, stream);
