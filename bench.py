@@ -5,9 +5,9 @@
 Workload: a 512 x 512 x 224 FP32 synthetic cube (8 endmembers, 200 implanted anomaly
 objects including 2x2 blobs).  One step is the detection hot path over the cube:
   1. hsad_dwt        per-pixel db4 DWT to L' approximation coefficients (Sec. 4);
-  2. hsad_lrx_dwrx   LRX (eq. 1) and DWRX (eq. 5) with a 5x5 inner / 15x15 outer window,
-                     from one pass of window statistics;
-  3. hsad_threshold  eq. (12) cut-off tau = mu + 3 sigma and the anomaly mask.
+  2. hsad_detect     LRX (eq. 1) and DWRX (eq. 5) with a 5x5 inner / 15x15 outer window,
+                     from one pass of window statistics, then the eq. (12) cut-off
+                     tau = mu + 3 sigma of the LRX map and the anomaly mask.
 The default depth is the paper's rule, "until four samples are left": J = 6, L' = 4.
 Inputs are resident in HBM before timing.  Two copies of the cube alternate between
 steps so that the 256 MB Infinity Cache cannot hold the input.  One JSON line is
@@ -20,7 +20,11 @@ printed.  Beside the timed step, the script also measures:
   * DWEST (eqs. 2-4) at L' = 14 / 28 / 56 on the same cube (inner 3, outer 11);
   * the paper's image shapes and windows (60x100x189, 100x100x189), each detector with and without the DWT;
   * the learned surrogate: exact vs hybrid LRX on a 2048 x 2048 x 224 scene at L' = 14
-    and 56, with the change of ROC AUC.
+    and 56, with the change of ROC AUC;
+  * the reduced-precision Grams at L' = 56, global RX (eq. 1 over the whole image), the full
+    DWT and its inverse (Daubechies orders 1, 4, 16), a Table 1-style AUC sweep with the eq. 11
+    adjacency ring, and max / p99 / median errors of LRX, DWRX and DWEST against the oracle;
+  * with --oracle-protocol, the FP64 oracle at 1 thread and all threads on every configuration.
 """
 from __future__ import annotations
 
@@ -58,6 +62,10 @@ def parse():
                     help="training scenes of 256x256x224 for the surrogate (200 in the full workload)")
     ap.add_argument("--surrogate-levels", type=str, default="4,2",
                     help="DWT depths of the surrogate measurement (4 -> L'=14, 2 -> L'=56)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the reduced-precision, global RX, full DWT, Table 1 sweep and error sections")
+    ap.add_argument("--oracle-protocol", action="store_true",
+                    help="also time the FP64 oracle, 1 thread and all threads, on every configuration (minutes)")
     ap.add_argument("--profile", action="store_true",
                     help="timed steps only, then 3 plain 256 MiB device copies (counter calibration)")
     return ap.parse_args()
@@ -147,9 +155,10 @@ def bench_batch(args, dev):
 
 def bench_dwest(cube, dev, log):
     """DWEST (eqs. 2-4) on the 512 x 512 x 224 cube reduced to L' = 14 / 28 / 56, inner 3 x 3,
-    outer 11 x 11: FP64 Gram of the inner and annulus windows, then a parallel Jacobi
-    eigensolve per pixel.  Reports time, pixels/s and the FP64 rate of the nominal
-    9 L'^3 flop per pixel of a symmetric eigensolve with vectors."""
+    outer 11 x 11: FP64 box statistics of the inner and annulus windows, then per pixel a
+    Householder tridiagonalisation of C_diff and the implicit QL iteration with m_diff carried
+    through.  Reports time, pixels/s and the FP64 rate of the nominal 9 L'^3 flop per pixel
+    of a symmetric eigensolve with vectors."""
     import torch
     import paper_1201_2025_amd as hs
     H, W = cube.shape[0], cube.shape[1]
@@ -298,15 +307,27 @@ def bench_surrogate(args, dev, log):
         def run_hybrid():
             hs.hsad_dwt(cube, lv, out=approx)
             _, _, r = sur.run(approx, z_alpha=3.0, band_k=3.0, audit_frac=0.01, fallback_factor=2.0,
-                              seed=12345, ws=sws, scores=hyb, mask=hmask)
+                              seed=12345, ws=sws, scores=hyb, mask=hmask, exact_above=False)
             rep.update(r)
 
         hybrid_ms = timed(run_hybrid)
-        hs.hsad_dwt(cube, lv, out=approx)
-        pred_ms = timed(lambda: sur.predict(approx))
         a_e = hs.auc_from_counts(hs.hsad_auc(exact, truth_t))
         a_h = hs.auc_from_counts(hs.hsad_auc(hyb, truth_t))
         mm = int((emask != hmask).sum().item())
+        # the same with every predicted detection recomputed exactly (the band extends upward)
+        rep_up = {}
+
+        def run_hybrid_up():
+            hs.hsad_dwt(cube, lv, out=approx)
+            _, _, r = sur.run(approx, z_alpha=3.0, band_k=3.0, audit_frac=0.01, fallback_factor=2.0,
+                              seed=12345, ws=sws, scores=hyb, mask=hmask, exact_above=True)
+            rep_up.update(r)
+
+        hybrid_up_ms = timed(run_hybrid_up)
+        a_u = hs.auc_from_counts(hs.hsad_auc(hyb, truth_t))
+        mm_u = int((emask != hmask).sum().item())
+        hs.hsad_dwt(cube, lv, out=approx)
+        pred_ms = timed(lambda: sur.predict(approx))
         del sws
         entry = {"levels": lv, "Lp": Lp, "train_rows": train_rows, "label_gen_s": label_s,
                  "train_s": train_s, "epochs": len(hist), "val_rmse": sur.rmse_val,
@@ -315,13 +336,253 @@ def bench_surrogate(args, dev, log):
                  "gain": exact_ms / hybrid_ms,
                  "exact_pixels_per_s": npix / (exact_ms * 1e-3), "hybrid_pixels_per_s": npix / (hybrid_ms * 1e-3),
                  "auc_exact": a_e, "auc_hybrid": a_h, "auc_delta": a_h - a_e,
-                 "mask_mismatch": mm, "report": rep}
-        log("surrogate L'=%d: exact %.2f ms, hybrid %.2f ms (gain %.2fx), dAUC %.2e, selected %.4f, fallback %d"
-            % (Lp, exact_ms, hybrid_ms, exact_ms / hybrid_ms, a_h - a_e, rep["selected"] / npix, rep["fallback"]))
+                 "mask_mismatch": mm, "report": rep,
+                 "exact_above": {"hybrid_ms": hybrid_up_ms, "gain": exact_ms / hybrid_up_ms, "auc_hybrid": a_u,
+                                 "auc_delta": a_u - a_e, "mask_mismatch": mm_u, "report": rep_up}}
+        log("surrogate L'=%d: exact %.2f ms, hybrid %.2f ms (gain %.2fx), dAUC %.2e, selected %.4f, fallback %d, "
+            "mask mismatches %d; with exact detections: %.2f ms, dAUC %.2e, selected %.4f, mask mismatches %d"
+            % (Lp, exact_ms, hybrid_ms, exact_ms / hybrid_ms, a_h - a_e, rep["selected"] / npix, rep["fallback"], mm,
+               hybrid_up_ms, a_u - a_e, rep_up["selected"] / npix, mm_u))
         out["levels"].append(entry)
         del sur, approx, exact, hyb
         torch.cuda.empty_cache()
     return out
+
+
+def _timed_ms(fn, reps=10):
+    """Median of reps event-timed calls after one warm-up call."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def _err_stats(g, r):
+    """max / p99 / median of the elementwise relative error with a floor of 1e-3 * median."""
+    g = np.asarray(g, dtype=np.float64).ravel()
+    r = np.asarray(r, dtype=np.float64).ravel()
+    fin = np.isfinite(r) & np.isfinite(g)
+    floor = 1e-3 * np.median(np.abs(r[fin]))
+    e = np.abs(g[fin] - r[fin]) / np.maximum(np.abs(r[fin]), floor)
+    return {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "median": float(np.median(e)),
+            "n": int(fin.sum())}
+
+
+def bench_reduced_precision(cube, truth, dev, log):
+    """The reduced-precision Grams against the exact path at L' = 56 (J = 2) on the 512 x 512 x 224
+    cube, 5 x 5 / 15 x 15 windows (200 annulus samples >= 2 L'): time, ROC AUC and the error
+    against the exact GPU map."""
+    import torch
+    import paper_1201_2025_amd as hs
+    H, W = cube.shape[0], cube.shape[1]
+    x = hs.hsad_dwt(cube, 2)
+    Lp = x.shape[-1]
+    truth_t = torch.from_numpy(truth.ravel()).to(dev)
+    out = {"workload": "512x512x224 cube, J = 2 (L' = 56), LRX inner 5 outer 15", "Lp": Lp, "modes": {}}
+    ref = None
+    for name, prec in (("fp64", hs.HSAD_PREC_AUTO), ("fp32", hs.HSAD_PREC_FP32), ("bf16", hs.HSAD_PREC_GRAM_BF16),
+                       ("fp16", hs.HSAD_PREC_GRAM_FP16)):
+        wsb = hs.hsad_workspace_bytes(hs.HSAD_OP_LRX, H, W, Lp, 5, 15, 1e-6, prec)
+        ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
+        l = torch.empty((H, W), dtype=torch.float32, device=dev)
+        ms = _timed_ms(lambda: hs.hsad_lrx(x, 5, 15, 1e-6, prec, out=l, ws=ws), reps=3)
+        a = hs.auc_from_counts(hs.hsad_auc(l, truth_t))
+        m = l.cpu().numpy()
+        e = {"ms": ms, "auc": a}
+        if ref is None:
+            ref = (m, a)
+        else:
+            e["auc_delta_vs_fp64"] = a - ref[1]
+            e["err_vs_fp64"] = _err_stats(m, ref[0])
+        out["modes"][name] = e
+        log("reduced precision %s L'=%d: %.2f ms, AUC %.5f" % (name, Lp, ms, a))
+        del ws
+    return out
+
+
+def bench_global_rx(cube, dev, log):
+    """Global RX (eq. 1, whole image as background) on the 512 x 512 x 224 cube at L' = 4 (J = 6)
+    and at full band.  Bound: HBM at L' = 4 (reduced cube read twice, scores written); FP64
+    at full band (symmetric Gram and triangular scoring, 2 N L'(L'+1) flop)."""
+    import torch
+    import paper_1201_2025_amd as hs
+    H, W = cube.shape[0], cube.shape[1]
+    n = H * W
+    out = {"workload": "512x512x224 cube, J = 6 (L' = 4) and full band (L' = 224)", "levels": []}
+    for lv in (6, 0):
+        x = hs.hsad_dwt(cube, lv) if lv else cube
+        Lp = x.shape[-1]
+        ws = torch.empty(hs.hsad_global_rx_workspace_bytes(n, Lp), dtype=torch.uint8, device=dev)
+        sc = torch.empty((H, W), dtype=torch.float32, device=dev)
+        ms = _timed_ms(lambda: hs.hsad_global_rx(x, 1e-6, out=sc, ws=ws), reps=10)
+        e = {"levels": lv, "Lp": Lp, "ms": ms, "pixels_per_s": n / (ms * 1e-3)}
+        if Lp <= 16:
+            e["hbm_bytes"] = n * (8 * Lp + 4)
+            e["bound_ms"] = e["hbm_bytes"] / HBM_PEAK * 1e3
+        else:
+            e["fp64_flop"] = 2.0 * n * Lp * (Lp + 1)
+            e["bound_ms"] = e["fp64_flop"] / 78.6e12 * 1e3
+        e["frac_of_bound"] = e["bound_ms"] / ms
+        out["levels"].append(e)
+        log("global RX L'=%d: %.3f ms (%.3f of bound)" % (Lp, ms, e["frac_of_bound"]))
+        del ws
+    return out
+
+
+def bench_wavelet_full(cube, dev, log):
+    """Full DWT [a_J d_J ... d_1] and its inverse (Daubechies orders 1, 4, 16; J = 3) on the
+    512 x 512 x 224 cube: time and the fraction of HBM bandwidth (cube read + coefficients
+    written, or the reverse)."""
+    import torch
+    import paper_1201_2025_amd as hs
+    H, W, L = cube.shape
+    out = {"workload": "512x512x224 cube, J = 3", "orders": []}
+    for order in (1, 4, 16):
+        c = hs.hsad_dwt_full(cube, 3, order)
+        y = torch.empty_like(cube)
+        f = _timed_ms(lambda: hs.hsad_dwt_full(cube, 3, order, out=c), reps=5)
+        i = _timed_ms(lambda: hs.hsad_idwt_full(c, L, 3, order, out=y), reps=5)
+        by = H * W * (L + c.shape[-1]) * 4
+        out["orders"].append({"order": order, "taps": 2 * order, "forward_ms": f, "inverse_ms": i,
+                              "forward_hbm_frac": by / (f * 1e-3) / HBM_PEAK,
+                              "inverse_hbm_frac": by / (i * 1e-3) / HBM_PEAK})
+        log("full DWT db%d: forward %.3f ms, inverse %.3f ms" % (order, f, i))
+        del c, y
+    return out
+
+
+def bench_table1(dev, log):
+    """Table 1-style AUC sweep (Sec. 5.3.1) on device-generated scenes with eq. 10 implants and
+    the eq. 11 adjacency ring (w = 1): the Img1-shaped 60 x 100 x 189 scene with the paper's
+    windows (LRX 15 x 15 single window, DWRX / DWEST 5 x 5 in 13 x 13) at every depth, and the
+    512 x 512 x 224 cube (LRX / DWRX, 5 x 5 / 15 x 15) at J = 0 and 2..6."""
+    from paper_1201_2025_amd import sweep
+    res = {"img1_60x100x189": sweep.table1_sweep(adjacency_w=1.0)}
+    rows = sweep.table1_sweep(H=512, W=512, L=224, seed=1202, K=8, n_single=150, n_blob=50, adjacency_w=1.0,
+                              levels=[0, 2, 3, 4, 5, 6], lrx_window=(5, 15), dual_window=(5, 15),
+                              detectors=("LRX", "DWRX"))
+    res["cube_512x512x224"] = rows
+    for k, v in res.items():
+        log("table1 %s: %s" % (k, ", ".join("%s J=%d %.4f" % (r["detector"], r["levels"], r["auc"]) for r in v)))
+    return res
+
+
+def bench_errors(cube, approx_fn, dev, log):
+    """max / p99 / median relative errors of LRX, DWRX (headline configuration, every pixel)
+    and DWEST (L' = 14, inner 3, outer 11, 20 000 sampled pixels) against the FP64 oracle on
+    the same FP32 reduced cube."""
+    import torch
+    import oracle
+    import paper_1201_2025_amd as hs
+    out = {}
+    x = approx_fn(6)
+    l, d = hs.hsad_lrx_dwrx(x, 5, 15, 1e-6)
+    xn = x.cpu().numpy().astype(np.float64)
+    rl, rd = oracle.lrx_dwrx(xn, 5, 15, 1e-6)
+    out["lrx_L4"] = _err_stats(l.cpu().numpy(), rl)
+    out["dwrx_L4"] = _err_stats(d.cpu().numpy(), rd)
+    x = approx_fn(4)
+    sc, lit, _ = hs.hsad_dwest(x, 3, 11)
+    torch.cuda.synchronize()
+    H, W = x.shape[0], x.shape[1]
+    idx = np.sort(np.random.default_rng(5).choice(H * W, 20000, replace=False))
+    rs, rlit, _ = oracle.dwest(x.cpu().numpy().astype(np.float64), 3, 11, idx=idx)
+    out["dwest_L14"] = _err_stats(sc.cpu().numpy().ravel()[idx], rs)
+    out["dwest_literal_L14"] = _err_stats(lit.cpu().numpy().ravel()[idx], rlit)
+    log("errors: " + ", ".join("%s max %.2e p99 %.2e" % (k, v["max"], v["p99"]) for k, v in out.items()))
+    return out
+
+
+def oracle_protocol(log):
+    """The FP64 oracle on this host, 1 thread and all threads, median of 3, per configuration:
+    the 64 x 64 x 224 parity scene, the 512 x 512 x 224 cube at every depth (LRX + DWRX, 5 / 15),
+    DWEST at L' = 14 / 28 / 56 (3 / 11) and the Img1 / Img2-shaped scenes (all three detectors).
+    Heavy configurations run on a block of whole rows chosen to take about a second and are
+    scaled to the whole image (pixels are independent); each entry says which."""
+    import platform
+    import oracle
+    from paper_1201_2025_amd import synth
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nthreads = oracle.set_threads(None)
+    res = {"cpu_model": cpu_model, "threads_all": nthreads, "machine": platform.machine(), "configs": []}
+
+    def med3(fn):
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    def run(name, cube, levels, work, px_per_row):
+        H = cube.shape[0]
+        # rows: grow the block until one all-thread pass takes about 0.3 s (or the whole image)
+        rows = min(H, 8)
+        while True:
+            sub = np.ascontiguousarray(cube[:rows])
+            t = time.perf_counter()
+            work(sub, levels)
+            dt = time.perf_counter() - t
+            if dt > 0.3 or rows >= H:
+                break
+            rows = min(H, rows * 2)
+        entry = {"config": name, "rows": rows, "of_rows": H, "scaled": rows < H}
+        for tag, th in (("all", nthreads), ("one", 1)):
+            oracle.set_threads(th)
+            s = med3(lambda: work(sub, levels))
+            entry["%s_thread_s" % tag] = s * H / rows
+            entry["%s_thread_pixels_per_s" % tag] = rows * px_per_row / s
+        oracle.set_threads(nthreads)
+        res["configs"].append(entry)
+        log("oracle %s: all %.3g s, one %.3g s (rows %d of %d)" % (name, entry["all_thread_s"],
+                                                                   entry["one_thread_s"], rows, H))
+
+    def lrx_work(inner, outer):
+        def w(sub, lv):
+            x = oracle.dwt_approx(sub, lv) if lv else sub.astype(np.float64)
+            oracle.lrx_dwrx(x, inner, outer, 1e-6)
+        return w
+
+    def dwest_work(inner, outer):
+        def w(sub, lv):
+            x = oracle.dwt_approx(sub, lv) if lv else sub.astype(np.float64)
+            oracle.dwest(x, inner, outer)
+        return w
+
+    c = synth.CONFIGS["small_64x64x224"]
+    s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"], n_blob=c["n_blob"])
+    run("64x64x224 J=6 LRX+DWRX 3/9", s.cube, 6, lrx_work(3, 9), c["W"])
+    c = synth.CONFIGS["cube_512x512x224"]
+    s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"], n_blob=c["n_blob"])
+    for lv in (6, 5, 4, 3, 2, 1, 0):
+        run("512x512x224 J=%d LRX+DWRX 5/15" % lv, s.cube, lv, lrx_work(5, 15), c["W"])
+    for lv in (4, 3, 2):
+        run("512x512x224 J=%d DWEST 3/11" % lv, s.cube, lv, dwest_work(3, 11), c["W"])
+    for name in ("img1_60x100x189", "img2_100x100x189"):
+        c = synth.CONFIGS[name]
+        s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"], n_blob=c["n_blob"])
+        for lv in (c["levels"], 0):
+            run("%s J=%d LRX %d/%d" % (name, lv, c["lrx_inner"], c["lrx_outer"]), s.cube, lv,
+                lrx_work(c["lrx_inner"], c["lrx_outer"]), c["W"])
+            run("%s J=%d DWEST %d/%d" % (name, lv, c["inner"], c["outer"]), s.cube, lv,
+                dwest_work(c["inner"], c["outer"]), c["W"])
+    return res
 
 
 def main():
@@ -414,7 +675,7 @@ def main():
     # once (H W L 4) and write the approximation matrix (H W L' 4).
     dwt_bytes = npix * L * 4 + npix * Lp * 4
     achieved = dwt_bytes / (dwt_ms * 1e-3)
-    dwt_kernel = "dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_cascade_kernel"
+    dwt_kernel = "dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_banded_kernel"
     src_hash = kernel_source_hash(["dwt.hip", "dev_dwt.hpp"])
     traffic = load_traffic(dwt_kernel, "C2_L%d_J%d" % (L, J), src_hash)
 
@@ -466,7 +727,7 @@ def main():
         fl = torch.empty((H, W), dtype=torch.float32, device=dev)
         fd = torch.empty((H, W), dtype=torch.float32, device=dev)
         res = {}
-        for name, prec in (("fp64", hs.HSAD_PREC_AUTO), ("bf16_gram", hs.HSAD_PREC_GRAM_BF16)):
+        for name, prec in (("fp64", hs.HSAD_PREC_AUTO),):
             hs.hsad_lrx_dwrx(cubes[0], inner, outer, load, prec, lrx=fl, dwrx=fd, ws=fb_ws)
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -486,6 +747,8 @@ def main():
         del fb_ws
         full = res
         full["speedup_dwt_vs_fullband_fp64"] = value / res["fp64"]["value"]
+        full["note"] = ("the reduced-precision Grams are refused at full band (200 annulus samples < 2 L'); "
+                        "see reduced_precision for them at L' = 56")
 
     sweep = []
     if not args.no_sweep:
@@ -542,6 +805,24 @@ def main():
         except Exception as e:     # report, keep the headline line
             surrogate = {"error": repr(e)}
 
+    extras = {}
+    if not args.no_extras:
+        for key, fn in (("reduced_precision", lambda: bench_reduced_precision(cubes[0], scene.truth, dev, log)),
+                        ("global_rx", lambda: bench_global_rx(cubes[0], dev, log)),
+                        ("wavelet_full", lambda: bench_wavelet_full(cubes[0], dev, log)),
+                        ("table1_sweep", lambda: bench_table1(dev, log)),
+                        ("errors", lambda: bench_errors(cubes[0], lambda lv: hs.hsad_dwt(cubes[0], lv), dev, log))):
+            try:
+                extras[key] = fn()
+            except Exception as e:     # report, keep the headline line
+                extras[key] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+    if args.oracle_protocol and cpu is not None:
+        try:
+            cpu["protocol"] = oracle_protocol(log)
+        except Exception as e:
+            cpu["protocol"] = {"error": repr(e)}
+
     batch = None
     if not args.no_batch:
         try:
@@ -580,6 +861,7 @@ def main():
         "paper_shaped": paper_shaped,
         "surrogate": surrogate,
     }
+    out.update(extras)
     out.update(result_extra)
     print(json.dumps(out))
 

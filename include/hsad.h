@@ -48,7 +48,10 @@ extern "C" {
 #define HSAD_EHIP (-3)         /* a HIP launch or runtime call failed */
 #define HSAD_EUNSUPPORTED (-4) /* size or precision combination not built */
 
-/* precision of the window covariance (Gram) */
+/* precision of the window covariance (Gram).  The reduced precisions (FP32, BF16, FP16)
+ * need an annulus of at least 2 L' samples (outer^2 - inner^2 >= 2 L'); with fewer the
+ * covariance is (nearly) singular and the call returns HSAD_EUNSUPPORTED.  Pixels near the
+ * image borders whose clipped annulus holds fewer than 2 L' samples take the FP64 Gram. */
 #define HSAD_PREC_AUTO 0       /* exact: FP64 sums / FP64 MFMA Gram, FP64 factorisation */
 #define HSAD_PREC_FP32 1       /* FP32 MFMA Gram on exactly centred samples, FP64 factor */
 #define HSAD_PREC_FP64 2       /* same as AUTO, requested explicitly */
@@ -395,6 +398,8 @@ typedef struct hsad_surrogate_options {
     uint64_t seed;          /* audit stream seed */
     double band_quantile;   /* 0, or widen the band to this quantile of the audited |error|, [0, 1) */
     double max_exact_frac;  /* exact fallback when more than this fraction would be recomputed, (0, 1] */
+    int32_t exact_above;    /* 1: also recompute every pixel predicted above the band (the detections) */
+    int32_t reserved;       /* must be 0 */
 } hsad_surrogate_options;
 
 typedef struct hsad_surrogate_report {
@@ -501,7 +506,8 @@ size_t hsad_surrogate_workspace_bytes(int64_t H, int64_t W, int64_t Lp, int32_t 
  * audit's |error| histogram (bins of 1/256 in log1p space) sets a wider band when its
  * band_quantile quantile exceeds band_k * rmse_val; the pixels of that band are also
  * recomputed exactly, and when the band and the audit together exceed max_exact_frac of
- * the pixels the whole map is recomputed instead.  Then eq. (12) and the mask (if mask !=
+ * the pixels the whole map is recomputed instead.  With exact_above the band extends upward
+ * without limit, so every predicted detection carries its exact score.  Then eq. (12) and the mask (if mask !=
  * NULL) of the final map.  scores: device, H*W float32 (exact at the selected pixels,
  * expm1(prediction) elsewhere).  rep: host.  Synchronises `stream` up to five times.
  * Errors: HSAD_EINVAL (arguments, model/cube mismatch), HSAD_ENOMEM, HSAD_EHIP. */

@@ -185,18 +185,33 @@ def _idx(H: int, W: int, idx) -> np.ndarray:
     return idx
 
 
+_ROUNDING = {None: 0, "fp32": 1, "bf16": 2, "fp16": 3}
+
+
+def round_samples(v: np.ndarray, rounding) -> np.ndarray:
+    """The rounding applied to centred samples by lrx_dwrx(..., rounding=...)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty_like(v)
+    lib().orc_round_samples(ptr(v, _D), v.size, _ROUNDING[rounding], ptr(out, _D))
+    return out
+
+
 def lrx_dwrx(x: np.ndarray, inner: int, outer: int, load_rel: float = 1e-6, idx=None,
-             want=("lrx", "dwrx")):
+             want=("lrx", "dwrx"), rounding=None):
     """LRX (eq. 1, annulus background) and DWRX (eq. 5) at pixels `idx` (flat y*W+x, all
-    pixels by default).  Returns (lrx, dwrx) as float64; an unrequested output is None."""
+    pixels by default).  Returns (lrx, dwrx) as float64; an unrequested output is None.
+    rounding ("fp32", "bf16", "fp16") rounds each centred annulus sample (through binary32,
+    to nearest even) before the covariance sums, the input of the reduced-precision Gram
+    modes; everything else stays FP64."""
     x = _cube64(x)
     _check_windows(inner, outer)
     H, W, Lp = x.shape
     idx = _idx(H, W, idx)
     lrx = np.empty(idx.size) if "lrx" in want else None
     dwrx = np.empty(idx.size) if "dwrx" in want else None
-    lib().orc_lrx_dwrx(ptr(x, _D), H, W, Lp, inner, outer, float(load_rel),
-                       ptr(idx, ctypes.c_int64), idx.size, ptr(lrx, _D), ptr(dwrx, _D))
+    lib().orc_lrx_dwrx_rounded(ptr(x, _D), H, W, Lp, inner, outer, float(load_rel),
+                               ptr(idx, ctypes.c_int64), idx.size, ptr(lrx, _D), ptr(dwrx, _D),
+                               _ROUNDING[rounding])
     return lrx, dwrx
 
 

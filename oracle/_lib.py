@@ -77,6 +77,12 @@ def lib():
             L.orc_lrx_dwrx.argtypes = [_d, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, _i64,
                                        ctypes.c_int64, _d, _d]
+            L.orc_round_samples.restype = None
+            L.orc_round_samples.argtypes = [_d, ctypes.c_int64, ctypes.c_int, _d]
+            L.orc_lrx_dwrx_rounded.restype = None
+            L.orc_lrx_dwrx_rounded.argtypes = [_d, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                               ctypes.c_int, ctypes.c_int, ctypes.c_double, _i64,
+                                               ctypes.c_int64, _d, _d, ctypes.c_int]
             L.orc_jacobi_eig.restype = ctypes.c_int
             L.orc_jacobi_eig.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_double,
                                          ctypes.c_int]

@@ -260,12 +260,46 @@ static int in_box(int64_t dy, int64_t dx, int half)
     return llabs(dy) <= half && llabs(dx) <= half;
 }
 
+/* Rounding of a centred sample before it enters the covariance sums, for the
+ * reduced-precision Gram modes: 0 keeps FP64; 1 rounds to binary32; 2 to bfloat16 and 3 to
+ * binary16, each through binary32 first (round to nearest, ties to even at both steps). */
+static double orc_round_sample(double v, int mode)
+{
+    if (mode == 0) return v;
+    const float f = (float)v;
+    if (mode == 1 || !isfinite(f)) return (double)f;
+    if (mode == 2) {
+        uint32_t b;
+        memcpy(&b, &f, 4);
+        b += 0x7FFFu + ((b >> 16) & 1u);
+        b &= 0xFFFF0000u;
+        float r;
+        memcpy(&r, &b, 4);
+        return (double)r;
+    }
+    /* binary16: 11 significant bits, quantum 2^(e - 11), at least 2^-24 (subnormals) */
+    const double a = fabs((double)f);
+    if (a == 0.0) return (double)f;
+    int e;
+    frexp(a, &e);
+    int q = e - 11;
+    if (q < -24) q = -24;
+    const double r = ldexp(nearbyint(ldexp(a, -q)), q);
+    return copysign(r > 65504.0 ? INFINITY : r, (double)f);
+}
+
+/* Exposed for tests: orc_round_sample over an array. */
+void orc_round_samples(const double *v, int64_t n, int mode, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_round_sample(v[i], mode);
+}
+
 /* Gathers the statistics of one pixel: annulus = outer window minus inner window (both
  * clipped to the image), and the inner window itself.  Two-pass: mean, then centred
- * outer products. */
-static void orc_pixel_stats(const double *x, int64_t H, int64_t W, int64_t Lp, int inner,
-                            int outer, int64_t py, int64_t px, orc_stats *ann,
-                            orc_stats *inn)
+ * outer products (of the centred samples rounded by orc_round_sample(., rnd)). */
+static void orc_pixel_stats_r(const double *x, int64_t H, int64_t W, int64_t Lp, int inner,
+                              int outer, int64_t py, int64_t px, orc_stats *ann,
+                              orc_stats *inn, int rnd)
 {
     const int ro = outer / 2, ri = inner / 2;
     const int64_t y0 = py - ro < 0 ? 0 : py - ro, y1 = py + ro >= H ? H - 1 : py + ro;
@@ -301,7 +335,7 @@ static void orc_pixel_stats(const double *x, int64_t H, int64_t W, int64_t Lp, i
             orc_stats *st = inside ? inn : ann;
             if (!st) continue;
             const double *v = x + (y * W + xx) * Lp;
-            for (int64_t i = 0; i < Lp; ++i) c[i] = v[i] - st->mean[i];
+            for (int64_t i = 0; i < Lp; ++i) c[i] = orc_round_sample(v[i] - st->mean[i], rnd);
             for (int64_t i = 0; i < Lp; ++i)
                 for (int64_t j = 0; j < Lp; ++j) st->cov[i * Lp + j] += c[i] * c[j];
         }
@@ -311,6 +345,13 @@ static void orc_pixel_stats(const double *x, int64_t H, int64_t W, int64_t Lp, i
         if (!st || st->n == 0) continue;
         for (int64_t i = 0; i < Lp * Lp; ++i) st->cov[i] /= (double)st->n;
     }
+}
+
+static void orc_pixel_stats(const double *x, int64_t H, int64_t W, int64_t Lp, int inner,
+                            int outer, int64_t py, int64_t px, orc_stats *ann,
+                            orc_stats *inn)
+{
+    orc_pixel_stats_r(x, H, W, Lp, inner, outer, py, px, ann, inn, 0);
 }
 
 /* Exposed for tests: statistics of one pixel.  n_out = {n_annulus, n_inner}. */
@@ -371,9 +412,23 @@ static double orc_quad_form(const double *Lf, int64_t n, const double *b, double
 /* LRX (eq. 1 with the annulus as local background) and DWRX (eq. 5) at the listed pixels.
  * x: H x W x Lp reduced cube.  Either output may be NULL.  A covariance that is not
  * positive definite after loading gives +inf. */
+void orc_lrx_dwrx_rounded(const double *x, int64_t H, int64_t W, int64_t Lp, int inner, int outer,
+                          double load_rel, const int64_t *idx, int64_t nidx, double *lrx,
+                          double *dwrx, int rnd);
+
 void orc_lrx_dwrx(const double *x, int64_t H, int64_t W, int64_t Lp, int inner, int outer,
                   double load_rel, const int64_t *idx, int64_t nidx, double *lrx,
                   double *dwrx)
+{
+    orc_lrx_dwrx_rounded(x, H, W, Lp, inner, outer, load_rel, idx, nidx, lrx, dwrx, 0);
+}
+
+/* As orc_lrx_dwrx, with each centred annulus sample rounded by orc_round_sample(., rnd)
+ * before its outer product is summed (the Gram of the reduced-precision modes); the means
+ * and the vectors x - mu, m_in - mu stay FP64. */
+void orc_lrx_dwrx_rounded(const double *x, int64_t H, int64_t W, int64_t Lp, int inner, int outer,
+                          double load_rel, const int64_t *idx, int64_t nidx, double *lrx,
+                          double *dwrx, int rnd)
 {
 #pragma omp parallel
     {
@@ -385,7 +440,7 @@ void orc_lrx_dwrx(const double *x, int64_t H, int64_t W, int64_t Lp, int inner, 
         for (int64_t t = 0; t < nidx; ++t) {
             int64_t p = idx[t], py = p / W, px = p % W;
             orc_stats a = {0, mu, C}, b = {0, mi, Ci};
-            orc_pixel_stats(x, H, W, Lp, inner, outer, py, px, &a, dwrx ? &b : NULL);
+            orc_pixel_stats_r(x, H, W, Lp, inner, outer, py, px, &a, dwrx ? &b : NULL, rnd);
             double lam = orc_loading(C, Lp, load_rel);
             for (int64_t i = 0; i < Lp; ++i) C[i * Lp + i] += lam;
             int ok = orc_cholesky(C, Lp) == 0;

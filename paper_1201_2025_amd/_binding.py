@@ -54,7 +54,8 @@ class SurrogateOptions(ctypes.Structure):
     _fields_ = [("z_alpha", ctypes.c_double), ("band_k", ctypes.c_double),
                 ("audit_frac", ctypes.c_double), ("fallback_factor", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("band_quantile", ctypes.c_double),
-                ("max_exact_frac", ctypes.c_double)]
+                ("max_exact_frac", ctypes.c_double), ("exact_above", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SurrogateReport(ctypes.Structure):
@@ -799,7 +800,8 @@ def hsad_surrogate_workspace_bytes(H: int, W: int, Lp: int, Dp: int, inner: int,
 def hsad_surrogate_run(x, inner: int, outer: int, load_rel: float, params, wbf, norm, rmse_val: float,
                        z_alpha: float = 3.0, band_k: float = 3.0, audit_frac: float = 0.01,
                        fallback_factor: float = 2.0, seed: int = 0, scores=None, mask=True, ws=None,
-                       stream=None, band_quantile: float = 0.999, max_exact_frac: float = 0.25):
+                       stream=None, band_quantile: float = 0.999, max_exact_frac: float = 0.25,
+                       exact_above: bool = True):
     """Hybrid LRX map of the reduced cube x; returns (scores, mask or None, report dict)."""
     torch = _torch()
     px = _dev(x, "x", torch.float32, 3)
@@ -811,7 +813,8 @@ def hsad_surrogate_run(x, inner: int, outer: int, load_rel: float, params, wbf, 
     _dev(wbf, "wbf", torch.int16)
     _dev(norm, "norm", torch.float32)
     opt = SurrogateOptions(float(z_alpha), float(band_k), float(audit_frac), float(fallback_factor),
-                           int(seed) & ((1 << 64) - 1), float(band_quantile), float(max_exact_frac))
+                           int(seed) & ((1 << 64) - 1), float(band_quantile), float(max_exact_frac),
+                           1 if exact_above else 0, 0)
     scores = torch.empty((H, W), dtype=torch.float32, device=x.device) if scores is None else scores
     if mask is True:
         mask = torch.empty((H, W), dtype=torch.uint8, device=x.device)

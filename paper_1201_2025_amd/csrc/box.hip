@@ -20,9 +20,10 @@
 //      the second kind is flagged;
 //   2. for each feature chunk and each window (inner, then outer): vertical box sums,
 //      one job per (column, block of 4 output rows) with every feature of the chunk in
-//      registers; running sums along each tile row; then each output thread takes its
-//      horizontal box sum as a difference of two running sums.  S = outer - inner gives
-//      the annulus sums directly;
+//      registers, over only the columns that window's horizontal sums read; then the
+//      horizontal window sums in short sliding segments of 8 outputs per job (the first
+//      sum of a segment taken directly, the next ones by adding the entering column and
+//      subtracting the leaving one).  S = outer - inner gives the annulus sums directly;
 //   3. mu, C, diagonal loading lambda = load_rel tr(C)/L' (floor 1e-30), Cholesky in
 //      registers (FP64), z = L^-1 d and score = |z|^2 for d = x_p - mu (LRX, eq. 1)
 //      and d = m_in - mu (DWRX, eq. 5).

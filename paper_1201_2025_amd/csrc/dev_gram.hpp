@@ -63,6 +63,14 @@ __device__ inline void gram_pixel(const GramArgs &a, int local, double *stage)
     const int n_o = clipn(py, a.R, a.H) * clipn(px, a.R, a.W);
     const int n_i = a.has_inner ? clipn(py, a.RI, a.H) * clipn(px, a.RI, a.W) : 0;
     const int n_a = n_o - n_i;
+    if constexpr (PREC != 0) {
+        // a clipped annulus (image borders) with fewer than 2 L' samples gives a nearly
+        // singular covariance, which the reduced precisions would not resolve: FP64 there
+        if (a.mode == GRAM_LRX && n_a < 2 * a.Lp) {
+            gram_pixel<0, kMaxTilesPerPass>(a, local, stage);
+            return;
+        }
+    }
 
     // ---- pass 1: FP64 sums over the annulus and the inner window ----
     // Loads are unconditional (clamped coordinates and component) with a wave-uniform

@@ -23,6 +23,8 @@
 // and W2n [128][128] (in x out, for the backward pass).
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include <algorithm>
 #include <cmath>
 
@@ -694,14 +696,17 @@ __device__ inline unsigned block_sum_u32(unsigned v, unsigned *red)
 __global__ __launch_bounds__(256) void select_flags_kernel(const float *__restrict__ yhat, int64_t n,
                                                            const double *__restrict__ stats, double band,
                                                            uint64_t seed, uint32_t audit_cut, int64_t seg,
-                                                           uint8_t *__restrict__ flags, unsigned *__restrict__ bcnt)
+                                                           uint8_t *__restrict__ flags, unsigned *__restrict__ bcnt,
+                                                           int upper)
 {
     __shared__ unsigned red[4];
     const double tl = log1p(stats[3]);
     const int64_t b0 = (int64_t)blockIdx.x * seg, b1 = b0 + seg < n ? b0 + seg : n;
     unsigned cs = 0, cb = 0, ca = 0;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
-        const bool in_band = !(fabs((double)yhat[i] - tl) > band);
+        // the band |yhat - log1p(tau)| <= band, or with `upper` everything above its lower edge
+        const double dv = (double)yhat[i] - tl;
+        const bool in_band = upper ? !(dv < -band) : !(fabs(dv) > band);
         const bool audit = (uint32_t)(splitmix64_at(seed, (uint64_t)i) >> 32) < audit_cut;
         const unsigned f = (in_band ? 1u : 0u) | (audit ? 2u : 0u);
         flags[i] = (uint8_t)f;
@@ -874,6 +879,44 @@ __global__ __launch_bounds__(256) void err_final_kernel(const double *__restrict
     }
 }
 
+// Histogram of the audit's absolute prediction errors |yhat - log1p(score)| (log1p space) in
+// kAuditBins bins of width 1 / kAuditBinsPerUnit (the last bin also takes everything beyond),
+// and in hist[kAuditBins] the audited pixels whose predicted score and exact score fall on
+// different sides of the predicted map's eq. (12) threshold (stats[3]).  Integer atomics,
+// so the counts do not depend on the order.
+static constexpr int kAuditBins = 4096;
+static constexpr double kAuditBinsPerUnit = 256.0;
+
+__global__ __launch_bounds__(256) void audit_hist_kernel(const float *__restrict__ yhat,
+                                                         const float *__restrict__ scores,
+                                                         const uint8_t *__restrict__ flags, int64_t n,
+                                                         const double *__restrict__ stats, unsigned *__restrict__ hist)
+{
+    const double tau = stats[3], ltau = log1p(tau);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!(flags[i] & 2)) continue;
+        const double y = (double)yhat[i], sc = (double)scores[i];
+        const double e = y - log1p(sc);
+        if (!isfinite(e)) continue;
+        const double b = fabs(e) * kAuditBinsPerUnit;
+        const int bin = b >= (double)(kAuditBins - 1) ? kAuditBins - 1 : (int)b;
+        atomicAdd(&hist[bin], 1u);
+        if ((y > ltau) != (sc > tau)) atomicAdd(&hist[kAuditBins], 1u);
+    }
+}
+
+// number of audited pixels (flags & 2) outside the second selection (flags2 == 0)
+__global__ __launch_bounds__(256) void audit_outside_kernel(const uint8_t *__restrict__ flags,
+                                                            const uint8_t *__restrict__ flags2, int64_t n,
+                                                            unsigned *__restrict__ count)
+{
+    unsigned c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += ((flags[i] & 2) && !flags2[i]) ? 1u : 0u;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 int grid_for(int64_t n, int cap = 8192)
 {
     int64_t g = (n + 255) / 256;
@@ -967,7 +1010,8 @@ RunLayout run_layout(int64_t H, int64_t W, int64_t Lp, int Dp, const hsad_window
     // then the threshold / error-statistics workspace
     L.small = o;
     o = align256(o + 256 + std::max({hsad_threshold_workspace_bytes(n), (size_t)3 * 1024 * sizeof(double),
-                                     (size_t)kSelMaxBlocks * 4 * sizeof(unsigned)}));
+                                     (size_t)kSelMaxBlocks * 4 * sizeof(unsigned),
+                                     (size_t)(kAuditBins + 1) * sizeof(unsigned)}));
     L.gen = o;
     size_t g = hsad_workspace_bytes(HSAD_OP_LRX, H, W, Lp, p);
     g = std::max(g, generic_ws_per_pixel(Lp, GRAM_LRX) * (size_t)std::min<int64_t>(n, 8192));
@@ -1121,9 +1165,20 @@ size_t hsad_surrogate_select_workspace_bytes(int64_t n)
     return (size_t)kSelMaxBlocks * 4 * sizeof(unsigned);
 }
 
+static int select_common(const float *yhat, int64_t n, const double *stats, double band, uint64_t seed,
+                         double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, void *ws,
+                         size_t ws_bytes, hipStream_t stream, int upper);
+
 int hsad_surrogate_select(const float *yhat, int64_t n, const double *stats, double band, uint64_t seed,
                           double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, void *ws,
                           size_t ws_bytes, hipStream_t stream)
+{
+    return select_common(yhat, n, stats, band, seed, audit_frac, flags, idx, counts, ws, ws_bytes, stream, 0);
+}
+
+static int select_common(const float *yhat, int64_t n, const double *stats, double band, uint64_t seed,
+                         double audit_frac, uint8_t *flags, int32_t *idx, uint32_t *counts, void *ws,
+                         size_t ws_bytes, hipStream_t stream, int upper)
 {
     clear_error();
     if (!yhat || !stats || !flags || !idx || !counts || n < 1 || n > ((int64_t)1 << 31) - 1 || !(band >= 0.0) ||
@@ -1140,7 +1195,7 @@ int hsad_surrogate_select(const float *yhat, int64_t n, const double *stats, dou
     nb = (n + seg - 1) / seg;
     unsigned *bcnt = (unsigned *)ws, *boff = bcnt + 3 * kSelMaxBlocks;
     hipLaunchKernelGGL(select_flags_kernel, dim3((unsigned)nb), dim3(256), 0, stream, yhat, n, stats, band, seed,
-                       audit_cut, seg, flags, bcnt);
+                       audit_cut, seg, flags, bcnt, upper);
     hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(1024), 0, stream, (const unsigned *)bcnt, (int)nb, boff,
                        (unsigned *)counts);
     hipLaunchKernelGGL(select_write_kernel, dim3((unsigned)nb), dim3(256), 0, stream, flags, n, seg,
@@ -1185,7 +1240,9 @@ int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const h
         model->Dp < 3 * Lp || !(model->rmse_val >= 0.0))
         return fail(HSAD_EINVAL, "hsad_surrogate_run: model does not match the cube (L', Dp, pointers, rmse_val)");
     if (!(opt->band_k >= 0.0) || !(opt->audit_frac >= 0.0 && opt->audit_frac <= 1.0) ||
-        !std::isfinite(opt->z_alpha) || !(opt->fallback_factor > 0.0))
+        !std::isfinite(opt->z_alpha) || !(opt->fallback_factor > 0.0) ||
+        !(opt->band_quantile >= 0.0 && opt->band_quantile < 1.0) ||
+        !(opt->max_exact_frac > 0.0 && opt->max_exact_frac <= 1.0) || opt->reserved != 0)
         return fail(HSAD_EINVAL, "hsad_surrogate_run: bad options");
     if (p->precision != HSAD_PREC_AUTO && p->precision != HSAD_PREC_FP64)
         return fail(HSAD_EINVAL, "hsad_surrogate_run: exact recomputation needs precision AUTO/FP64");
@@ -1212,8 +1269,8 @@ int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const h
     if ((rc = hsad_threshold(scores, n, opt->z_alpha, dev_stats, nullptr, ws_small, ws_small_bytes, stream)))
         return rc;
     // near-threshold band + audit sample, then exact LRX there (overwrites those pixels)
-    if ((rc = hsad_surrogate_select(yhat, n, dev_stats, opt->band_k * model->rmse_val, opt->seed, opt->audit_frac,
-                                    flags, idx, counts, ws_small, ws_small_bytes, stream)))
+    if ((rc = select_common(yhat, n, dev_stats, opt->band_k * model->rmse_val, opt->seed, opt->audit_frac, flags, idx,
+                            counts, ws_small, ws_small_bytes, stream, opt->exact_above ? 1 : 0)))
         return rc;
     uint32_t hc[3] = {0, 0, 0};
     if (hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -1229,7 +1286,66 @@ int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const h
         hipStreamSynchronize(stream) != hipSuccess)
         return fail(HSAD_EHIP, "hsad_surrogate_run: reading the audit failed");
     const double *audit = hs + 8;
-    const int fallback = (audit[0] > 0.0 && !(audit[1] <= opt->fallback_factor * model->rmse_val)) ? 1 : 0;
+    int fallback = (audit[0] > 0.0 && !(audit[1] <= opt->fallback_factor * model->rmse_val)) ? 1 : 0;
+    // the audit's error tail and mask flips: the band widens to the band_quantile quantile of
+    // the audited |error| (when that exceeds band_k * rmse_val), and the pixels of the wider
+    // band are recomputed exactly as well
+    double band = opt->band_k * model->rmse_val;
+    int64_t flips = 0, band_count = hc[1], selected = hc[0];
+    if (!fallback && hc[2] > 0) {
+        unsigned *hist = (unsigned *)ws_small;
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, stream, hist, kAuditBins + 1, 0u);
+        hipLaunchKernelGGL(audit_hist_kernel, dim3(grid_for(n)), dim3(256), 0, stream, yhat, scores, flags, n,
+                           (const double *)dev_stats, hist);
+        if ((rc = check_launch("audit_hist_kernel"))) return rc;
+        std::vector<unsigned> hh(kAuditBins + 1);
+        if (hipMemcpyAsync(hh.data(), hist, hh.size() * sizeof(unsigned), hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return fail(HSAD_EHIP, "hsad_surrogate_run: reading the audit histogram failed");
+        flips = hh[kAuditBins];
+        if (opt->band_quantile > 0.0) {
+            uint64_t tot = 0;
+            for (int b = 0; b < kAuditBins; ++b) tot += hh[b];
+            const double want = opt->band_quantile * (double)tot;
+            uint64_t cum = 0;
+            int qb = kAuditBins - 1;
+            for (int b = 0; b < kAuditBins; ++b) {
+                cum += hh[b];
+                if ((double)cum >= want) {
+                    qb = b;
+                    break;
+                }
+            }
+            const double qw = (double)(qb + 1) / kAuditBinsPerUnit;   // upper edge of the quantile's bin
+            if (qw > band) {
+                band = qw;
+                // the feature rows are no longer needed: their space holds the second
+                // selection's flags and indices
+                uint8_t *flags2 = (uint8_t *)X;
+                int32_t *idx2 = (int32_t *)((char *)X + align256((size_t)n));
+                if ((rc = select_common(yhat, n, dev_stats, band, opt->seed, 0.0, flags2, idx2, counts, ws_small,
+                                        ws_small_bytes, stream, opt->exact_above ? 1 : 0)))
+                    return rc;
+                hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, stream, counts + 3, 1, 0u);
+                hipLaunchKernelGGL(audit_outside_kernel, dim3(grid_for(n, 1024)), dim3(256), 0, stream,
+                                   (const uint8_t *)flags, (const uint8_t *)flags2, n, counts + 3);
+                if ((rc = check_launch("audit_outside_kernel"))) return rc;
+                uint32_t h2[4] = {0, 0, 0, 0};
+                if (hipMemcpyAsync(h2, counts, sizeof(h2), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                    hipStreamSynchronize(stream) != hipSuccess)
+                    return fail(HSAD_EHIP, "hsad_surrogate_run: reading the selection counts failed");
+                band_count = h2[1];
+                selected = (int64_t)h2[0] + (int64_t)h2[3];   // the wider band, plus the audit outside it
+                if ((double)selected > opt->max_exact_frac * (double)n) {
+                    fallback = 1;
+                } else if (h2[0] > 0 && (rc = hsad_lrx_dwrx_at(x, H, W, Lp, p, idx2, h2[0], scores, nullptr, ws_gen,
+                                                               ws_gen_bytes, stream))) {
+                    return rc;
+                }
+            }
+        }
+    }
     if (fallback && (rc = hsad_lrx(x, H, W, Lp, p, scores, ws_gen, ws_gen_bytes, stream))) return rc;
     // eq. (12) threshold and mask of the final map
     if ((rc = hsad_threshold(scores, n, opt->z_alpha, dev_stats + 4, mask, ws_small, ws_small_bytes, stream)))
@@ -1239,8 +1355,8 @@ int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const h
         hipStreamSynchronize(stream) != hipSuccess)
         return fail(HSAD_EHIP, "hsad_surrogate_run: reading the threshold failed");
     rep->pixels = n;
-    rep->selected = fallback ? n : (int64_t)hc[0];
-    rep->band = hc[1];
+    rep->selected = fallback ? n : selected;
+    rep->band = band_count;
     rep->audit = hc[2];
     rep->audit_rmse = audit[1];
     rep->audit_max = audit[2];
@@ -1248,6 +1364,8 @@ int hsad_surrogate_run(const float *x, int64_t H, int64_t W, int64_t Lp, const h
     rep->tau = tf[3];
     rep->fallback = fallback;
     rep->reserved = 0;
+    rep->band_width = band;
+    rep->audit_flips = flips;
     return HSAD_OK;
 }
 

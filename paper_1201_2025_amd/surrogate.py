@@ -137,13 +137,16 @@ class Surrogate:
         return B.hsad_mlp_infer(Xp, self.params, self.wbf).reshape(x.shape[0], x.shape[1])
 
     def run(self, x, z_alpha: float = 3.0, band_k: float = 3.0, audit_frac: float = 0.01,
-            fallback_factor: float = 2.0, seed: int = 0, ws=None, scores=None, mask=True):
+            fallback_factor: float = 2.0, seed: int = 0, ws=None, scores=None, mask=True,
+            band_quantile: float = 0.999, max_exact_frac: float = 0.25, exact_above: bool = True):
         """Hybrid LRX map of the reduced cube x: (scores, mask, report)."""
         if self.norm is None or self.rmse_val is None:
             raise RuntimeError("the surrogate is not trained")
         return B.hsad_surrogate_run(x, self.inner, self.outer, self.load_rel, self.params, self.wbf, self.norm,
                                     self.rmse_val, z_alpha=z_alpha, band_k=band_k, audit_frac=audit_frac,
-                                    fallback_factor=fallback_factor, seed=seed, scores=scores, mask=mask, ws=ws)
+                                    fallback_factor=fallback_factor, seed=seed, scores=scores, mask=mask, ws=ws,
+                                    band_quantile=band_quantile, max_exact_frac=max_exact_frac,
+                                    exact_above=exact_above)
 
     def workspace_bytes(self, H: int, W: int) -> int:
         return B.hsad_surrogate_workspace_bytes(H, W, self.Lp, self.Dp, self.inner, self.outer, self.load_rel)

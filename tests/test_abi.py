@@ -257,17 +257,17 @@ def test_surrogate_argument_errors():
                                  1 << 30, None) == hs.HSAD_EINVAL
     # hybrid run: model / cube mismatch, options, workspace
     m = hs.MlpModel(0x1000, 0x1000, 0x1000, 14, 64, 0, 0.1)
-    o = hs.SurrogateOptions(3.0, 3.0, 0.01, 2.0, 1, 0.999, 0.25)
+    o = hs.SurrogateOptions(3.0, 3.0, 0.01, 2.0, 1, 0.999, 0.25, 0, 0)
     rep = hs.SurrogateReport()
     run = L.hsad_surrogate_run
     assert run(FAKE, 64, 64, 13, ctypes.byref(p), ctypes.byref(m), ctypes.byref(o), FAKE, FAKE,
                ctypes.byref(rep), FAKE, 1 << 40, None) == hs.HSAD_EINVAL
     assert "model" in hs.hsad_last_error()
-    bad = hs.SurrogateOptions(3.0, 3.0, 2.0, 2.0, 1, 0.999, 0.25)
+    bad = hs.SurrogateOptions(3.0, 3.0, 2.0, 2.0, 1, 0.999, 0.25, 0, 0)
     assert run(FAKE, 64, 64, 14, ctypes.byref(p), ctypes.byref(m), ctypes.byref(bad), FAKE, FAKE,
                ctypes.byref(rep), FAKE, 1 << 40, None) == hs.HSAD_EINVAL
     for q, mx in ((1.0, 0.25), (-0.1, 0.25), (0.999, 0.0), (0.999, 1.5)):
-        bq = hs.SurrogateOptions(3.0, 3.0, 0.01, 2.0, 1, q, mx)
+        bq = hs.SurrogateOptions(3.0, 3.0, 0.01, 2.0, 1, q, mx, 0, 0)
         assert run(FAKE, 64, 64, 14, ctypes.byref(p), ctypes.byref(m), ctypes.byref(bq), FAKE, FAKE,
                    ctypes.byref(rep), FAKE, 1 << 40, None) == hs.HSAD_EINVAL
     need = L.hsad_surrogate_workspace_bytes(64, 64, 14, 64, ctypes.byref(p))

@@ -213,3 +213,42 @@ def test_global_rx_affine_invariance_and_subset():
     assert np.allclose(g1, g2, rtol=1e-8)
     idx = np.array([0, 17, H * W - 1, 17])
     assert np.array_equal(oracle.global_rx(x, 1e-6, idx=idx), oracle.global_rx(x, 1e-6)[idx])
+
+
+def test_sample_rounding_matches_library_conversions():
+    """The reduced-precision roundings of the oracle against numpy's binary32 and binary16
+    and torch's bfloat16 conversions (each from binary32, round to nearest even), on
+    ordinary values, ties, subnormals, overflow and signed zero."""
+    import torch
+    rng = np.random.default_rng(3)
+    v = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.integers(-9, 6, 4000),
+                        [0.0, -0.0, 1.0, -1.0, 65504.0, 65519.0, 65520.0, 1e6, -1e6, 2.0 ** -24,
+                         2.0 ** -25, 3 * 2.0 ** -26, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -9,
+                         1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -12, 1e-40, np.inf, -np.inf]])
+    f32 = v.astype(np.float32)
+    assert np.array_equal(oracle.round_samples(v, "fp32"), f32.astype(np.float64))
+    with np.errstate(over="ignore"):
+        want16 = f32.astype(np.float16).astype(np.float64)
+    got16 = oracle.round_samples(v, "fp16")
+    assert np.array_equal(np.signbit(got16), np.signbit(want16))
+    assert np.array_equal(got16, want16)
+    wantbf = torch.from_numpy(f32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(oracle.round_samples(v, "bf16"), wantbf)
+    assert np.array_equal(oracle.round_samples(v, None), v)
+
+
+def test_rounded_statistics_reduce_to_exact_on_representable_data():
+    """Data whose centred samples are exactly representable in bfloat16 (small integers on a
+    window whose mean is an integer) gives the same LRX with and without rounding."""
+    x = np.zeros((9, 9, 3))
+    rng = np.random.default_rng(4)
+    x[:] = rng.integers(-4, 5, size=(9, 9, 3))
+    # single pixel whose 3 x 3 annulus (inner 1) mean is integral: make it so by construction
+    idx = np.array([4 * 9 + 4])
+    ann = [(4 + dy) * 9 + 4 + dx for dy in (-1, 0, 1) for dx in (-1, 0, 1) if dy or dx]
+    flat = x.reshape(-1, 3)
+    flat[ann[-1]] += (8 - flat[ann].sum(axis=0) % 8) % 8   # annulus sums divisible by 8
+    for r in ("fp32", "bf16", "fp16"):
+        a = oracle.lrx_dwrx(x, 1, 3, 1e-6, idx=idx, want=("lrx",))[0]
+        b = oracle.lrx_dwrx(x, 1, 3, 1e-6, idx=idx, want=("lrx",), rounding=r)[0]
+        assert np.array_equal(a, b)
