@@ -99,6 +99,13 @@ int hsad_levels_for(int64_t L, int target);
  *   cube   : device, H*W*L float32, [y][x][band]
  *   approx : device, H*W*L' float32, [y][x][k]; must not overlap cube
  *   levels : 0 copies the cube
+ * The first call for an (L, levels) pair on a device computes its composite filter table on
+ * the host and enqueues the table's copy into a library-owned device arena (4 MiB, from a
+ * pinned host mirror allocated on the first call) on `stream`, ahead of the transform;
+ * calls on other streams wait for that copy through an event, and nothing synchronises.
+ * Under graph capture the copy is captured with the transform.  A first call of the process
+ * made under capture (no pinned mirror yet), or one for which the arena is full, uses the
+ * level-by-level kernel instead, with the same results to rounding.
  * Errors: HSAD_EINVAL (H, W, L < 1, bad levels, null pointers), HSAD_EHIP. */
 int hsad_dwt(const float *cube, int64_t H, int64_t W, int64_t L, int levels, float *approx,
              hipStream_t stream);

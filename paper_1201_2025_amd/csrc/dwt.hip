@@ -65,6 +65,14 @@ void dwt_composite_matrix(int64_t L, int levels, double *A)
 }
 
 // Device-resident cache of equivalent-filter matrices (append-only arena, FP64).
+//
+// The tables are computed on the host once per (device, L, J, layout) and written into the
+// device arena by an asynchronous copy from a pinned host mirror of the arena, on the
+// caller's stream, so no call synchronises.  An event recorded after that copy orders other
+// streams: a later call on another stream waits on it (hipStreamWaitEvent) until the event
+// is seen complete, after which nothing is enqueued.  A call on a stream under graph capture
+// enqueues the copy again inside the graph (the same bytes: replays rewrite identical
+// values), so a captured DWT never depends on work outside the graph.
 static constexpr size_t kCoefArenaDoubles = 1u << 19;   // 4 MiB per device
 __device__ double g_coef_arena[kCoefArenaDoubles];
 
@@ -83,13 +91,103 @@ struct CoefKey {
     }
 };
 struct CoefEntry {
-    size_t offset;               // in doubles
-    std::vector<double> host;    // kept alive for the asynchronous upload
+    size_t offset = 0;           // in doubles, in the device arena and its pinned mirror
+    size_t n = 0;                // doubles
+    int W = 0;                   // banded tables: band width
+    hipEvent_t ev = nullptr;     // recorded after the first uncaptured copy
+    int state = 0;               // 0 not uploaded outside a capture, 1 copy in flight, 2 resident
+};
+struct DevArena {
+    double *dev = nullptr;       // device address of g_coef_arena
+    double *pinned = nullptr;    // pinned host mirror (kCoefArenaDoubles)
+    size_t used = 0;
 };
 std::mutex g_coef_mu;
 std::map<CoefKey, CoefEntry> g_coef;
-std::map<int, size_t> g_coef_used;
+std::map<int, DevArena> g_arena;
 }  // namespace
+
+static bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs == hipStreamCaptureStatusActive;
+}
+
+// The arena of the current device (allocating its pinned mirror on first use, which is
+// refused under graph capture).  Caller holds g_coef_mu.
+static DevArena *arena_for(int dev, bool capturing)
+{
+    DevArena &a = g_arena[dev];
+    if (!a.dev && hipGetSymbolAddress((void **)&a.dev, HIP_SYMBOL(g_coef_arena)) != hipSuccess) {
+        (void)hipGetLastError();
+        a.dev = nullptr;
+        return nullptr;
+    }
+    if (!a.pinned) {
+        if (capturing) return nullptr;
+        if (hipHostMalloc((void **)&a.pinned, kCoefArenaDoubles * sizeof(double), hipHostMallocDefault) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            a.pinned = nullptr;
+            return nullptr;
+        }
+    }
+    return &a;
+}
+
+// Makes the entry's table visible to work enqueued next on s (see the note above).  Caller
+// holds g_coef_mu.
+static bool entry_ready_on(CoefEntry &e, DevArena &a, hipStream_t s)
+{
+    if (e.state == 2) return true;
+    const bool capturing = stream_capturing(s);
+    if (e.state == 1 && !capturing) {
+        const hipError_t q = hipEventQuery(e.ev);
+        if (q == hipSuccess) {
+            e.state = 2;
+            return true;
+        }
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();
+            return hipStreamWaitEvent(s, e.ev, 0) == hipSuccess;
+        }
+        (void)hipGetLastError();
+        return false;
+    }
+    if (hipMemcpyAsync(a.dev + e.offset, a.pinned + e.offset, e.n * sizeof(double), hipMemcpyHostToDevice, s) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (!capturing) {
+        if (!e.ev && hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            e.ev = nullptr;
+            return false;
+        }
+        if (hipEventRecord(e.ev, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        e.state = 1;
+    }
+    return true;
+}
+
+// Reserves n doubles of the arena for a new entry; false when it is full.
+static bool reserve(DevArena &a, size_t n, CoefEntry &e)
+{
+    const size_t off = (a.used + 31) & ~(size_t)31;   // 256-byte aligned entries
+    if (off + n > kCoefArenaDoubles) return false;
+    e.offset = off;
+    e.n = n;
+    a.used = off + n;
+    return true;
+}
 
 // Returns a device pointer to the interleaved [L/VEC][L'][VEC] matrix, or nullptr when the
 // arena is full (the caller then uses the cascade kernel).
@@ -98,32 +196,26 @@ static const double *composite_coefs(int64_t L, int levels, int64_t Lp, int vec,
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(g_coef_mu);
-    double *base = nullptr;
-    if (hipGetSymbolAddress((void **)&base, HIP_SYMBOL(g_coef_arena)) != hipSuccess) return nullptr;
+    DevArena *a = arena_for(dev, stream_capturing(s));
+    if (!a) return nullptr;
     CoefKey key{dev, L, levels, vec};
     auto it = g_coef.find(key);
-    if (it != g_coef.end()) return base + it->second.offset;
-    const size_t nfl = (size_t)(Lp * L);
-    size_t &used = g_coef_used[dev];
-    size_t off = (used + 31) & ~(size_t)31;      // 256-byte aligned entries
-    if (off + nfl > kCoefArenaDoubles) return nullptr;
-    std::vector<double> A((size_t)(Lp * L));
-    dwt_composite_matrix(L, levels, A.data());
-    CoefEntry e;
-    e.offset = off;
-    e.host.resize(nfl);
-    const int64_t nc = L / vec;
-    for (int64_t c = 0; c < nc; ++c)
-        for (int64_t k = 0; k < Lp; ++k)
-            for (int v = 0; v < vec; ++v)
-                e.host[(size_t)((c * Lp + k) * vec + v)] = A[(size_t)(k * L + c * vec + v)];
-    if (hipMemcpyAsync(base + off, e.host.data(), nfl * sizeof(double), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
-        return nullptr;
-    if (hipStreamSynchronize(s) != hipSuccess) return nullptr;   // once per (L, J)
-    used = off + nfl;
-    auto res = g_coef.emplace(key, std::move(e));
-    return base + res.first->second.offset;
+    if (it == g_coef.end()) {
+        const size_t nfl = (size_t)(Lp * L);
+        CoefEntry e;
+        if (!reserve(*a, nfl, e)) return nullptr;
+        std::vector<double> A((size_t)(Lp * L));
+        dwt_composite_matrix(L, levels, A.data());
+        double *dst = a->pinned + e.offset;
+        const int64_t nc = L / vec;
+        for (int64_t c = 0; c < nc; ++c)
+            for (int64_t k = 0; k < Lp; ++k)
+                for (int v = 0; v < vec; ++v)
+                    dst[(size_t)((c * Lp + k) * vec + v)] = A[(size_t)(k * L + c * vec + v)];
+        it = g_coef.emplace(key, e).first;
+    }
+    if (!entry_ready_on(it->second, *a, s)) return nullptr;
+    return a->dev + it->second.offset;
 }
 
 // Banded form of the composite matrix: per row k the smallest circular window of input
@@ -141,8 +233,8 @@ static bool banded_coefs(int64_t L, int levels, int64_t Lp, int max_w, hipStream
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     std::lock_guard<std::mutex> lk(g_coef_mu);
-    double *base = nullptr;
-    if (hipGetSymbolAddress((void **)&base, HIP_SYMBOL(g_coef_arena)) != hipSuccess) return false;
+    DevArena *a = arena_for(dev, stream_capturing(s));
+    if (!a) return false;
     CoefKey key{dev, L, levels, -1};
     auto it = g_coef.find(key);
     if (it == g_coef.end()) {
@@ -164,9 +256,9 @@ static bool banded_coefs(int64_t L, int levels, int64_t Lp, int max_w, hipStream
             // largest circular gap between consecutive nonzeros; the window is its complement
             int64_t best_gap = -1, best_next = 0;
             for (size_t q = 0; q < nz.size(); ++q) {
-                const int64_t a = nz[q], b = q + 1 < nz.size() ? nz[q + 1] : nz[0] + L;
-                if (b - a - 1 > best_gap) {
-                    best_gap = b - a - 1;
+                const int64_t a0 = nz[q], b0 = q + 1 < nz.size() ? nz[q + 1] : nz[0] + L;
+                if (b0 - a0 - 1 > best_gap) {
+                    best_gap = b0 - a0 - 1;
                     best_next = (q + 1 < nz.size() ? nz[q + 1] : nz[0]);
                 }
             }
@@ -176,27 +268,20 @@ static bool banded_coefs(int64_t L, int levels, int64_t Lp, int max_w, hipStream
         }
         const size_t ncoef = (size_t)(Lp * W), nst = (size_t)((Lp + 1) / 2);
         CoefEntry e;
-        e.host.assign(ncoef + nst, 0.0);
+        e.W = W;
+        if (!reserve(*a, ncoef + nst, e)) return false;
+        double *dst = a->pinned + e.offset;
+        std::fill(dst, dst + ncoef + nst, 0.0);
         for (int64_t k = 0; k < Lp; ++k)
-            for (int t = 0; t < wd[k]; ++t) e.host[(size_t)(k * W + t)] = A[(size_t)(k * L + (st[k] + t) % L)];
-        std::memcpy(e.host.data() + ncoef, st.data(), st.size() * sizeof(int32_t));
-        size_t &used = g_coef_used[dev];
-        const size_t off = (used + 31) & ~(size_t)31;
-        if (off + ncoef + nst + 1 > kCoefArenaDoubles) return false;
-        e.host.push_back((double)W);   // width kept after the table
-        e.offset = off;
-        if (hipMemcpyAsync(base + off, e.host.data(), e.host.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return false;
-        used = off + e.host.size();
-        it = g_coef.emplace(key, std::move(e)).first;
+            for (int t = 0; t < wd[k]; ++t) dst[(size_t)(k * W + t)] = A[(size_t)(k * L + (st[k] + t) % L)];
+        std::memcpy(dst + ncoef, st.data(), st.size() * sizeof(int32_t));
+        it = g_coef.emplace(key, e).first;
     }
-    const std::vector<double> &h = it->second.host;
-    const int W = (int)h.back();
+    const int W = it->second.W;
     if (W < 1 || W > max_w) return false;
-    out->coef = base + it->second.offset;
-    out->start = reinterpret_cast<const int32_t *>(base + it->second.offset + (size_t)(Lp * W));
+    if (!entry_ready_on(it->second, *a, s)) return false;
+    out->coef = a->dev + it->second.offset;
+    out->start = reinterpret_cast<const int32_t *>(a->dev + it->second.offset + (size_t)(Lp * W));
     out->W = W;
     return true;
 }

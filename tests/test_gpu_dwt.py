@@ -91,3 +91,52 @@ def test_dwt_nan_stays_in_its_pixel():
     got = _gpu_dwt(cube, 4)
     bad = ~np.isfinite(got).all(axis=2)
     assert bad[3, 4] and bad.sum() == 1
+
+
+@pytest.mark.parametrize("L,levels", [(277, 6), (313, 3)])
+def test_graph_capture_on_unseen_shape(L, levels):
+    """hsad_dwt + hsad_detect captured in a graph on an (L, J) pair the process has not seen
+    (the composite (L' <= 16) and banded (L' > 16) tables): no synchronisation inside the
+    capture, and every replay, with eager work in between, equals the eager result bitwise."""
+    import torch
+    import paper_1201_2025_amd as hs
+    H, W = 48, 40
+    rng = np.random.default_rng(L)
+    cube = torch.from_numpy((rng.random((H, W, L)) + 0.05 * rng.standard_normal((H, W, L))).astype(np.float32)).cuda()
+    warm = torch.rand((4, 4, 64), device="cuda")
+    hs.hsad_dwt(warm, 2)                       # some other shape first: the pinned mirror exists
+    Lp = hs.hsad_dwt_out_len(L, levels)
+    approx = torch.empty((H, W, Lp), dtype=torch.float32, device="cuda")
+    lrx = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    dwrx = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    mask = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    stats = torch.empty(4, dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(1, hs.hsad_detect_workspace_bytes(H, W, Lp, 3, 9)), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hs.hsad_dwt(cube, levels, out=approx)
+            hs.hsad_detect(approx, 3, 9, lrx=lrx, dwrx=dwrx, stats=stats, mask=mask, ws=ws)
+    torch.cuda.synchronize()
+    # eager reference (the table is uploaded outside the capture now)
+    ea = hs.hsad_dwt(cube, levels)
+    el, ed, est, em = hs.hsad_detect(ea, 3, 9)
+    torch.cuda.synchronize()
+    ref = [t.cpu().numpy() for t in (ea, el, ed, est, em)]
+    for rep in range(3):
+        for t in (approx, lrx, dwrx, stats):
+            t.fill_(float("nan"))
+        mask.fill_(7)
+        g.replay()
+        torch.cuda.synchronize()
+        got = [t.cpu().numpy() for t in (approx, lrx, dwrx, stats, mask)]
+        for a, b in zip(got, ref):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), rep
+        hs.hsad_dwt(warm, 2)                   # eager work between the replays
+        torch.cuda.synchronize()
+    # and the transform itself against the oracle
+    import oracle
+    r = oracle.dwt_approx(cube.cpu().numpy(), levels)
+    assert dwt_rel_err(ref[0], r) <= 1e-5
