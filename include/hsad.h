@@ -341,9 +341,10 @@ int hsad_batch_plan_destroy(hsad_batch_plan *plan);
  * and one timed run each, and stores the fastest in *best.  The candidates cover
  * persistent workgroups per CU {1,2,4}, DWT item size {max, 8} and Gram chunk bytes
  * {1 GiB, 4 GiB}; those whose workspace exceeds ws_bytes are skipped.  If cache_path
- * is not NULL, the result is cached there as JSON keyed by GPU architecture and batch
- * signature, and a cached entry is returned without timing (*best_ms = -1).  ws is
- * overwritten.  Synchronises `stream`.
+ * is not NULL, the result is cached there as JSON keyed by GPU architecture, the library
+ * build (a hash of its sources) and the batch signature (shapes, levels, windows), and a
+ * cached entry whose plan fits ws_bytes is returned without timing (*best_ms = -1); one
+ * that does not fit is tuned again.  ws is overwritten.  Synchronises `stream`.
  * Errors: HSAD_EINVAL, HSAD_ENOMEM (no candidate fits), HSAD_EHIP. */
 int hsad_batch_autotune(const hsad_scene *scenes, int n, void *ws, size_t ws_bytes,
                         hipStream_t stream, const char *cache_path, hsad_batch_options *best,

@@ -732,7 +732,11 @@ static std::string batch_signature(const hsad_scene *sc, int n)
         arch = p.gcnArchName;
     char buf[64];
     std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
-    return arch.substr(0, arch.find(':')) + "/" + std::to_string(n) + "/" + buf;
+    // the library build (a hash of its sources): schedules tuned for other kernels are not reused
+#ifndef HSAD_BUILD_ID
+#define HSAD_BUILD_ID "unknown"
+#endif
+    return arch.substr(0, arch.find(':')) + "/" + HSAD_BUILD_ID + "/" + std::to_string(n) + "/" + buf;
 }
 
 static bool cache_lookup(const char *path, const std::string &key, hsad_batch_options *o)
@@ -795,9 +799,18 @@ extern "C" int hsad_batch_autotune(const hsad_scene *scenes, int n, void *ws, si
     if (!scenes || n < 1 || !ws || !best) return fail(HSAD_EINVAL, "hsad_batch_autotune: bad arguments");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const std::string key = batch_signature(scenes, n);
-    if (cache_lookup(cache_path, key, best)) {
-        if (best_ms) *best_ms = -1.0;
-        return HSAD_OK;
+    hsad_batch_options cached;
+    if (cache_lookup(cache_path, key, &cached)) {
+        // a cached schedule is used only if its plan fits the caller's workspace
+        hsad_batch_plan *P = nullptr;
+        const bool fits = hsad_batch_plan_create(scenes, n, &cached, &P) == HSAD_OK && P->total <= ws_bytes;
+        if (P) hsad_batch_plan_destroy(P);
+        clear_error();
+        if (fits) {
+            *best = cached;
+            if (best_ms) *best_ms = -1.0;
+            return HSAD_OK;
+        }
     }
     const int wgs[] = {1, 2, 4};
     const int dps[] = {0, 8};

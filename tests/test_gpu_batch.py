@@ -93,3 +93,104 @@ def test_batch_rejects_bad_scenes():
         hs.BatchPlan([dict(cube=c, levels=2, inner=4, outer=9)])
     with pytest.raises(hs.HsadError):      # L' = 150 > 128
         hs.BatchPlan([dict(cube=torch.zeros((8, 8, 300), device="cuda"), levels=1, inner=3, outer=9)])
+
+
+def test_autotune_cache_roundtrip_and_plans_agree(tmp_path):
+    """The tuner's cache: a second call returns the stored schedule without timing; a cached
+    schedule that does not fit a smaller workspace is tuned again; and a batch run with the
+    tuned schedule gives the same maps, bit for bit, as the default schedule."""
+    import torch
+    specs = _specs()
+    scs = []
+    for sp in specs:
+        s = scene(sp["seed"], sp["H"], sp["W"], sp["L"])
+        scs.append(dict(cube=torch.from_numpy(s.cube).cuda(), levels=sp["levels"], inner=sp["inner"],
+                        outer=sp["outer"], load_rel=1e-6))
+    path = str(tmp_path / "tune.json")
+    base = hs.BatchPlan(scs)
+    need = base.ws.numel()
+    ws = torch.empty(need + (64 << 20), dtype=torch.uint8, device="cuda")
+    best, ms = hs.hsad_batch_autotune(scs, ws, path)
+    assert ms > 0
+    again, ms2 = hs.hsad_batch_autotune(scs, ws, path)
+    assert ms2 == -1.0
+    assert (again.wgs_per_cu, again.dwt_pixels, again.chunk_bytes) == (best.wgs_per_cu, best.dwt_pixels,
+                                                                      best.chunk_bytes)
+    import json
+    d = json.load(open(path))
+    assert len(d) == 1 and list(d.values())[0][:3] == [best.wgs_per_cu, best.dwt_pixels, best.chunk_bytes]
+    # the default plan and the tuned plan compute the same maps
+    base.run()
+    tuned = hs.BatchPlan(scs, best)
+    tuned.run()
+    torch.cuda.synchronize()
+    for a, b in zip(base.lrx + base.dwrx, tuned.lrx + tuned.dwrx):
+        assert torch.equal(a, b)
+    # a workspace too small for the cached schedule: tuned again among those that fit
+    small = torch.empty(need, dtype=torch.uint8, device="cuda")
+    third, ms3 = hs.hsad_batch_autotune(scs, small, path)
+    chk = hs.BatchPlan(scs, third)
+    assert chk.ws.numel() <= need
+    assert ms3 > 0 or (third.chunk_bytes == best.chunk_bytes and third.wgs_per_cu == best.wgs_per_cu)
+    for p in (base, tuned, chk):
+        p.close()
+
+
+def test_full_benchmark_batch_sampled():
+    """The 64-scene benchmark batch (H, W in [128, 1024], L in [100, 430], J = 2..5, outer
+    9..21, inner 3..7, 21 M pixels) at full size: every scene's DWT at 64 sampled pixels
+    against the oracle's DWT of the same spectra, LRX and DWRX at those pixels against the
+    oracle on the batch's own reduced cube (the window patch around each pixel), and each
+    scene's maps against the single-scene calls (hsad_dwt + hsad_lrx_dwrx) with their ROC
+    AUCs (truth masks of the generator)."""
+    import torch
+    from paper_1201_2025_amd import synth
+    from gpu_util import dwt_rel_err
+    specs = synth.batch_scene_specs(seed=1204, n=64)
+    scs, truths = [], []
+    for sp in specs:
+        cube, truth, _ = synth.make_scene_torch(sp["seed"], sp["H"], sp["W"], sp["L"], K=sp["K"],
+                                                n_single=sp["n_single"], n_blob=sp["n_blob"], device="cuda")
+        scs.append(dict(cube=cube, levels=sp["levels"], inner=sp["inner"], outer=sp["outer"],
+                        load_rel=sp["load_rel"]))
+        truths.append(truth)
+    plan = hs.BatchPlan(scs)
+    plan.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(64)
+    worst = {"dwt": 0.0, "lrx": 0.0, "dwrx": 0.0, "single": 0.0, "dauc": 0.0}
+    for i, (sp, sc) in enumerate(zip(specs, scs)):
+        H, W, L = sp["H"], sp["W"], sp["L"]
+        R = sp["outer"] // 2
+        idx = rng.choice(H * W, 64, replace=False)
+        cube_rows = sc["cube"].view(H * W, L)[torch.from_numpy(idx).cuda()].cpu().numpy()
+        a = plan.approx[i]
+        Lp = a.shape[-1]
+        ga = a.view(H * W, Lp)[torch.from_numpy(idx).cuda()].cpu().numpy()
+        e_dwt = dwt_rel_err(ga, oracle.dwt_approx(cube_rows, sp["levels"]))
+        gl = plan.lrx[i].view(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+        gd = plan.dwrx[i].view(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+        rl, rd = np.empty(len(idx)), np.empty(len(idx))
+        for j, p in enumerate(idx):
+            y, x = divmod(int(p), W)
+            y0, y1, x0, x1 = max(0, y - R), min(H, y + R + 1), max(0, x - R), min(W, x + R + 1)
+            patch = a[y0:y1, x0:x1].cpu().numpy().astype(np.float64)
+            li = (y - y0) * (x1 - x0) + (x - x0)
+            l_, d_ = oracle.lrx_dwrx(patch, sp["inner"], sp["outer"], sp["load_rel"], idx=np.array([li]))
+            rl[j], rd[j] = l_[0], d_[0]
+        e_l, e_d = score_rel_err(gl, rl).max(), score_rel_err(gd, rd).max()
+        # the single-scene path on the same cube
+        sa = hs.hsad_dwt(sc["cube"], sp["levels"])
+        sl, sd = hs.hsad_lrx_dwrx(sa, sp["inner"], sp["outer"], sp["load_rel"])
+        torch.cuda.synchronize()
+        e_s = max(score_rel_err(plan.lrx[i].cpu().numpy().ravel(), sl.cpu().numpy().ravel()).max(),
+                  score_rel_err(plan.dwrx[i].cpu().numpy().ravel(), sd.cpu().numpy().ravel()).max())
+        tt = torch.from_numpy(truths[i].ravel()).cuda()
+        dauc = abs(hs.auc_from_counts(hs.hsad_auc(plan.lrx[i].view(-1), tt)) -
+                   hs.auc_from_counts(hs.hsad_auc(sl.view(-1), tt)))
+        for k, v in (("dwt", e_dwt), ("lrx", e_l), ("dwrx", e_d), ("single", e_s), ("dauc", dauc)):
+            worst[k] = max(worst[k], float(v))
+        assert e_dwt <= 1e-5 and e_l <= 1e-3 and e_d <= 1e-3 and e_s <= 1e-3 and dauc <= 2e-3, (i, sp)
+        del sa, sl, sd
+    print("full batch worst:", worst, flush=True)
+    plan.close()
