@@ -66,6 +66,9 @@ def parse():
                     help="skip the reduced-precision, global RX, full DWT, Table 1 sweep and error sections")
     ap.add_argument("--oracle-protocol", action="store_true",
                     help="also time the FP64 oracle, 1 thread and all threads, on every configuration (minutes)")
+    ap.add_argument("--profile-workload", type=str, default=None,
+                    help="run one named workload 3 times (after one warm-up) for a profiler and exit: "
+                         "fullband, lp56, lp56_bf16, lp4, dwest14, dwest56, grx4, grx224, wavelet")
     ap.add_argument("--profile", action="store_true",
                     help="timed steps only, then 3 plain 256 MiB device copies (counter calibration)")
     return ap.parse_args()
@@ -585,6 +588,36 @@ def oracle_protocol(log):
     return res
 
 
+def profile_workload(name, dev):
+    """One named workload on the 512 x 512 x 224 cube, for rocprofv3 kernel traces and counters."""
+    import torch
+    import paper_1201_2025_amd as hs
+    from paper_1201_2025_amd import synth
+    c = synth.CONFIGS["cube_512x512x224"]
+    s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"], n_blob=c["n_blob"])
+    cube = torch.from_numpy(s.cube).to(dev)
+    H, W = c["H"], c["W"]
+    works = {
+        "fullband": (0, lambda x: hs.hsad_lrx_dwrx(x, 5, 15, 1e-6)),
+        "lp56": (2, lambda x: hs.hsad_lrx_dwrx(x, 5, 15, 1e-6)),
+        "lp56_bf16": (2, lambda x: hs.hsad_lrx_dwrx(x, 5, 15, 1e-6, hs.HSAD_PREC_GRAM_BF16)),
+        "lp4": (6, lambda x: hs.hsad_detect(x, 5, 15, 1e-6, 3.0)),
+        "dwest14": (4, lambda x: hs.hsad_dwest(x, 3, 11)),
+        "dwest56": (2, lambda x: hs.hsad_dwest(x, 3, 11)),
+        "grx4": (6, lambda x: hs.hsad_global_rx(x, 1e-6)),
+        "grx224": (0, lambda x: hs.hsad_global_rx(x, 1e-6)),
+        "wavelet": (None, lambda x: hs.hsad_idwt_full(hs.hsad_dwt_full(x, 3, 4), 224, 3, 4)),
+    }
+    if name not in works:
+        raise SystemExit("unknown workload %r (one of %s)" % (name, ", ".join(works)))
+    lv, fn = works[name]
+    x = cube if not lv else hs.hsad_dwt(cube, lv)
+    for i in range(4):
+        fn(x)
+        torch.cuda.synchronize()
+        print("profile workload %s: run %d done" % (name, i), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -599,6 +632,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.profile_workload:
+        profile_workload(args.profile_workload, dev)
+        return
     c = synth.CONFIGS["cube_512x512x224"]
     H, W, L = c["H"], c["W"], c["L"]
     J = hs.hsad_levels_for(L, 4) if args.level is None else args.level
