@@ -155,6 +155,8 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_dwest_solver", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwest_stats", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_chol_cb", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_gram_wg", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    ("hsad_internal_chol_blk", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_boxg_rb", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_variant", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     ("hsad_internal_generic_force", ctypes.c_int, [ctypes.c_int]),

@@ -8,11 +8,14 @@
 // row below the diagonal, so they end as (L^-1 d)^T and the scores are their squared
 // norms.  No separate triangular solve is needed.
 //
-// One workgroup per pixel.  Columns are processed in panels of NB = 32.  A panel
-// (all rows from the panel down) is factored in LDS, written back, and applied to the
-// trailing lower trapezoid with 4 x 4 register blocks per thread.  The trailing part
-// stays in the workspace, which is L2-resident for a chunk.  With L' <= 32 this is a
-// single panel and the whole factorisation runs in LDS.
+// L' > 64 (chol_blk_kernel): one workgroup per pixel, columns in panels of NB = 32.  The
+// panel's diagonal block is factored and inverted by one wavefront, the rows below are
+// solved as a product with that inverse, and the trailing lower trapezoid is updated in
+// place; both products run on the FP64 matrix cores (dev_chol.hpp, chol_pixel_blk).
+// chol_rx_kernel keeps the earlier form (panel factored with one workgroup barrier per
+// column, trailing update in 4 x 4 register blocks); with L' <= 32 it is a single panel in
+// LDS.  Smaller L' use one wavefront per pixel (L' <= 64) or a lane group per pixel
+// (L' + 2 <= 64), below.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -34,6 +37,22 @@ __global__ __launch_bounds__(256) void chol_rx_kernel(double *__restrict__ ws, i
     if (p < 0 || p >= npix_img) return;   // listed index outside the image: skipped
     chol_pixel(ws + (size_t)local * stride, Lp, load_rel, lrx ? lrx + p : nullptr, dwrx ? dwrx + p : nullptr, sm,
                raw);
+}
+
+// L' > 64: chol_pixel_blk (diagonal blocks by one wavefront, row solves in registers,
+// trailing updates on the FP64 matrix cores)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void chol_blk_kernel(double *__restrict__ ws, int Lp, int npix, int64_t pix0,
+                                                       double load_rel, float *__restrict__ lrx,
+                                                       float *__restrict__ dwrx, const int32_t *__restrict__ idx,
+                                                       int64_t npix_img, int raw, int64_t stride)
+{
+    extern __shared__ double sm[];
+    const int local = blockIdx.x;
+    if (local >= npix) return;
+    const int64_t p = idx ? (int64_t)idx[pix0 + local] : pix0 + local;
+    if (p < 0 || p >= npix_img) return;   // listed index outside the image: skipped
+    chol_pixel_blk(ws + (size_t)local * stride, Lp, load_rel, lrx ? lrx + p : nullptr, dwrx ? dwrx + p : nullptr,
+                   sm, raw);
 }
 
 // one wavefront per pixel (L' <= 64), four pixels per workgroup
@@ -76,6 +95,8 @@ size_t chol_smem(int64_t Lp) { return chol_smem_doubles((int)Lp) * sizeof(double
 
 // columns per unrolled block of the register-resident factorisation (64: fully unrolled)
 static int g_chol_cb = 16;
+// L' > 64: blocked factorisation with matrix-core trailing updates (0: chol_pixel)
+static int g_chol_blk = 1;
 
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
                 float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img, int raw)
@@ -110,12 +131,25 @@ int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel,
     const size_t sh = chol_smem(Lp);
     const int nt = Lp <= 32 ? 64 : 256;
     if (int rc = allow_lds((const void *)chol_rx_kernel, sh, "chol_rx_kernel")) return rc;
+    if (g_chol_blk && Lp > 64) {
+        const size_t shb = chol_blk_smem_doubles((int)Lp) * sizeof(double);
+        if (int rc = allow_lds((const void *)chol_blk_kernel, shb, "chol_blk_kernel")) return rc;
+        hipLaunchKernelGGL(chol_blk_kernel, dim3((unsigned)npix), dim3(256), shb, s, ws, (int)Lp, npix, pix0, load_rel,
+                           lrx, dwrx, idx, npix_img, raw, stride);
+        return check_launch("chol_blk_kernel");
+    }
     hipLaunchKernelGGL(chol_rx_kernel, dim3((unsigned)npix), dim3(nt), sh, s, ws, (int)Lp, npix,
                        pix0, load_rel, lrx, dwrx, idx, npix_img, raw, stride);
     return check_launch("chol_rx_kernel");
 }
 
 }  // namespace hsad
+
+extern "C" int hsad_internal_chol_blk(int on)
+{
+    hsad::g_chol_blk = on != 0;
+    return 0;
+}
 
 extern "C" int hsad_internal_chol_cb(int cb)
 {

@@ -146,8 +146,8 @@ __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_re
     __syncthreads();
 }
 
-
 __host__ __device__ inline size_t chol_smem_doubles(int Lp) { return (size_t)(Lp + 2) * (NB + 1) + 8 + NB; }
+__host__ __device__ inline size_t chol_blk_smem_doubles(int Lp) { return chol_smem_doubles(Lp) + (size_t)NB * (NB + 1); }
 
 }  // namespace hsad
 
@@ -171,6 +171,222 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// value of v in lane l (l wave-uniform), as an FP64 scalar
+__device__ __forceinline__ double lane_read_d(double v, int l)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Blocked variant of chol_pixel for L' > 64 (same arguments, definitions and outputs;
+// sm holds chol_blk_smem_doubles(L') doubles): per panel of NB columns, one wavefront
+// factors the NB x NB diagonal block and inverts its triangle in registers; the rows below are solved against it as one product with
+// that inverse, and the trailing lower trapezoid takes the rank-NB update, both on the FP64
+// matrix cores in 16 x 16 tiles, the trailing tiles read and written in place (coalesced
+// rows of 16 doubles).  The two extra rows are ordinary rows of this elimination; their
+// squared norms are summed panel by panel from LDS, so nothing is written back but the
+// trailing part.  Four workgroup barriers per panel.
+__device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double load_rel,
+                                      float *lrx_out, float *dwrx_out, double *sm, int raw = 0)
+{
+    constexpr int LD = NB + 1;
+    const int rows = Lp + 2;
+    double *P = sm;                            // panel: rows x NB (row stride LD)
+    double *red = sm + (size_t)rows * LD;
+    double &bad = red[6];
+    double *Wm = red + 8 + NB;                 // inverse of the diagonal block, NB x NB (stride LD)
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const int c16 = lane & 15, g4 = lane >> 4;
+    if (raw) {
+        const double *mu = A + (size_t)(Lp + 2) * Lp;
+        for (int t = tid; t < Lp * Lp; t += nt) {
+            const int i = t / Lp, j = t - i * Lp;
+            if (j >= i) A[(size_t)j * Lp + i] = A[(size_t)i * Lp + j] - mu[i] * mu[j];
+        }
+        __syncthreads();
+    }
+    double tr = 0.0;
+    for (int i = tid; i < Lp; i += nt) tr += A[(size_t)i * Lp + i];
+    tr = block_sum(tr, red);
+    double lam = load_rel * tr / (double)Lp;
+    lam = lam < 1e-30 ? 1e-30 : lam;
+    if (tid == 0) bad = 0.0;
+    for (int i = tid; i < Lp; i += nt) A[(size_t)i * Lp + i] += lam;
+    __syncthreads();
+
+    double s1 = 0.0, s2 = 0.0;   // partial squared norms of the extra rows (threads < NB)
+    for (int kb = 0; kb < Lp; kb += NB) {
+        const int nb = Lp - kb < NB ? Lp - kb : NB;
+        const int prow = rows - kb;
+        for (int t = tid; t < prow * nb; t += nt) {
+            const int r = t / nb, c = t - r * nb;
+            P[(size_t)r * LD + c] = A[(size_t)(kb + r) * Lp + kb + c];
+        }
+        __syncthreads();
+        // diagonal block: Cholesky factor L_kk and its inverse W = L_kk^-1 in one pass by
+        // one wavefront, lane i (mod 32) holding row i of the block and row i of W (identity to
+        // start) in registers.  Step j: l_jj = sqrt(a_jj), l_ij = a_ij / l_jj; row j of W is
+        // final once divided by l_jj; rows i > j then take a_ic -= l_ij l_cj (c > j) and
+        // W_ic -= l_ij W_jc (c <= j).  Every broadcast is a lane read of a compile-time
+        // register, so the step has no LDS round trip.
+        if (wv == (kb / NB) % nw) {   // rotates over the SIMDs from panel to panel
+            const int i = lane & 31;
+            double a[NB], w[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                a[c] = P[i * LD + c];
+                w[c] = c == i ? 1.0 : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if (j < nb) {
+                    const double d = lane_read_d(a[j], j);
+                    const double sq = sqrt(d), iv = 1.0 / sq;
+                    if (lane == 0 && !(d > 0.0)) bad = 1.0;
+                    const double lij = i == j ? sq : a[j] * iv;
+                    a[j] = lij;
+                    const double ws = i == j ? iv : 1.0, lw = i > j ? lij : 0.0;
+#pragma unroll
+                    for (int c = 0; c <= j; ++c) w[c] *= ws;
+                    // rows i <= j only change entries above their diagonal, which are not used
+#pragma unroll
+                    for (int c = j + 1; c < NB; ++c) {
+                        a[c] = fma(-lij, lane_read_d(a[j], c), a[c]);
+                        // few lane reads in flight: each holds two scalar registers
+                        if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int c = 0; c <= j; ++c) {
+                        w[c] = fma(-lw, lane_read_d(w[c], j), w[c]);
+                        if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            if (lane < 32) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    const bool in = i < nb && c <= i;
+                    if (in) P[i * LD + c] = a[c];
+                    Wm[i * LD + c] = in ? w[c] : 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        // rows below the block: X = A_below L_kk^-T = A_below W^T with W = L_kk^-1 (computed
+        // above), 16 rows x 32 columns per wavefront on the matrix cores.
+        // Columns >= nb (last panel) are zero on both operands and never stored.
+        {
+            const int nrb = (prow - nb + 15) >> 4;
+            const int nk = (nb + 3) >> 2;
+            for (int rb = wv; rb < nrb; rb += nw) {
+                f64x4 x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
+                const int ra = nb + 16 * rb + c16;
+                for (int kk = 0; kk < nk; ++kk) {
+                    const int col = 4 * kk + g4;
+                    const double av = ra < prow && col < nb ? P[(size_t)ra * LD + col] : 0.0;
+                    x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Wm[c16 * LD + col], x0, 0, 0, 0);
+                    x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Wm[(16 + c16) * LD + col], x1, 0, 0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = nb + 16 * rb + 4 * e + g4;
+                    if (r < prow) {
+                        if (c16 < nb) P[(size_t)r * LD + c16] = x0[e];
+                        if (16 + c16 < nb) P[(size_t)r * LD + 16 + c16] = x1[e];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < nb) {
+            const double u = P[(size_t)(prow - 2) * LD + tid], v = P[(size_t)(prow - 1) * LD + tid];
+            s1 += u * u;
+            s2 += v * v;
+        }
+        // trailing update A[i][k] -= sum_j L[i][j] L[k][j], k0 <= k <= i, on 16 x 16 tiles
+        const int k0 = kb + nb;
+        if (k0 < Lp) {
+            const int nr = rows - k0, ncl = Lp - k0;
+            const int TI = (nr + 15) >> 4, TJ = (ncl + 15) >> 4;
+            const int ntri = TJ * (TJ + 1) / 2, ntile = ntri + (TI - TJ) * TJ;
+            const int nk = (nb + 3) >> 2;
+            // tile t -> (I, J): row-major over the triangle J <= I < TJ, then full rows of TJ
+            auto tile_of = [&](int t, int &I, int &J) {
+                if (t < ntri) {
+                    I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+                    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+                    while (I * (I + 1) / 2 > t) --I;
+                    J = t - I * (I + 1) / 2;
+                } else {
+                    const int u = t - ntri;
+                    I = TJ + u / TJ;
+                    J = u - (I - TJ) * TJ;
+                }
+            };
+            // TB tiles per wavefront and step; the next step's tiles are loaded before this
+            // step's products are issued
+            constexpr int TB = 2;
+            auto load_tiles = [&](int t0, f64x4 *acc, int *tij) {
+#pragma unroll
+                for (int q = 0; q < TB; ++q) {
+                    int I, J;
+                    tile_of(t0 + q < ntile ? t0 + q : ntile - 1, I, J);
+                    tij[q] = 16 * I | (16 * J) << 16;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = k0 + 16 * I + 4 * e + g4, c = k0 + 16 * J + c16;
+                        acc[q][e] = r < rows && c < Lp ? A[(size_t)r * Lp + c] : 0.0;
+                    }
+                }
+            };
+            f64x4 acc[TB], nacc[TB];
+            int tij[TB], nij[TB];
+            if (TB * wv < ntile) load_tiles(TB * wv, acc, tij);
+            for (int t0 = TB * wv; t0 < ntile; t0 += TB * nw) {
+                const int t1 = t0 + TB * nw;
+                if (t1 < ntile) load_tiles(t1, nacc, nij);
+                for (int kk = 0; kk < nk; ++kk) {
+                    const int col = 4 * kk + g4;
+#pragma unroll
+                    for (int q = 0; q < TB; ++q) {
+                        const int ra = nb + (tij[q] & 0xffff) + c16, rb = nb + (tij[q] >> 16) + c16;
+                        const double av = ra < prow && col < nb ? -P[(size_t)ra * LD + col] : 0.0;
+                        const double bv = rb < prow && col < nb ? P[(size_t)rb * LD + col] : 0.0;
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < TB; ++q) {
+                    if (t0 + q < ntile) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            // FP64 16x16x4: element e of lane l is row 4e + (l >> 4), column l & 15
+                            const int r = k0 + (tij[q] & 0xffff) + 4 * e + g4, c = k0 + (tij[q] >> 16) + c16;
+                            if (r < rows && c < Lp && c <= r) A[(size_t)r * Lp + c] = acc[q][e];
+                        }
+                    }
+                    acc[q] = nacc[q];
+                    tij[q] = nij[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (tid == 0) {
+        if (lrx_out) *lrx_out = bad != 0.0 ? INFINITY : (float)s1;
+        if (dwrx_out) *dwrx_out = bad != 0.0 ? INFINITY : (float)s2;
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ double wave_sum_d(double v)

@@ -26,6 +26,11 @@
 
 namespace hsad {
 
+// smallest tile count T = ceil(L'/16) that takes the workgroup-per-pixel FP64 Gram, and its
+// most accumulator tiles per wavefront and pass (tests choose through hsad_internal_gram_wg)
+static int g_gram_wg_min_t = 6;
+static int g_gram_wg_tiles = 17;
+
 template <int PREC, int kMaxTilesPerPass>
 __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_block)
 {
@@ -34,6 +39,219 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_blo
     const int local = blockIdx.x * waves_per_block + wv;
     if (local >= a.npix) return;
     gram_pixel<PREC, kMaxTilesPerPass>(a, local, lds + wv * gram_wave_doubles(a.Lp, PREC));
+}
+
+// ------------------------------------------------------------------------------------
+// Workgroup per pixel (FP64, LRX mode, 81 <= L' <= 256).  A pixel's annulus Gram has
+// T(T+1)/2 tiles of 16 x 16 (105 at L' = 224), more than one wavefront can keep in
+// registers, so the per-wavefront kernel above re-reads every window sample once per pass
+// of 16 tiles.  Here the four wavefronts of a workgroup share each group of 4 centred
+// samples through LDS (staged once per group for all bands) and split the tiles, MT
+// accumulators per wavefront and pass.  Each group's samples are fetched into registers
+// two groups ahead of use (two LDS buffers, one barrier per group).  Definitions as in
+// gram_pixel: FP64 means first (all threads, band-parallel partial sums), then the Gram
+// of the exactly centred annulus samples, scaled by 1/n_a.
+// The tiles are written through an LDS transpose so that both triangles are stored in
+// rows of 16 consecutive doubles.
+// LDS: mu, m_in [256] doubles; two staging buffers [4][256] doubles (also the partial
+// sums of the means and the transposes); sample table [4 ceil(K/4)] ints (annulus:
+// pixel index, inner window: -2 - pixel index, outside the image or past K: -1).
+// ------------------------------------------------------------------------------------
+static constexpr int kWgMaxLpad = 256;
+
+__host__ __device__ inline size_t gram_wg_lds_bytes(int K)
+{
+    return (size_t)(2 + 8) * kWgMaxLpad * sizeof(double) + (size_t)4 * ((K + 3) / 4) * sizeof(int);
+}
+
+template <int MT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void gram_wg_kernel(GramArgs a)
+{
+    extern __shared__ double sm[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int Lp = a.Lp, T = (Lp + 15) >> 4, Lpad = 16 * T;
+    double *mu = sm, *mi = sm + kWgMaxLpad, *buf = sm + 2 * kWgMaxLpad;
+    const int local = blockIdx.x;
+    if (local >= a.npix) return;
+    const int64_t pix = a.idx ? (int64_t)a.idx[a.pix0 + local] : a.pix0 + local;
+    if (pix < 0 || pix >= (int64_t)a.H * a.W) return;   // uniform over the workgroup
+    const int py = (int)(pix / a.W), px = (int)(pix - (int64_t)py * a.W);
+    const int K = (2 * a.R + 1) * (2 * a.R + 1);
+    const int ng = (K + 3) / 4;
+    const int n_o = clipn(py, a.R, a.H) * clipn(px, a.R, a.W);
+    const int n_i = a.has_inner ? clipn(py, a.RI, a.H) * clipn(px, a.RI, a.W) : 0;
+    const int n_a = n_o - n_i;
+    int *sof = reinterpret_cast<int *>(sm + 10 * kWgMaxLpad);
+    for (int k = tid; k < 4 * ng; k += 256) {
+        int v = -1;
+        if (k < K) {
+            int sy, sx;
+            bool inn;
+            if (sample_pos(a, py, px, k, sy, sx, inn)) {
+                const int q = sy * a.W + sx;
+                v = inn ? -2 - q : q;
+            }
+        }
+        sof[k] = v;
+    }
+    // the thread's staged elements e = tid + 256 i: sample e / Lpad of the group, band e % Lpad
+    constexpr int NE = 4 * kWgMaxLpad / 256;
+    const int nel = 4 * Lpad;
+    int es[NE], eb[NE];
+    bool ev[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int e = tid + 256 * i;
+        es[i] = e < nel ? e / Lpad : 0;
+        eb[i] = e < nel ? e - es[i] * Lpad : 0;
+        ev[i] = e < nel && eb[i] < Lp;
+        if (eb[i] >= Lp) eb[i] = Lp - 1;   // clamped band: loads stay in the row, value dropped
+    }
+    __syncthreads();
+
+    // pass 1: FP64 sums over the annulus and the inner window
+    {
+        double sa[NE], si[NE];
+#pragma unroll
+        for (int i = 0; i < NE; ++i) sa[i] = si[i] = 0.0;
+#pragma unroll 8
+        for (int g = 0; g < ng; ++g) {
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int o = sof[4 * g + es[i]];
+                const int q = o >= 0 ? o : o <= -2 ? -2 - o : 0;
+                const double v = (double)a.x[(size_t)q * Lp + eb[i]];
+                sa[i] += ev[i] && o >= 0 ? v : 0.0;
+                si[i] += ev[i] && o <= -2 ? v : 0.0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+            const int e = tid + 256 * i;
+            if (e < nel) {
+                buf[e] = sa[i];
+                buf[4 * kWgMaxLpad + e] = si[i];
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < Lpad; b += 256) {
+        const double sa = (buf[b] + buf[Lpad + b]) + (buf[2 * Lpad + b] + buf[3 * Lpad + b]);
+        const double *bi = buf + 4 * kWgMaxLpad;
+        const double si = (bi[b] + bi[Lpad + b]) + (bi[2 * Lpad + b] + bi[3 * Lpad + b]);
+        mu[b] = b < Lp ? sa / (double)n_a : 0.0;
+        mi[b] = (b < Lp && n_i > 0) ? si / (double)n_i : 0.0;
+    }
+    __syncthreads();
+    double *out = a.ws + (size_t)local * (Lp + 2) * Lp;
+    for (int b = tid; b < Lp; b += 256) {
+        out[(size_t)Lp * Lp + b] = (double)a.x[(size_t)pix * Lp + b] - mu[b];
+        out[(size_t)(Lp + 1) * Lp + b] = mi[b] - mu[b];
+    }
+    double emu[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) emu[i] = mu[eb[i]];
+
+    // pass 2: the Gram, MT tiles per wavefront per pass (tile t = wv + 4 m, row-major over
+    // the upper triangle bi <= bj)
+    const int ntiles = T * (T + 1) / 2;
+    const int nper = (ntiles + 3) / 4;
+    const int c16 = lane & 15, g4 = lane >> 4;
+    const double scale = 1.0 / (double)n_a;
+    double *tw = buf + wv * (16 * 17);   // this wavefront's transpose tile (after the loop)
+    for (int m0 = 0; m0 < nper; m0 += MT) {
+        int tb[MT];   // 16 bi | (16 bj) << 16, wave-uniform
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            int t = wv + 4 * (m0 + m), bi = 0;
+            t = t < ntiles ? t : 0;
+            while (t >= T - bi) {
+                t -= T - bi;
+                ++bi;
+            }
+            tb[m] = 16 * bi | (16 * (bi + t)) << 16;
+        }
+        f64x4 acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            for (int e = 0; e < 4; ++e) acc[m][e] = 0.0;
+        // group g's samples: fetched into registers two groups before they are staged, so
+        // each load has two groups of matrix-core work to arrive
+        float xa[NE], xb[NE];
+        bool ka[NE], kb[NE];
+        auto fetch = [&](int g, float *xv, bool *xok) {
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int o = sof[4 * g + es[i]];
+                xv[i] = a.x[(size_t)(o >= 0 ? o : 0) * Lp + eb[i]];
+                xok[i] = ev[i] && o >= 0;
+            }
+        };
+        auto stage = [&](double *dst, const float *xv, const bool *xok) {
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int e = tid + 256 * i;
+                if (e < nel) dst[e] = xok[i] ? (double)xv[i] - emu[i] : 0.0;
+            }
+        };
+        auto mfma_group = [&](const double *b) {
+            const double *cur = b + g4 * Lpad + c16;
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                if (m0 + m < nper && wv + 4 * (m0 + m) < ntiles)
+                    acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[tb[m] & 0xffff], cur[tb[m] >> 16], acc[m], 0,
+                                                                  0, 0);
+        };
+        double *buf0 = buf, *buf1 = buf + 4 * kWgMaxLpad;
+        fetch(0, xa, ka);
+        __syncthreads();   // readers of the buffers (means, previous pass) are done
+        stage(buf0, xa, ka);
+        if (1 < ng) fetch(1, xb, kb);
+        if (2 < ng) fetch(2, xa, ka);
+        __syncthreads();
+        // even steps: group g in buf0, group g+1 (xb) staged to buf1, group g+3 fetched to
+        // xb; odd steps mirror with buf1 / xa
+        for (int g = 0; g < ng; g += 2) {
+            mfma_group(buf0);
+            if (g + 1 < ng) stage(buf1, xb, kb);
+            if (g + 3 < ng) fetch(g + 3, xb, kb);
+            __syncthreads();
+            if (g + 1 >= ng) break;
+            mfma_group(buf1);
+            if (g + 2 < ng) stage(buf0, xa, ka);
+            if (g + 4 < ng) fetch(g + 4, xa, ka);
+            __syncthreads();
+        }
+        // write the tiles: the upper triangle straight from the accumulators, the lower
+        // through the transpose (diagonal tiles: one value per symmetric pair)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (!(m0 + m < nper && wv + 4 * (m0 + m) < ntiles)) continue;
+            const int r0 = tb[m] & 0xffff, c0 = tb[m] >> 16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // FP64 16x16x4: element e of lane l sits at row 4e + (l >> 4), column l & 15
+                const int rl = 4 * e + g4;
+                const double v = acc[m][e] * scale;
+                tw[rl * 17 + c16] = v;
+                if (r0 + rl < Lp && c0 + c16 < Lp && (r0 < c0 || rl <= c16))
+                    out[(size_t)(r0 + rl) * Lp + c0 + c16] = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // row c0 + jl of the lower triangle, column r0 + c16
+                const int jl = 4 * e + g4;
+                const double v = tw[c16 * 17 + jl];
+                if (c0 + jl < Lp && r0 + c16 < Lp && (r0 < c0 || c16 <= jl))
+                    out[(size_t)(c0 + jl) * Lp + r0 + c16] = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
+    }
 }
 
 size_t gram_lds_per_wave(int64_t Lp, int prec)
@@ -61,14 +279,33 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
     a.ws = ws;
     const uint32_t outer = (uint32_t)w.outer;
     a.outer_magic = (uint32_t)((((uint64_t)1 << 32) + outer - 1) / outer);
+    const int T = (int)((Lp + 15) / 16);
+    const int ntiles = T * (T + 1) / 2;
+    if (prec == GP_FP64 && mode == GRAM_LRX && T >= g_gram_wg_min_t && 16 * T <= kWgMaxLpad) {
+        // long spectra: one workgroup per pixel, samples staged once per pass for all tiles
+        const size_t shw = gram_wg_lds_bytes(w.outer * w.outer);
+        const int nper = (ntiles + 3) / 4;
+        const int npass = (nper + g_gram_wg_tiles - 1) / g_gram_wg_tiles;
+        const int need = (nper + npass - 1) / npass;
+        const void *k = need <= 6    ? (const void *)gram_wg_kernel<6, 2>
+                        : need <= 9  ? (const void *)gram_wg_kernel<9, 2>
+                        : need <= 12 ? (const void *)gram_wg_kernel<12, 2>
+                        : need <= 14 ? (const void *)gram_wg_kernel<14, 2>
+                        : need <= 17 ? (const void *)gram_wg_kernel<17, 2>
+                        : need <= 22 ? (const void *)gram_wg_kernel<22, 1>
+                                     : (const void *)gram_wg_kernel<28, 1>;
+        if (int rc = allow_lds(k, shw, "gram_wg_kernel")) return rc;
+        void *args[] = {&a};
+        if (hipLaunchKernel(k, dim3((unsigned)npix), dim3(256), args, shw, s) != hipSuccess)
+            return fail(HSAD_EHIP, "gram_wg_kernel: launch failed");
+        return check_launch("gram_wg_kernel");
+    }
     const size_t per_wave = gram_lds_per_wave(Lp, prec);
     int wpb = 4;
     while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
     const size_t sh = per_wave * wpb;
     if (sh > 160 * 1024) return fail(HSAD_EUNSUPPORTED, "gram: L' too large for LDS staging");
     dim3 grid((unsigned)((npix + wpb - 1) / wpb)), block(64 * wpb);
-    const int T = (int)((Lp + 15) / 16);
-    const int ntiles = T * (T + 1) / 2;
     const int mt = ntiles <= 1 ? 1 : ntiles <= 3 ? 3 : ntiles <= 6 ? 6 : ntiles <= 10 ? 10 : 16;
     int rc = HSAD_OK;
 #define HSAD_GRAM_LAUNCH(P, M)                                                                   \
@@ -96,3 +333,13 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
 }
 
 }  // namespace hsad
+
+// min_t: smallest T = ceil(L'/16) taking the workgroup kernel (< 1: never); tiles: most
+// accumulator tiles per wavefront and pass (6..28)
+extern "C" int hsad_internal_gram_wg(int min_t, int tiles)
+{
+    if (tiles < 6 || tiles > 28) return HSAD_EINVAL;
+    hsad::g_gram_wg_min_t = min_t < 1 ? 1 << 20 : min_t;
+    hsad::g_gram_wg_tiles = tiles;
+    return 0;
+}

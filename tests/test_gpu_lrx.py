@@ -108,7 +108,9 @@ def test_box_kernels_non_finite(bad, box_kernel):
 
 # generic path: matrix-core Gram + FP64 Cholesky
 GEN = [(23, 19, 14, 5, 15), (20, 17, 28, 3, 11), (12, 14, 56, 3, 11), (9, 11, 112, 5, 15),
-       (7, 6, 224, 5, 15), (18, 13, 9, 0, 7), (11, 21, 20, 1, 5), (5, 4, 33, 3, 9)]
+       (7, 6, 224, 5, 15), (18, 13, 9, 0, 7), (11, 21, 20, 1, 5), (5, 4, 33, 3, 9),
+       (10, 9, 189, 3, 11), (6, 7, 256, 0, 9), (8, 5, 81, 1, 7), (5, 6, 257, 3, 9), (5, 4, 300, 3, 7),
+       (4, 5, 512, 1, 5)]
 
 
 @pytest.mark.parametrize("H,W,Lp,inner,outer", GEN)
@@ -328,6 +330,86 @@ def test_gram_step_against_window_stats(Lp, inner, outer, prec, tol):
             assert np.allclose(g[pix, Lp + 1], mi - mu, rtol=1e-12, atol=1e-12)
     print("gram prec", prec, "L'", Lp, "max normwise err %.3g" % worst)
     assert worst <= tol
+
+
+# the workgroup-per-pixel FP64 Gram (81 <= L' <= 256) at several tile budgets per
+# wavefront (one pass, two passes), and the per-wavefront kernel forced for the same shapes
+# (min_t 0); L' = 257 is past the workgroup kernel's band limit and takes the per-wavefront one
+@pytest.mark.parametrize("Lp,inner,outer", [(81, 5, 15), (100, 0, 9), (189, 3, 11), (224, 5, 15), (256, 1, 7),
+                                            (257, 3, 9)])
+@pytest.mark.parametrize("min_t,tiles", [(6, 17), (6, 28), (6, 6), (0, 17)])
+def test_workgroup_gram_step(Lp, inner, outer, min_t, tiles):
+    import ctypes
+    import torch
+    from paper_1201_2025_amd import synth
+    H, W = 9, 7
+    print("workgroup gram", Lp, inner, outer, min_t, tiles, flush=True)
+    x = synth.random_cube(Lp + tiles, H, W, Lp) * 0.1 + 1.0
+    t = torch.from_numpy(x).cuda()
+    npix = H * W
+    ws = torch.zeros(npix * (Lp + 2) * Lp, dtype=torch.float64, device="cuda")
+    p = hs.WindowParams(inner, outer, 1e-6, 0, 0)
+    L_ = hs.lib()
+    try:
+        assert L_.hsad_internal_gram_wg(min_t, tiles) == 0
+        rc = L_.hsad_internal_gram(ctypes.c_void_p(t.data_ptr()), H, W, Lp, ctypes.byref(p), 0, 0,
+                                   0, npix, ctypes.c_void_p(ws.data_ptr()), None)
+        assert rc == 0, hs.hsad_last_error()
+        torch.cuda.synchronize()
+    finally:
+        L_.hsad_internal_gram_wg(6, 17)
+    g = ws.cpu().numpy().reshape(npix, Lp + 2, Lp)
+    worst = 0.0
+    for pix in range(npix):
+        py, px = divmod(pix, W)
+        n_a, mu, C, n_in, mi, Ci = oracle.window_stats(x.astype(np.float64), inner, outer, py, px)
+        worst = max(worst, np.abs(g[pix, :Lp] - C).max() / np.abs(C).max())
+        assert np.array_equal(g[pix, :Lp], g[pix, :Lp].T)
+        assert np.allclose(g[pix, Lp], x[py, px].astype(np.float64) - mu, rtol=1e-12, atol=1e-12)
+        if inner:
+            assert np.allclose(g[pix, Lp + 1], mi - mu, rtol=1e-12, atol=1e-12)
+    assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("Lp", [65, 100, 224])
+def test_blocked_cholesky_matches_panel_kernel(Lp):
+    # the blocked factorisation (matrix-core products) and the per-column panel kernel give
+    # the same maps up to rounding order
+    import torch
+    from paper_1201_2025_amd import synth
+    x = synth.random_cube(6 + Lp, 19, 17, Lp) * 0.2 + 1.0
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    L_ = hs.lib()
+    try:
+        L_.hsad_internal_generic_force(1)
+        a, b = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
+        L_.hsad_internal_chol_blk(0)
+        c, d = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
+        torch.cuda.synchronize()
+    finally:
+        L_.hsad_internal_chol_blk(1)
+        L_.hsad_internal_generic_force(-1)
+    for u, v in ((a, c), (b, d)):
+        u, v = u.cpu().numpy().ravel().astype(np.float64), v.cpu().numpy().ravel().astype(np.float64)
+        assert np.max(np.abs(u - v) / np.abs(v)) <= 1e-6
+
+
+def test_workgroup_gram_scores_match_per_wavefront_kernel():
+    # the two FP64 Gram kernels give the same LRX / DWRX maps up to rounding order
+    import torch
+    x, _ = _reduced(5, 21, 23, 224)
+    t = torch.from_numpy(x).cuda()
+    a, b = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
+    L_ = hs.lib()
+    try:
+        L_.hsad_internal_gram_wg(0, 17)
+        c, d = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
+        torch.cuda.synchronize()
+    finally:
+        L_.hsad_internal_gram_wg(6, 17)
+    for u, v in ((a, c), (b, d)):
+        u, v = u.cpu().numpy().ravel().astype(np.float64), v.cpu().numpy().ravel().astype(np.float64)
+        assert np.max(np.abs(u - v) / np.abs(v)) <= 1e-6
 
 
 # hsad_detect: detector + eq. (12) threshold + mask in one call.  The maps must equal the

@@ -458,7 +458,8 @@ def test_error_stats():
     assert o2[0] == ok.sum() and np.isclose(o2[1], np.sqrt(np.mean(e2 * e2)), rtol=1e-12)
 
 
-@pytest.mark.parametrize("H,W,Lp,inner,outer", [(37, 29, 14, 5, 15), (30, 31, 6, 3, 9), (25, 20, 28, 1, 13)])
+@pytest.mark.parametrize("H,W,Lp,inner,outer", [(37, 29, 14, 5, 15), (30, 31, 6, 3, 9), (25, 20, 28, 1, 13),
+                                            (13, 12, 100, 3, 11)])
 def test_lrx_dwrx_at(H, W, Lp, inner, outer):
     print("lrx at", H, W, Lp, inner, outer, flush=True)
     import torch
