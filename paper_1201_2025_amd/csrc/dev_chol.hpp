@@ -147,7 +147,10 @@ __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_re
 }
 
 __host__ __device__ inline size_t chol_smem_doubles(int Lp) { return (size_t)(Lp + 2) * (NB + 1) + 8 + NB; }
-__host__ __device__ inline size_t chol_blk_smem_doubles(int Lp) { return chol_smem_doubles(Lp) + (size_t)NB * (NB + 1); }
+__host__ __device__ inline size_t chol_blk_smem_doubles(int Lp)
+{
+    return (size_t)(Lp + 2) * (NB + 2) + 8 + NB + (size_t)NB * (NB + 2);
+}
 
 }  // namespace hsad
 
@@ -195,7 +198,9 @@ __device__ __forceinline__ double lane_read_d(double v, int l)
 __device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double load_rel,
                                       float *lrx_out, float *dwrx_out, double *sm, int raw = 0)
 {
-    constexpr int LD = NB + 1;
+    // row stride NB + 2: a matrix-core operand read (16 rows x 2 columns per half
+    // wavefront) then touches 64 distinct LDS banks
+    constexpr int LD = NB + 2;
     const int rows = Lp + 2;
     double *P = sm;                            // panel: rows x NB (row stride LD)
     double *red = sm + (size_t)rows * LD;

@@ -53,15 +53,18 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_blo
 // of the exactly centred annulus samples, scaled by 1/n_a.
 // The tiles are written through an LDS transpose so that both triangles are stored in
 // rows of 16 consecutive doubles.
-// LDS: mu, m_in [256] doubles; two staging buffers [4][256] doubles (also the partial
-// sums of the means and the transposes); sample table [4 ceil(K/4)] ints (annulus:
+// LDS: mu, m_in [256] doubles; two staging buffers [4][Lpad + 16] doubles (also the
+// partial sums of the means and the transposes); sample table [4 ceil(K/4)] ints (annulus:
 // pixel index, inner window: -2 - pixel index, outside the image or past K: -1).
 // ------------------------------------------------------------------------------------
 static constexpr int kWgMaxLpad = 256;
+// row stride of a staged group (doubles): Lpad + 16 puts the four sample rows a matrix-core
+// operand read spans 32 banks apart, so each half-wavefront reads 64 distinct banks
+static constexpr int kWgStageLd = kWgMaxLpad + 16;
 
 __host__ __device__ inline size_t gram_wg_lds_bytes(int K)
 {
-    return (size_t)(2 + 8) * kWgMaxLpad * sizeof(double) + (size_t)4 * ((K + 3) / 4) * sizeof(int);
+    return ((size_t)2 * kWgMaxLpad + 8 * (size_t)kWgStageLd) * sizeof(double) + (size_t)4 * ((K + 3) / 4) * sizeof(int);
 }
 
 template <int MT, int WPE>
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     extern __shared__ double sm[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int Lp = a.Lp, T = (Lp + 15) >> 4, Lpad = 16 * T;
+    const int Lp = a.Lp, T = (Lp + 15) >> 4, Lpad = 16 * T, LS = Lpad + 16;
     double *mu = sm, *mi = sm + kWgMaxLpad, *buf = sm + 2 * kWgMaxLpad;
     const int local = blockIdx.x;
     if (local >= a.npix) return;
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const int n_o = clipn(py, a.R, a.H) * clipn(px, a.R, a.W);
     const int n_i = a.has_inner ? clipn(py, a.RI, a.H) * clipn(px, a.RI, a.W) : 0;
     const int n_a = n_o - n_i;
-    int *sof = reinterpret_cast<int *>(sm + 10 * kWgMaxLpad);
+    int *sof = reinterpret_cast<int *>(sm + 2 * kWgMaxLpad + 8 * kWgStageLd);
     for (int k = tid; k < 4 * ng; k += 256) {
         int v = -1;
         if (k < K) {
@@ -98,13 +101,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     // the thread's staged elements e = tid + 256 i: sample e / Lpad of the group, band e % Lpad
     constexpr int NE = 4 * kWgMaxLpad / 256;
     const int nel = 4 * Lpad;
-    int es[NE], eb[NE];
+    int es[NE], eb[NE], eo[NE];
     bool ev[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
         const int e = tid + 256 * i;
         es[i] = e < nel ? e / Lpad : 0;
         eb[i] = e < nel ? e - es[i] * Lpad : 0;
+        eo[i] = es[i] * LS + eb[i];   // staging offset (padding bands keep their own cell)
         ev[i] = e < nel && eb[i] < Lp;
         if (eb[i] >= Lp) eb[i] = Lp - 1;   // clamped band: loads stay in the row, value dropped
     }
@@ -192,18 +196,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 #pragma unroll
             for (int i = 0; i < NE; ++i) {
                 const int e = tid + 256 * i;
-                if (e < nel) dst[e] = xok[i] ? (double)xv[i] - emu[i] : 0.0;
+                if (e < nel) dst[eo[i]] = xok[i] ? (double)xv[i] - emu[i] : 0.0;
             }
         };
         auto mfma_group = [&](const double *b) {
-            const double *cur = b + g4 * Lpad + c16;
+            const double *cur = b + g4 * LS + c16;
 #pragma unroll
             for (int m = 0; m < MT; ++m)
                 if (m0 + m < nper && wv + 4 * (m0 + m) < ntiles)
                     acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[tb[m] & 0xffff], cur[tb[m] >> 16], acc[m], 0,
                                                                   0, 0);
         };
-        double *buf0 = buf, *buf1 = buf + 4 * kWgMaxLpad;
+        double *buf0 = buf, *buf1 = buf + 4 * kWgStageLd;
         fetch(0, xa, ka);
         __syncthreads();   // readers of the buffers (means, previous pass) are done
         stage(buf0, xa, ka);
