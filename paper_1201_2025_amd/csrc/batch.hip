@@ -266,8 +266,8 @@ __global__ __launch_bounds__(256) void batch_chol_kernel(const SceneDev *__restr
         const Item m = items[it];
         const SceneDev &s = sc[m.scene];
         const int64_t p = m.a;
-        chol_pixel_blk(chunk_ws + m.ws_off, s.Lp, s.load_rel, s.lrx ? s.lrx + p : nullptr,
-                       s.dwrx ? s.dwrx + p : nullptr, sm, m.raw);
+        chol_pixel(chunk_ws + m.ws_off, s.Lp, s.load_rel, s.lrx ? s.lrx + p : nullptr,
+                   s.dwrx ? s.dwrx + p : nullptr, sm, m.raw);
     }
 }
 
@@ -653,10 +653,10 @@ int hsad_batch_run(const hsad_batch_plan *P, void *ws, hipStream_t s)
             ++c;
             if (int rc = check_launch("batch_chol_wave_kernel")) return rc;
         } else {
-            // max_Lp > 64 here: the blocked factorisation, one 256-thread workgroup per item
-            const size_t sh = chol_blk_smem_doubles(ch.max_Lp) * sizeof(double);
+            const size_t sh = chol_smem_doubles(ch.max_Lp) * sizeof(double);
+            const int nt = ch.max_Lp <= 32 ? 64 : 256;
             if (int rc = allow_lds((const void *)batch_chol_kernel, sh, "batch_chol_kernel")) return rc;
-            hipLaunchKernelGGL(batch_chol_kernel, dim3(grid), dim3(256), sh, s, sc,
+            hipLaunchKernelGGL(batch_chol_kernel, dim3(grid * (nt == 64 ? 4 : 1)), dim3(nt), sh, s, sc,
                                ci + ch.chol_first, (int)ch.chol_count, ctr + c, chunk_ws);
             ++c;
             if (int rc = check_launch("batch_chol_kernel")) return rc;

@@ -95,8 +95,10 @@ size_t chol_smem(int64_t Lp) { return chol_smem_doubles((int)Lp) * sizeof(double
 
 // columns per unrolled block of the register-resident factorisation (64: fully unrolled)
 static int g_chol_cb = 16;
-// L' > 64: blocked factorisation with matrix-core trailing updates (0: chol_pixel)
-static int g_chol_blk = 1;
+// L' > 64: 2 = blocked factorisation (chol_pixel_blk) above kCholBlkMinLp, the panel form
+// below (measured crossover between L' = 128 and 144); 1 = blocked for every L' > 64;
+// 0 = panel form only
+static int g_chol_blk = 2;
 
 int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel, float *lrx,
                 float *dwrx, hipStream_t s, const int32_t *idx, int64_t npix_img, int raw)
@@ -131,7 +133,7 @@ int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel,
     const size_t sh = chol_smem(Lp);
     const int nt = Lp <= 32 ? 64 : 256;
     if (int rc = allow_lds((const void *)chol_rx_kernel, sh, "chol_rx_kernel")) return rc;
-    if (g_chol_blk && Lp > 64) {
+    if (g_chol_blk == 1 || (g_chol_blk == 2 && Lp >= kCholBlkMinLp)) {
         const size_t shb = chol_blk_smem_doubles((int)Lp) * sizeof(double);
         if (int rc = allow_lds((const void *)chol_blk_kernel, shb, "chol_blk_kernel")) return rc;
         hipLaunchKernelGGL(chol_blk_kernel, dim3((unsigned)npix), dim3(256), shb, s, ws, (int)Lp, npix, pix0, load_rel,
@@ -145,9 +147,10 @@ int chol_launch(double *ws, int64_t Lp, int npix, int64_t pix0, double load_rel,
 
 }  // namespace hsad
 
-extern "C" int hsad_internal_chol_blk(int on)
+extern "C" int hsad_internal_chol_blk(int mode)
 {
-    hsad::g_chol_blk = on != 0;
+    if (mode < 0 || mode > 2) return HSAD_EINVAL;
+    hsad::g_chol_blk = mode;
     return 0;
 }
 

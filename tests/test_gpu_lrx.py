@@ -371,10 +371,10 @@ def test_workgroup_gram_step(Lp, inner, outer, min_t, tiles):
     assert worst <= 1e-12
 
 
-@pytest.mark.parametrize("Lp", [65, 100, 224])
+@pytest.mark.parametrize("Lp", [65, 100, 136, 137, 224])
 def test_blocked_cholesky_matches_panel_kernel(Lp):
     # the blocked factorisation (matrix-core products) and the per-column panel kernel give
-    # the same maps up to rounding order
+    # the same maps up to rounding order (both forced: by default L' < 137 takes the panel form)
     import torch
     from paper_1201_2025_amd import synth
     x = synth.random_cube(6 + Lp, 19, 17, Lp) * 0.2 + 1.0
@@ -382,12 +382,13 @@ def test_blocked_cholesky_matches_panel_kernel(Lp):
     L_ = hs.lib()
     try:
         L_.hsad_internal_generic_force(1)
+        assert L_.hsad_internal_chol_blk(1) == 0
         a, b = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
         L_.hsad_internal_chol_blk(0)
         c, d = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
         torch.cuda.synchronize()
     finally:
-        L_.hsad_internal_chol_blk(1)
+        L_.hsad_internal_chol_blk(2)
         L_.hsad_internal_generic_force(-1)
     for u, v in ((a, c), (b, d)):
         u, v = u.cpu().numpy().ravel().astype(np.float64), v.cpu().numpy().ravel().astype(np.float64)
