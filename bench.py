@@ -41,6 +41,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+FP64_PEAK = 78.6e12        # MI355X FP64, vector and matrix, flop/s
+
+
+def annulus_samples(H, W, inner, outer):
+    """Sum over all pixels of n_a, the annulus sample count with windows clipped at the image
+    border (outer window minus inner window, Sec. 2.2)."""
+    def clipped(n, r):
+        c = np.arange(n)
+        return np.minimum(c, r) + np.minimum(n - 1 - c, r) + 1
+    ro, ri = outer // 2, inner // 2
+    tot = clipped(H, ro).sum() * clipped(W, ro).sum()
+    if inner > 0:
+        tot -= clipped(H, ri).sum() * clipped(W, ri).sum()
+    return float(tot)
+
+
+def lrx_fp64_roofline(H, W, Lp, inner, outer, ms):
+    """FP64 roofline of one LRX + DWRX call: the definition's flops, the annulus Gram
+    (n_a L'(L'+1) per pixel: L'(L'+1)/2 entries, a multiply-add per sample each) plus the
+    Cholesky and the two triangular solves (L'^3/3 + 2 L'^2 per pixel), over the call's time.
+    The box-statistics path (L' <= 128) needs fewer flops than this definition count."""
+    flops = annulus_samples(H, W, inner, outer) * Lp * (Lp + 1) + H * W * (Lp ** 3 / 3.0 + 2.0 * Lp ** 2)
+    ach = flops / (ms * 1e-3)
+    return {"bound": "fp64", "achieved": ach / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": ach / FP64_PEAK, "flops": flops}
 METRIC = "pixels/s for DWT+LRX at 512×512×224 vs full-band GPU; ROC AUC delta vs FP64"
 
 
@@ -183,7 +208,11 @@ def bench_dwest(cube, dev, log):
         ms = a.elapsed_time(b)
         nominal = 9.0 * Lp ** 3 * H * W
         out.append({"levels": lv, "Lp": Lp, "ms": ms, "pixels_per_s": H * W / (ms * 1e-3),
-                    "nominal_fp64_tflops": nominal / (ms * 1e-3) / 1e12})
+                    "nominal_fp64_tflops": nominal / (ms * 1e-3) / 1e12,
+                    "roofline": {"bound": "fp64", "achieved": nominal / (ms * 1e-3) / 1e12,
+                                 "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                                 "frac": nominal / (ms * 1e-3) / FP64_PEAK, "flops": nominal,
+                                 "count": "nominal 9 L'^3 per pixel"}})
         log("dwest L'=%d: %.2f ms" % (Lp, ms))
         del ws
     return {"workload": "512x512x224 cube (150 singles + 50 blobs) at L' = 14/28/56, inner 3, outer 11", "levels": out}
@@ -773,7 +802,7 @@ def main():
             torch.cuda.synchronize()
             ms = a.elapsed_time(b)
             fsc = fl.cpu().numpy().ravel()
-            r = {"ms": ms, "value": npix / (ms * 1e-3)}
+            r = {"ms": ms, "value": npix / (ms * 1e-3), "roofline": lrx_fp64_roofline(H, W, L, inner, outer, ms)}
             try:
                 import oracle
                 r["auc_lrx"] = oracle.auc(fsc, scene.truth)
@@ -814,7 +843,8 @@ def main():
             dm, lm = float(np.mean(dts)), float(np.mean(lts))
             sweep.append({"levels": j, "Lp": lpj, "dwt_ms": dm, "lrx_dwrx_ms": lm,
                           "pixels_per_s": npix / ((dm + lm) * 1e-3),
-                          "dwt_hbm_frac": (npix * (L + lpj) * 4) / (dm * 1e-3) / HBM_PEAK})
+                          "dwt_hbm_frac": (npix * (L + lpj) * 4) / (dm * 1e-3) / HBM_PEAK,
+                          "lrx_dwrx_roofline": lrx_fp64_roofline(H, W, lpj, inner, outer, lm)})
             del wsj
 
     def log(msg):
