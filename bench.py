@@ -700,7 +700,7 @@ def main():
     # the DWT's launch duration (roofline) comes from events around the DWT of every
     # EV_EVERY-th timed step: an event pair costs a few microseconds of pipeline drain, so
     # bracketing every step would make every step slower than it is
-    EV_EVERY = 4
+    EV_EVERY = 10
     evs = {i: [torch.cuda.Event(enable_timing=True) for _ in range(2)]
            for i in range(args.steps) if i % EV_EVERY == 0}
     t0 = torch.cuda.Event(enable_timing=True)

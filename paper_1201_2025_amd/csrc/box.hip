@@ -77,9 +77,16 @@ bool box_supported(int64_t Lp, const Windows &w)
 static int g_box_gc = 0;   // 0: default feature chunk; 15 / 8 / 5 forced (tuning, tests)
 static int g_box_tx = 0;   // 0: widest tile whose LDS fits; 16 forced (tuning, tests)
 
-// default chunk width: measured fastest on gfx950 at 512 x 512 (5 features keep four
-// 16 x 16 workgroups resident per CU; 8 for L' = 5..7, where 5 spills registers)
-static int box_gc(int Lp) { return g_box_gc ? g_box_gc : ((Lp >= 5 && Lp <= 7) ? 8 : 5); }
+// default chunk width per L' (features per round of vertical and horizontal sums; the
+// tile keeps L' + L'(L'+1)/2 + 1 features): the fastest of 5 / 8 / 15 for hsad_detect with
+// 5 x 5 / 15 x 15 windows, at 512 x 512 and at 1024 x 1024 alike (32 x 16 tiles).  At
+// 512 x 512, L' = 2: 18.0 vs 21.4 us (5); L' = 3: 24.1 vs 26.0 (8); L' = 4: 28.1 vs 30.4 (5);
+// L' = 5: 40.2 vs 45.8 (15); L' = 6 / 7 / 8: 49.7 / 64.6 / 70.1 vs 59.7 / 73.4 / 94.0 (8)
+static int box_gc(int Lp)
+{
+    static const int best[9] = {5, 5, 8, 5, 8, 5, 15, 15, 15};
+    return g_box_gc ? g_box_gc : best[Lp >= 0 && Lp <= 8 ? Lp : 0];
+}
 
 template <int LP, int GCMAX> static int box_width(int R)
 {
