@@ -29,7 +29,7 @@ namespace hsad {
 // smallest tile count T = ceil(L'/16) that takes the workgroup-per-pixel FP64 Gram, and its
 // most accumulator tiles per wavefront and pass (tests choose through hsad_internal_gram_wg)
 static int g_gram_wg_min_t = 6;
-static int g_gram_wg_tiles = 17;
+static int g_gram_wg_tiles = 14;
 
 template <int PREC, int kMaxTilesPerPass>
 __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_block)
@@ -47,13 +47,13 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_blo
 // registers, so the per-wavefront kernel above re-reads every window sample once per pass
 // of 16 tiles.  Here the four wavefronts of a workgroup share each group of 4 centred
 // samples through LDS (staged once per group for all bands) and split the tiles, MT
-// accumulators per wavefront and pass.  Each group's samples are fetched into registers
-// two groups ahead of use (two LDS buffers, one barrier per group).  Definitions as in
+// accumulators per wavefront and pass.  Groups are staged two at a time (one barrier per
+// pair), each pair fetched into registers two pairs ahead of use (two LDS buffers).  Definitions as in
 // gram_pixel: FP64 means first (all threads, band-parallel partial sums), then the Gram
 // of the exactly centred annulus samples, scaled by 1/n_a.
 // The tiles are written through an LDS transpose so that both triangles are stored in
 // rows of 16 consecutive doubles.
-// LDS: mu, m_in [256] doubles; two staging buffers [4][Lpad + 16] doubles (also the
+// LDS: mu, m_in [256] doubles; two staging buffers [2][4][Lpad + 16] doubles (also the
 // partial sums of the means and the transposes); sample table [4 ceil(K/4)] ints (annulus:
 // pixel index, inner window: -2 - pixel index, outside the image or past K: -1).
 // ------------------------------------------------------------------------------------
@@ -62,9 +62,14 @@ static constexpr int kWgMaxLpad = 256;
 // operand read spans 32 banks apart, so each half-wavefront reads 64 distinct banks
 static constexpr int kWgStageLd = kWgMaxLpad + 16;
 
+// groups of 4 samples staged per barrier
+static constexpr int kWgGroups = 2;
+
 __host__ __device__ inline size_t gram_wg_lds_bytes(int K)
 {
-    return ((size_t)2 * kWgMaxLpad + 8 * (size_t)kWgStageLd) * sizeof(double) + (size_t)4 * ((K + 3) / 4) * sizeof(int);
+    const size_t nsg = ((size_t)(K + 3) / 4 + kWgGroups - 1) / kWgGroups;
+    return ((size_t)2 * kWgMaxLpad + 8 * (size_t)kWgGroups * kWgStageLd) * sizeof(double) +
+           (size_t)4 * kWgGroups * nsg * sizeof(int);
 }
 
 template <int MT, int WPE>
@@ -82,11 +87,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     const int py = (int)(pix / a.W), px = (int)(pix - (int64_t)py * a.W);
     const int K = (2 * a.R + 1) * (2 * a.R + 1);
     const int ng = (K + 3) / 4;
+    constexpr int GPB = kWgGroups;
+    const int nsg = (ng + GPB - 1) / GPB;   // staged units of GPB groups
     const int n_o = clipn(py, a.R, a.H) * clipn(px, a.R, a.W);
     const int n_i = a.has_inner ? clipn(py, a.RI, a.H) * clipn(px, a.RI, a.W) : 0;
     const int n_a = n_o - n_i;
-    int *sof = reinterpret_cast<int *>(sm + 2 * kWgMaxLpad + 8 * kWgStageLd);
-    for (int k = tid; k < 4 * ng; k += 256) {
+    int *sof = reinterpret_cast<int *>(sm + 2 * kWgMaxLpad + 8 * GPB * kWgStageLd);
+    for (int k = tid; k < 4 * GPB * nsg; k += 256) {
         int v = -1;
         if (k < K) {
             int sy, sx;
@@ -180,51 +187,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 #pragma unroll
         for (int m = 0; m < MT; ++m)
             for (int e = 0; e < 4; ++e) acc[m][e] = 0.0;
-        // group g's samples: fetched into registers two groups before they are staged, so
-        // each load has two groups of matrix-core work to arrive
-        float xa[NE], xb[NE];
-        bool ka[NE], kb[NE];
-        auto fetch = [&](int g, float *xv, bool *xok) {
+        // unit u (groups GPB u .. GPB u + GPB - 1): fetched into registers two units before
+        // it is staged, so that each load has two units of matrix-core work to arrive
+        float xa[GPB * NE], xb[GPB * NE];
+        bool ka[GPB * NE], kb[GPB * NE];
+        auto fetch = [&](int u, float *xv, bool *xok) {
 #pragma unroll
-            for (int i = 0; i < NE; ++i) {
-                const int o = sof[4 * g + es[i]];
-                xv[i] = a.x[(size_t)(o >= 0 ? o : 0) * Lp + eb[i]];
-                xok[i] = ev[i] && o >= 0;
-            }
+            for (int gi = 0; gi < GPB; ++gi)
+#pragma unroll
+                for (int i = 0; i < NE; ++i) {
+                    const int o = sof[4 * (GPB * u + gi) + es[i]];
+                    xv[gi * NE + i] = a.x[(size_t)(o >= 0 ? o : 0) * Lp + eb[i]];
+                    xok[gi * NE + i] = ev[i] && o >= 0;
+                }
         };
         auto stage = [&](double *dst, const float *xv, const bool *xok) {
 #pragma unroll
-            for (int i = 0; i < NE; ++i) {
-                const int e = tid + 256 * i;
-                if (e < nel) dst[eo[i]] = xok[i] ? (double)xv[i] - emu[i] : 0.0;
+            for (int gi = 0; gi < GPB; ++gi)
+#pragma unroll
+                for (int i = 0; i < NE; ++i) {
+                    const int e = tid + 256 * i;
+                    if (e < nel)
+                        dst[gi * 4 * LS + eo[i]] = xok[gi * NE + i] ? (double)xv[gi * NE + i] - emu[i] : 0.0;
+                }
+        };
+        auto mfma_unit = [&](const double *b) {
+#pragma unroll
+            for (int gi = 0; gi < GPB; ++gi) {
+                const double *cur = b + gi * 4 * LS + g4 * LS + c16;
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    if (m0 + m < nper && wv + 4 * (m0 + m) < ntiles)
+                        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[tb[m] & 0xffff], cur[tb[m] >> 16], acc[m],
+                                                                      0, 0, 0);
             }
         };
-        auto mfma_group = [&](const double *b) {
-            const double *cur = b + g4 * LS + c16;
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-                if (m0 + m < nper && wv + 4 * (m0 + m) < ntiles)
-                    acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[tb[m] & 0xffff], cur[tb[m] >> 16], acc[m], 0,
-                                                                  0, 0);
-        };
-        double *buf0 = buf, *buf1 = buf + 4 * kWgStageLd;
+        double *buf0 = buf, *buf1 = buf + GPB * 4 * kWgStageLd;
         fetch(0, xa, ka);
         __syncthreads();   // readers of the buffers (means, previous pass) are done
         stage(buf0, xa, ka);
-        if (1 < ng) fetch(1, xb, kb);
-        if (2 < ng) fetch(2, xa, ka);
+        if (1 < nsg) fetch(1, xb, kb);
+        if (2 < nsg) fetch(2, xa, ka);
         __syncthreads();
-        // even steps: group g in buf0, group g+1 (xb) staged to buf1, group g+3 fetched to
-        // xb; odd steps mirror with buf1 / xa
-        for (int g = 0; g < ng; g += 2) {
-            mfma_group(buf0);
-            if (g + 1 < ng) stage(buf1, xb, kb);
-            if (g + 3 < ng) fetch(g + 3, xb, kb);
+        // even steps: unit u in buf0, unit u+1 (xb) staged to buf1, unit u+3 fetched to xb;
+        // odd steps mirror with buf1 / xa
+        for (int u = 0; u < nsg; u += 2) {
+            mfma_unit(buf0);
+            if (u + 1 < nsg) stage(buf1, xb, kb);
+            if (u + 3 < nsg) fetch(u + 3, xb, kb);
             __syncthreads();
-            if (g + 1 >= ng) break;
-            mfma_group(buf1);
-            if (g + 2 < ng) stage(buf0, xa, ka);
-            if (g + 4 < ng) fetch(g + 4, xa, ka);
+            if (u + 1 >= nsg) break;
+            mfma_unit(buf1);
+            if (u + 2 < nsg) stage(buf0, xa, ka);
+            if (u + 4 < nsg) fetch(u + 4, xa, ka);
             __syncthreads();
         }
         // write the tiles: the upper triangle straight from the accumulators, the lower

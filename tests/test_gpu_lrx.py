@@ -357,7 +357,7 @@ def test_workgroup_gram_step(Lp, inner, outer, min_t, tiles):
         assert rc == 0, hs.hsad_last_error()
         torch.cuda.synchronize()
     finally:
-        L_.hsad_internal_gram_wg(6, 17)
+        L_.hsad_internal_gram_wg(6, 14)
     g = ws.cpu().numpy().reshape(npix, Lp + 2, Lp)
     worst = 0.0
     for pix in range(npix):
@@ -407,7 +407,7 @@ def test_workgroup_gram_scores_match_per_wavefront_kernel():
         c, d = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
         torch.cuda.synchronize()
     finally:
-        L_.hsad_internal_gram_wg(6, 17)
+        L_.hsad_internal_gram_wg(6, 14)
     for u, v in ((a, c), (b, d)):
         u, v = u.cpu().numpy().ravel().astype(np.float64), v.cpu().numpy().ravel().astype(np.float64)
         assert np.max(np.abs(u - v) / np.abs(v)) <= 1e-6
