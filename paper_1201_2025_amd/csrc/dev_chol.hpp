@@ -151,7 +151,7 @@ __device__ inline void chol_pixel(double *__restrict__ A, int Lp, double load_re
 __host__ __device__ inline size_t chol_smem_doubles(int Lp) { return (size_t)(Lp + 2) * (NB + 1) + 8 + NB; }
 __host__ __device__ inline size_t chol_blk_smem_doubles(int Lp)
 {
-    return (size_t)(Lp + 2) * (NB + 2) + 8 + NB + (size_t)NB * (NB + 2);
+    return (size_t)(Lp + 2) * (NB + 2) + 8 + NB + 2 * (size_t)NB * (NB + 2);
 }
 
 }  // namespace hsad
@@ -190,13 +190,15 @@ __device__ __forceinline__ double lane_read_d(double v, int l)
 }
 
 // Blocked variant of chol_pixel for L' > 64 (same arguments, definitions and outputs;
-// sm holds chol_blk_smem_doubles(L') doubles): per panel of NB columns, one wavefront
-// factors the NB x NB diagonal block and inverts its triangle in registers; the rows below are solved against it as one product with
-// that inverse, and the trailing lower trapezoid takes the rank-NB update, both on the FP64
-// matrix cores in 16 x 16 tiles, the trailing tiles read and written in place (coalesced
-// rows of 16 doubles).  The two extra rows are ordinary rows of this elimination; their
-// squared norms are summed panel by panel from LDS, so nothing is written back but the
-// trailing part.  Four workgroup barriers per panel.
+// sm holds chol_blk_smem_doubles(L') doubles).  Panels of NB columns.  One wavefront
+// factors a panel's NB x NB diagonal block and inverts its triangle in registers.  The rows
+// below are solved as one product with that inverse, and the trailing lower trapezoid takes
+// the rank-NB update in place; both products run on the FP64 matrix cores in 16 x 16 tiles
+// (coalesced rows of 16 doubles).  Look-ahead: during panel p's trailing update one
+// wavefront updates the first tiles, which hold panel p+1's diagonal block, and factors
+// that block at once, while the other wavefronts update the rest.  The two extra rows are
+// ordinary rows of this elimination; their squared norms are summed panel by panel from
+// LDS.
 __device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double load_rel,
                                       float *lrx_out, float *dwrx_out, double *sm, int raw = 0)
 {
@@ -208,6 +210,7 @@ __device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double loa
     double *red = sm + (size_t)rows * LD;
     double &bad = red[6];
     double *Wm = red + 8 + NB;                 // inverse of the diagonal block, NB x NB (stride LD)
+    double *D = Wm + NB * LD;                  // next diagonal block before its factorisation
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const int c16 = lane & 15, g4 = lane >> 4;
     if (raw) {
@@ -227,68 +230,84 @@ __device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double loa
     for (int i = tid; i < Lp; i += nt) A[(size_t)i * Lp + i] += lam;
     __syncthreads();
 
+    // Cholesky factor L of the nbd x nbd block in src (row stride LD) and W = L^-1, by one
+    // wavefront, lane i (mod 32) holding row i of the block and row i of W (identity to
+    // start) in registers.  Step j: l_jj = sqrt(a_jj), l_ij = a_ij / l_jj; row j of W is
+    // final once divided by l_jj; rows i > j then take a_ic -= l_ij l_cj (c > j) and
+    // W_ic -= l_ij W_jc (c <= j).  Every broadcast is a lane read of a compile-time
+    // register, so the step has no LDS round trip.  L goes to P's first rows, W to Wm (zero
+    // outside the nbd x nbd lower triangle).
+    auto factor_diag = [&](const double *src, int nbd) {
+        const int i = lane & 31;
+        double a[NB], w[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            a[c] = src[i * LD + c];
+            w[c] = c == i ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (j < nbd) {
+                const double d = lane_read_d(a[j], j);
+                const double sq = sqrt(d), iv = 1.0 / sq;
+                if (lane == 0 && !(d > 0.0)) bad = 1.0;
+                const double lij = i == j ? sq : a[j] * iv;
+                a[j] = lij;
+                const double ws = i == j ? iv : 1.0, lw = i > j ? lij : 0.0;
+#pragma unroll
+                for (int c = 0; c <= j; ++c) w[c] *= ws;
+                // rows i <= j only change entries above their diagonal, which are not used
+#pragma unroll
+                for (int c = j + 1; c < NB; ++c) {
+                    a[c] = fma(-lij, lane_read_d(a[j], c), a[c]);
+                    // few lane reads in flight: each holds two scalar registers
+                    if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c <= j; ++c) {
+                    w[c] = fma(-lw, lane_read_d(w[c], j), w[c]);
+                    if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (lane < 32) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const bool in = i < nbd && c <= i;
+                if (in) P[i * LD + c] = a[c];
+                Wm[i * LD + c] = in ? w[c] : 0.0;
+            }
+        }
+    };
+
+    // panel 0: the whole panel, then its diagonal block
+    {
+        const int nb = Lp < NB ? Lp : NB;
+        for (int t = tid; t < rows * nb; t += nt) {
+            const int r = t / nb, c = t - r * nb;
+            P[(size_t)r * LD + c] = A[(size_t)r * Lp + c];
+        }
+        __syncthreads();
+        if (wv == 0) factor_diag(P, nb);
+        __syncthreads();
+    }
+
     double s1 = 0.0, s2 = 0.0;   // partial squared norms of the extra rows (threads < NB)
     for (int kb = 0; kb < Lp; kb += NB) {
         const int nb = Lp - kb < NB ? Lp - kb : NB;
         const int prow = rows - kb;
-        for (int t = tid; t < prow * nb; t += nt) {
-            const int r = t / nb, c = t - r * nb;
-            P[(size_t)r * LD + c] = A[(size_t)(kb + r) * Lp + kb + c];
+        if (kb > 0) {
+            // the rows below the diagonal block (factored during the previous trailing update)
+            for (int t = tid; t < (prow - nb) * nb; t += nt) {
+                const int r = nb + t / nb, c = t - (r - nb) * nb;
+                P[(size_t)r * LD + c] = A[(size_t)(kb + r) * Lp + kb + c];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        // diagonal block: Cholesky factor L_kk and its inverse W = L_kk^-1 in one pass by
-        // one wavefront, lane i (mod 32) holding row i of the block and row i of W (identity to
-        // start) in registers.  Step j: l_jj = sqrt(a_jj), l_ij = a_ij / l_jj; row j of W is
-        // final once divided by l_jj; rows i > j then take a_ic -= l_ij l_cj (c > j) and
-        // W_ic -= l_ij W_jc (c <= j).  Every broadcast is a lane read of a compile-time
-        // register, so the step has no LDS round trip.
-        if (wv == (kb / NB) % nw) {   // rotates over the SIMDs from panel to panel
-            const int i = lane & 31;
-            double a[NB], w[NB];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                a[c] = P[i * LD + c];
-                w[c] = c == i ? 1.0 : 0.0;
-            }
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                if (j < nb) {
-                    const double d = lane_read_d(a[j], j);
-                    const double sq = sqrt(d), iv = 1.0 / sq;
-                    if (lane == 0 && !(d > 0.0)) bad = 1.0;
-                    const double lij = i == j ? sq : a[j] * iv;
-                    a[j] = lij;
-                    const double ws = i == j ? iv : 1.0, lw = i > j ? lij : 0.0;
-#pragma unroll
-                    for (int c = 0; c <= j; ++c) w[c] *= ws;
-                    // rows i <= j only change entries above their diagonal, which are not used
-#pragma unroll
-                    for (int c = j + 1; c < NB; ++c) {
-                        a[c] = fma(-lij, lane_read_d(a[j], c), a[c]);
-                        // few lane reads in flight: each holds two scalar registers
-                        if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int c = 0; c <= j; ++c) {
-                        w[c] = fma(-lw, lane_read_d(w[c], j), w[c]);
-                        if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            if (lane < 32) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    const bool in = i < nb && c <= i;
-                    if (in) P[i * LD + c] = a[c];
-                    Wm[i * LD + c] = in ? w[c] : 0.0;
-                }
-            }
-        }
-        __syncthreads();
-        // rows below the block: X = A_below L_kk^-T = A_below W^T with W = L_kk^-1 (computed
-        // above), 16 rows x 32 columns per wavefront on the matrix cores.
+        // rows below the block: X = A_below L_kk^-T = A_below W^T with W = L_kk^-1,
+        // 16 rows x 32 columns per wavefront on the matrix cores.
         // Columns >= nb (last panel) are zero on both operands and never stored.
         {
             const int nrb = (prow - nb + 15) >> 4;
@@ -325,6 +344,10 @@ __device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double loa
             const int TI = (nr + 15) >> 4, TJ = (ncl + 15) >> 4;
             const int ntri = TJ * (TJ + 1) / 2, ntile = ntri + (TI - TJ) * TJ;
             const int nk = (nb + 3) >> 2;
+            const int nb1 = Lp - k0 < NB ? Lp - k0 : NB;   // the next panel's width
+            // the next diagonal block lies in the first ns tiles: (0,0), then (1,0), (1,1)
+            const int ns = nb1 > 16 ? 3 : 1;
+            const int la = (kb / NB + 1) % nw;             // rotates over the SIMDs
             // tile t -> (I, J): row-major over the triangle J <= I < TJ, then full rows of TJ
             auto tile_of = [&](int t, int &I, int &J) {
                 if (t < ntri) {
@@ -338,14 +361,27 @@ __device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double loa
                     J = u - (I - TJ) * TJ;
                 }
             };
-            // TB tiles per wavefront and step; the next step's tiles are loaded before this
-            // step's products are issued
-            constexpr int TB = 2;
-            auto load_tiles = [&](int t0, f64x4 *acc, int *tij) {
+            // products of the tiles in tij[] (16 I | 16 J << 16) with this panel's L
+            auto tile_products = [&](f64x4 *acc, const int *tij, int ntb) {
+                for (int kk = 0; kk < nk; ++kk) {
+                    const int col = 4 * kk + g4;
+                    for (int q = 0; q < ntb; ++q) {
+                        const int ra = nb + (tij[q] & 0xffff) + c16, rb = nb + (tij[q] >> 16) + c16;
+                        const double av = ra < prow && col < nb ? -P[(size_t)ra * LD + col] : 0.0;
+                        const double bv = rb < prow && col < nb ? P[(size_t)rb * LD + col] : 0.0;
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+                    }
+                }
+            };
+            if (wv == la) {
+                // the next diagonal block: its tiles updated (written back too, for the rows
+                // of a partial last block that lie below it) and kept in D, then factored
+                f64x4 acc[3];
+                int tij[3];
 #pragma unroll
-                for (int q = 0; q < TB; ++q) {
+                for (int q = 0; q < 3; ++q) {
                     int I, J;
-                    tile_of(t0 + q < ntile ? t0 + q : ntile - 1, I, J);
+                    tile_of(q < ns ? q : 0, I, J);
                     tij[q] = 16 * I | (16 * J) << 16;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
@@ -353,35 +389,64 @@ __device__ inline void chol_pixel_blk(double *__restrict__ A, int Lp, double loa
                         acc[q][e] = r < rows && c < Lp ? A[(size_t)r * Lp + c] : 0.0;
                     }
                 }
-            };
-            f64x4 acc[TB], nacc[TB];
-            int tij[TB], nij[TB];
-            if (TB * wv < ntile) load_tiles(TB * wv, acc, tij);
-            for (int t0 = TB * wv; t0 < ntile; t0 += TB * nw) {
-                const int t1 = t0 + TB * nw;
-                if (t1 < ntile) load_tiles(t1, nacc, nij);
-                for (int kk = 0; kk < nk; ++kk) {
-                    const int col = 4 * kk + g4;
+                tile_products(acc, tij, ns);
 #pragma unroll
-                    for (int q = 0; q < TB; ++q) {
-                        const int ra = nb + (tij[q] & 0xffff) + c16, rb = nb + (tij[q] >> 16) + c16;
-                        const double av = ra < prow && col < nb ? -P[(size_t)ra * LD + col] : 0.0;
-                        const double bv = rb < prow && col < nb ? P[(size_t)rb * LD + col] : 0.0;
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < TB; ++q) {
-                    if (t0 + q < ntile) {
+                for (int q = 0; q < 3; ++q) {
+                    if (q < ns) {
+                        const int I16 = tij[q] & 0xffff, J16 = tij[q] >> 16;
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             // FP64 16x16x4: element e of lane l is row 4e + (l >> 4), column l & 15
-                            const int r = k0 + (tij[q] & 0xffff) + 4 * e + g4, c = k0 + (tij[q] >> 16) + c16;
+                            const int r = k0 + I16 + 4 * e + g4, c = k0 + J16 + c16;
                             if (r < rows && c < Lp && c <= r) A[(size_t)r * Lp + c] = acc[q][e];
+                            D[(I16 + 4 * e + g4) * LD + J16 + c16] = acc[q][e];
                         }
                     }
-                    acc[q] = nacc[q];
-                    tij[q] = nij[q];
+                }
+                if (ns == 3) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) D[(4 * e + g4) * LD + 16 + c16] = 0.0;   // above the diagonal
+                }
+                wave_sync_lds();
+                factor_diag(D, nb1);
+            } else {
+                // the remaining tiles over the other wavefronts, TB per step, the next step's
+                // tiles loaded before this step's products are issued
+                constexpr int TB = 2;
+                const int wi = wv < la ? wv : wv - 1, nwr = nw - 1;
+                auto load_tiles = [&](int t0, f64x4 *acc, int *tij) {
+#pragma unroll
+                    for (int q = 0; q < TB; ++q) {
+                        int I, J;
+                        tile_of(t0 + q < ntile ? t0 + q : ntile - 1, I, J);
+                        tij[q] = 16 * I | (16 * J) << 16;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int r = k0 + 16 * I + 4 * e + g4, c = k0 + 16 * J + c16;
+                            acc[q][e] = r < rows && c < Lp ? A[(size_t)r * Lp + c] : 0.0;
+                        }
+                    }
+                };
+                f64x4 acc[TB], nacc[TB];
+                int tij[TB], nij[TB];
+                const int first = ns + TB * wi;
+                if (first < ntile) load_tiles(first, acc, tij);
+                for (int t0 = first; t0 < ntile; t0 += TB * nwr) {
+                    const int t1 = t0 + TB * nwr;
+                    if (t1 < ntile) load_tiles(t1, nacc, nij);
+                    tile_products(acc, tij, TB);
+#pragma unroll
+                    for (int q = 0; q < TB; ++q) {
+                        if (t0 + q < ntile) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int r = k0 + (tij[q] & 0xffff) + 4 * e + g4, c = k0 + (tij[q] >> 16) + c16;
+                                if (r < rows && c < Lp && c <= r) A[(size_t)r * Lp + c] = acc[q][e];
+                            }
+                        }
+                        acc[q] = nacc[q];
+                        tij[q] = nij[q];
+                    }
                 }
             }
         }
