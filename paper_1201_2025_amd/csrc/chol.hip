@@ -96,7 +96,7 @@ size_t chol_smem(int64_t Lp) { return chol_smem_doubles((int)Lp) * sizeof(double
 // columns per unrolled block of the register-resident factorisation (64: fully unrolled)
 static int g_chol_cb = 16;
 // L' > 64: 2 = blocked factorisation (chol_pixel_blk) above kCholBlkMinLp, the panel form
-// below (measured crossover between L' = 128 and 144); 1 = blocked for every L' > 64;
+// below (measured crossover at L' = 128: 29.0 ms either way at 256 x 256); 1 = blocked for every L' > 64;
 // 0 = panel form only
 static int g_chol_blk = 2;
 

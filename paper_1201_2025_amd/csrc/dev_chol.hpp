@@ -8,7 +8,7 @@ namespace hsad {
 
 static constexpr int NB = 32;
 // smallest L' that takes the blocked factorisation by default (chol_pixel_blk below)
-static constexpr int kCholBlkMinLp = 137;
+static constexpr int kCholBlkMinLp = 129;
 
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
