@@ -148,6 +148,7 @@ SIGNATURES = [
 INTERNAL_SIGNATURES = [
     ("hsad_internal_filter", ctypes.c_int, [ctypes.POINTER(ctypes.c_double)]),
     ("hsad_internal_dwt_force", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_dwt_banded_wide", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_chunk", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_width", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_feat_cfg", ctypes.c_int, [ctypes.c_int]),

@@ -101,15 +101,15 @@ __host__ __device__ inline int64_t dwt_banded_lds_floats(int64_t L, int64_t Lp, 
     return P * ((L + W - 1) | 1) + P * (Lp | 1);
 }
 
-// np (<= P <= 64) contiguous spectra starting at pixel p0; a workgroup of 256 threads.
+// np (<= P <= 64) contiguous spectra starting at pixel p0; a workgroup of NT threads.
 // Stage: the np*L contiguous input floats are copied into padded LDS rows (float4 loads
 // when L % 4 == 0), with the circular extension.  Compute: lane = pixel, wavefront w takes
-// outputs k = w, w + 4, ..., so k (and every coefficient address) is uniform across the
+// outputs k = w, w + NT/64, ..., so k (and every coefficient address) is uniform across the
 // wavefront, and a lane reads W consecutive samples of its own row (odd stride: no bank
 // conflicts; constant offsets).  FP64 accumulation.  Write-out: the np*L' outputs leave
 // through padded LDS rows as one contiguous store.
 // magic_L = ceil(2^32 / L), magic_Lp = ceil(2^32 / L'): exact quotients for t < 64 L.
-template <int VEC>
+template <int VEC, int NT = 256>
 __device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p0, int np, int L, int Lp,
                                        int W, const double *__restrict__ coef,
                                        const int32_t *__restrict__ start, uint32_t magic_L,
@@ -129,16 +129,16 @@ __device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p
         const int nv = total >> 2;
         const float4 *s4 = reinterpret_cast<const float4 *>(src);
         // four loads per thread in flight: unconditional (index clamped), then the stores
-        for (int v0 = 0; v0 < nv; v0 += 4 * 256) {
+        for (int v0 = 0; v0 < nv; v0 += 4 * NT) {
             float4 qs[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int v = v0 + 256 * u + tid;
+                const int v = v0 + NT * u + tid;
                 qs[u] = s4[v < nv ? v : nv - 1];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int v = v0 + 256 * u + tid;
+                const int v = v0 + NT * u + tid;
                 if (v >= nv) continue;
                 const float4 q = qs[u];
                 const uint32_t e = 4u * (uint32_t)v;
@@ -159,8 +159,34 @@ __device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p
             }
         }
     } else {
-#pragma unroll 4
-        for (int t = tid; t < total; t += 256) {
+        // L not a multiple of 4: the tile's np*L floats are still contiguous and start on a
+        // 16-byte boundary (P is a multiple of 4), so they load as float4 and each element
+        // finds its own row; the last total % 4 floats load one by one
+        const int nv = total >> 2;
+        const float4 *s4 = reinterpret_cast<const float4 *>(src);
+        for (int v0 = 0; v0 < nv; v0 += 4 * NT) {
+            float4 qs[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = v0 + NT * u + tid;
+                qs[u] = s4[v < nv ? v : (nv > 0 ? nv - 1 : 0)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = v0 + NT * u + tid;
+                if (v >= nv) continue;
+                const float qq[4] = {qs[u].x, qs[u].y, qs[u].z, qs[u].w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t e = 4u * (uint32_t)v + (uint32_t)j;
+                    const uint32_t r = __umulhi(e, magic_L);
+                    const uint32_t col = e - r * (uint32_t)L;
+                    xs[r * LDP + col] = qq[j];
+                    if (col < ext) xs[r * LDP + col + L] = qq[j];
+                }
+            }
+        }
+        for (int t = 4 * nv + tid; t < total; t += NT) {
             const uint32_t r = __umulhi((uint32_t)t, magic_L);
             const uint32_t col = (uint32_t)t - r * (uint32_t)L;
             const float v = src[t];
@@ -172,7 +198,7 @@ __device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p
 
     if (lane < np) {
         const float *xp = xs + lane * LDP;
-        for (int k = wave; k < Lp; k += 4) {
+        for (int k = wave; k < Lp; k += NT / 64) {
             const double *c = coef + (size_t)k * W;
             const float *xk = xp + start[k];
             double a0 = 0.0, a1 = 0.0;
@@ -193,7 +219,7 @@ __device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p
     float *dst = out + p0 * (int64_t)Lp;
     const int ototal = np * Lp;
 #pragma unroll 4
-    for (int t = tid; t < ototal; t += 256) {
+    for (int t = tid; t < ototal; t += NT) {
         const uint32_t r = __umulhi((uint32_t)t, magic_Lp);
         dst[t] = os[r * LDO + ((uint32_t)t - r * (uint32_t)Lp)];
     }

@@ -484,29 +484,33 @@ __global__ __launch_bounds__(256) void dwt_cascade_kernel(const float *__restric
 // ------------------------------------------------------------------------------------
 // device: banded equivalent-filter kernel (body in dev_dwt.hpp)
 // ------------------------------------------------------------------------------------
-template <int VEC>
-__global__ __launch_bounds__(256) void dwt_banded_kernel(const float *__restrict__ cube, int64_t npix, int L,
-                                                         int Lp, int W, const double *__restrict__ coef,
-                                                         const int32_t *__restrict__ start, uint32_t magic_L,
-                                                         uint32_t magic_Lp, int P, float *__restrict__ out)
+template <int VEC, int NT>
+__global__ __launch_bounds__(NT) void dwt_banded_kernel(const float *__restrict__ cube, int64_t npix, int L,
+                                                        int Lp, int W, const double *__restrict__ coef,
+                                                        const int32_t *__restrict__ start, uint32_t magic_L,
+                                                        uint32_t magic_Lp, int P, float *__restrict__ out)
 {
     extern __shared__ float ldsf[];
     const int64_t p0 = (int64_t)blockIdx.x * P;
     const int np = (int)((npix - p0) < P ? (npix - p0) : P);
-    dwt_banded_tile<VEC>(cube, p0, np, L, Lp, W, coef, start, magic_L, magic_Lp, out, ldsf, P);
+    dwt_banded_tile<VEC, NT>(cube, p0, np, L, Lp, W, coef, start, magic_L, magic_Lp, out, ldsf, P);
 }
 
 // ceil(2^32 / d) for d >= 2 (the banded path has L >= L' >= 2 whenever it runs)
 static uint32_t magic_u32(int64_t d) { return (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d); }
 
-// Pixels per banded tile: at most 32 and as many as fit 40 KiB of LDS, so that four
-// workgroups share a CU and one workgroup's staging overlaps another's FP64 loop (measured
-// at 2048 x 2048 x 224: 32-pixel tiles beat 64-pixel tiles by 10-30 %); a multiple of 4 so
-// float4 staging stays aligned.
-static int banded_pixels(int64_t L, int64_t Lp, int64_t W)
+// Pixels per banded tile and threads per workgroup.  Wide form (g_dwt_banded_wide): up to 64
+// pixels (every lane of a wavefront busy in the FP64 loop) and 512 threads, in at most
+// 80 KiB of LDS, two workgroups per CU.  Narrow form: up to 32 pixels in 40 KiB with 256
+// threads, four workgroups per CU (32-pixel tiles beat 64-pixel tiles of 256 threads by
+// 10-30 % at 2048 x 2048 x 224).  A multiple of 4 so float4 staging stays aligned.
+static int g_dwt_banded_wide = 1;
+
+static int banded_pixels(int64_t L, int64_t Lp, int64_t W, int wide)
 {
-    int64_t P = (40 * 1024 / 4) / (((L + W - 1) | 1) + (Lp | 1));
-    if (P > 32) P = 32;
+    int64_t P = ((wide ? 80 : 40) * 1024 / 4) / (((L + W - 1) | 1) + (Lp | 1));
+    const int64_t cap = wide ? 64 : 32;
+    if (P > cap) P = cap;
     P &= ~(int64_t)3;
     return (int)P;
 }
@@ -583,17 +587,25 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
     BandedCoefs bc;
     int bP = 0;
     if (g_dwt_force != 0 && g_dwt_force != 1 && g_dwt_force != 2 && L < 8192 &&
-        Lp >= 2 && banded_coefs(L, levels, Lp, 128, s, &bc) && (bP = banded_pixels(L, Lp, bc.W)) >= 4) {
+        Lp >= 2 && banded_coefs(L, levels, Lp, 128, s, &bc) && (bP = banded_pixels(L, Lp, bc.W, 0)) >= 4) {
+        int wide = g_dwt_banded_wide;
+        if (wide) {
+            const int bw = banded_pixels(L, Lp, bc.W, 1);
+            if (bw > bP) bP = bw;
+            else wide = 0;
+        }
         const size_t sh = (size_t)dwt_banded_lds_floats(L, Lp, bc.W, bP) * sizeof(float);
-        const void *kern = (L % 4 == 0) ? (const void *)dwt_banded_kernel<4> : (const void *)dwt_banded_kernel<1>;
+        const void *kern = wide ? ((L % 4 == 0) ? (const void *)dwt_banded_kernel<4, 512> : (const void *)dwt_banded_kernel<1, 512>)
+                                : ((L % 4 == 0) ? (const void *)dwt_banded_kernel<4, 256> : (const void *)dwt_banded_kernel<1, 256>);
         if (int rc = allow_lds(kern, sh, "dwt_banded_kernel")) return rc;
-        dim3 grid((unsigned)((npix + bP - 1) / bP)), block(256);
-        if (L % 4 == 0)
-            hipLaunchKernelGGL(dwt_banded_kernel<4>, grid, block, sh, s, cube, npix, (int)L, (int)Lp, bc.W, bc.coef,
-                               bc.start, magic_u32(L), magic_u32(Lp), bP, approx);
-        else
-            hipLaunchKernelGGL(dwt_banded_kernel<1>, grid, block, sh, s, cube, npix, (int)L, (int)Lp, bc.W, bc.coef,
-                               bc.start, magic_u32(L), magic_u32(Lp), bP, approx);
+        int Li = (int)L, Lpi = (int)Lp, Wi = bc.W;
+        uint32_t mL = magic_u32(L), mLp = magic_u32(Lp);
+        const double *cf = bc.coef;
+        const int32_t *st = bc.start;
+        void *args[] = {(void *)&cube, &npix, &Li, &Lpi, &Wi, (void *)&cf, (void *)&st, &mL, &mLp, &bP, &approx};
+        if (hipLaunchKernel(kern, dim3((unsigned)((npix + bP - 1) / bP)), dim3(wide ? 512 : 256), args, sh, s) !=
+            hipSuccess)
+            return fail(HSAD_EHIP, "dwt_banded_kernel: launch failed");
         return check_launch("dwt_banded_kernel");
     }
     // cascade: size the pixel tile so that both ping-pong buffers fit in 64 KiB of LDS
@@ -612,6 +624,12 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
 }
 
 }  // namespace hsad
+
+extern "C" int hsad_internal_dwt_banded_wide(int wide)
+{
+    hsad::g_dwt_banded_wide = wide != 0;
+    return 0;
+}
 
 extern "C" int hsad_internal_dwt_force(int mode)
 {

@@ -52,8 +52,14 @@ def test_dwt_equivalent_filter_and_cascade_agree(L, levels):
         for mode, name in [(0, "cascade"), (1, "equiv_lds"), (2, "equiv_lane"), (3, "banded"), (-1, "auto")]:
             L_.hsad_internal_dwt_force(mode)
             outs[name] = _gpu_dwt(s.cube, levels)
+        # the banded kernel's narrow form (32-pixel tiles, 256 threads) beside the wide one
+        L_.hsad_internal_dwt_force(3)
+        L_.hsad_internal_dwt_banded_wide(0)
+        outs["banded_narrow"] = _gpu_dwt(s.cube, levels)
     finally:
+        L_.hsad_internal_dwt_banded_wide(1)
         L_.hsad_internal_dwt_force(-1)
+    assert np.array_equal(outs["banded"], outs["banded_narrow"])
     for name, got in outs.items():
         e = dwt_rel_err(got, ref)
         print("  ", name, e, flush=True)
