@@ -154,6 +154,7 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_feat_cfg", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwt_nt", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwest_solver", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_dwest_lanes", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwest_stats", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_chol_cb", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_gram_wg", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),

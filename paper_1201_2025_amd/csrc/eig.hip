@@ -6,7 +6,7 @@
 // DWEST needs the eigenvalues of C_diff and the projections y_i = v_i^T m_diff, never the
 // eigenvectors themselves.  Every orthogonal similarity applied to C_diff is therefore
 // also applied to m_diff, as a vector:
-//   1. tridiag_dwest_kernel (one wavefront per pixel, the matrix in LDS, lane = row):
+//   1. tridiag_dwest_kernel (16, 32 or 64 lanes per pixel, the matrix in LDS, lane = row):
 //      n-2 Householder reflections H_k = I - beta v v^T, each annihilating column k below
 //      the subdiagonal, give T = Q^T C_diff Q tridiagonal and y = Q^T m_diff.  Per step:
 //      p = beta A v, q = p - (beta/2)(v^T p) v, A <- A - v q^T - q v^T on the trailing
@@ -39,10 +39,29 @@ namespace hsad {
 
 __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
 
-// One wavefront per pixel; rows i = lane, lane + 64, ...  The symmetric matrix is kept as its
-// packed lower triangle (row i at tri(i)): half the LDS of a square, so twice the pixels
-// per CU.  Element (i, j) of the trailing block is read at tri(max) + min; the rank-2 update
-// writes the lower triangle only (a predicated store after an unconditional read).
+// Sum over the G lanes of a lane group (G = 16, 32 or 64, aligned), the same value in every
+// lane of the group: DPP within rows of 16, then one exchange between the two rows of a
+// 32-lane group, or wave_sum64 for the whole wavefront.
+template <int G> __device__ __forceinline__ double group_sum(double v)
+{
+    if constexpr (G == 64) {
+        return wave_sum64(v);
+    } else {
+        v += dpp_f64<0xB1>(v);
+        v += dpp_f64<0x4E>(v);
+        v += dpp_f64<0x141>(v);
+        v += dpp_f64<0x140>(v);
+        if constexpr (G == 32) v += __shfl_xor(v, 16, 64);
+        return v;
+    }
+}
+
+// G lanes per pixel (64 / G pixels per 64-thread workgroup); rows i = gl, gl + G, ... of the
+// group's pixel.  The symmetric matrix is kept as its packed lower triangle (row i at
+// tri(i)): half the LDS of a square.  Element (i, j) of the trailing block is read at
+// tri(max) + min; the rank-2 update writes the lower triangle only (a predicated store after
+// an unconditional read).  A column that is already reduced takes no reflection (beta = 0,
+// v = 0: every update adds exact zeros), so the groups of a wavefront stay in step.
 // With dey set, d, e and y go to dey[i * S], dey[(n + i) * S] and dey[(2n + i) * S] (dey is
 // offset to the pixel's column, S the column count), else to the pixel's workspace.
 // rec_stride: doubles per pixel record.  raw = 0: a Gram record (rows 0..n-1 = C_diff,
@@ -50,41 +69,44 @@ __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
 // annulus moments R (j >= i), row n+1 m = m_inner - mu_ann, row n+2 mu_ann, rows n+3..2n+2
 // the inner moments R_in (j >= i), all of f = x - ref): C_diff = (R_in - mu_in mu_in^T) -
 // (R - mu_ann mu_ann^T) with mu_in = m + mu_ann, and m_diff = m.
+template <int G>
 __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ ws, int n, int npix,
                                                            double *__restrict__ dey, int64_t S,
                                                            int64_t rec_stride, int raw)
 {
     extern __shared__ double sm[];
-    double *A = sm;                       // packed lower triangle, tri(n) doubles
+    const int lane = threadIdx.x, grp = lane / G, gl = lane - grp * G;
+    const int per = tri(n) + 3 * n;
+    double *A = sm + (size_t)grp * per;   // packed lower triangle, tri(n) doubles
     double *v = A + tri(n);               // n (Householder vector; entries <= k unused)
     double *q = v + n;                    // n
     double *y = q + n;                    // n
-    const int lane = threadIdx.x;
-    const int local = blockIdx.x;
-    if (local >= npix) return;
+    const int want = blockIdx.x * (64 / G) + grp;
+    const bool active = want < npix;
+    const int local = active ? want : npix - 1;   // an idle group repeats a pixel, writes nothing
     double *pix = ws + (size_t)local * rec_stride;
 
     // load: unconditional reads (index clamped) four at a time, predicated LDS stores
     const int nn = n * n;
     if (!raw) {
-        for (int t0 = 0; t0 < nn; t0 += 4 * 64) {
+        for (int t0 = 0; t0 < nn; t0 += 4 * G) {
             double val[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int t = t0 + 64 * u + lane;
+                const int t = t0 + G * u + gl;
                 val[u] = pix[t < nn ? t : nn - 1];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int t = t0 + 64 * u + lane;
+                const int t = t0 + G * u + gl;
                 const int i = t / n, j = t - i * n;
                 if (t < nn && j <= i) A[tri(i) + j] = val[u];
             }
         }
-        for (int i = lane; i < n; i += 64) y[i] = pix[(size_t)n * n + i];
+        for (int i = gl; i < n; i += G) y[i] = pix[(size_t)n * n + i];
     } else {
         // v <- mu_ann, q <- mu_in, y <- m first; then the upper triangles of R and R_in
-        for (int i = lane; i < n; i += 64) {
+        for (int i = gl; i < n; i += G) {
             const double m = pix[(size_t)(n + 1) * n + i], mu = pix[(size_t)(n + 2) * n + i];
             v[i] = mu;
             q[i] = m + mu;
@@ -92,17 +114,17 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
         }
         __syncthreads();
         const double *rin = pix + (size_t)(n + 3) * n;
-        for (int t0 = 0; t0 < nn; t0 += 2 * 64) {
+        for (int t0 = 0; t0 < nn; t0 += 2 * G) {
             double ra[2], ri[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const int t = t0 + 64 * u + lane, tc = t < nn ? t : nn - 1;
+                const int t = t0 + G * u + gl, tc = t < nn ? t : nn - 1;
                 ra[u] = pix[tc];
                 ri[u] = rin[tc];
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const int t = t0 + 64 * u + lane;
+                const int t = t0 + G * u + gl;
                 const int r = t / n, c = t - r * n;   // stored at (r, c), c >= r: element (c, r)
                 if (t < nn && c >= r)
                     A[tri(c) + r] = (ri[u] - q[r] * q[c]) - (ra[u] - v[r] * v[c]);
@@ -114,17 +136,17 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
     for (int k = 0; k + 2 < n; ++k) {
         // column k below the diagonal: x = A[k+1.., k]
         double s2 = 0.0;
-        for (int i = k + 1 + lane; i < n; i += 64) s2 += A[tri(i) + k] * A[tri(i) + k];
-        s2 = wave_sum64(s2);
+        for (int i = k + 1 + gl; i < n; i += G) s2 += A[tri(i) + k] * A[tri(i) + k];
+        s2 = group_sum<G>(s2);
         const double x0 = A[tri(k + 1) + k];
-        if (s2 - x0 * x0 == 0.0) continue;    // already reduced: e_k = x0, no reflection
+        const bool refl = s2 - x0 * x0 != 0.0;   // else already reduced: e_k = x0
         const double alpha = x0 >= 0.0 ? -sqrt(s2) : sqrt(s2);
-        const double beta = 1.0 / (alpha * (alpha - x0));   // 2 / v^T v
-        for (int i = k + 1 + lane; i < n; i += 64) v[i] = i == k + 1 ? x0 - alpha : A[tri(i) + k];
+        const double beta = refl ? 1.0 / (alpha * (alpha - x0)) : 0.0;   // 2 / v^T v
+        for (int i = k + 1 + gl; i < n; i += G) v[i] = !refl ? 0.0 : i == k + 1 ? x0 - alpha : A[tri(i) + k];
         __syncthreads();
         // p = beta A' v on the trailing block; K = (beta/2) v^T p; q = p - K v
         double vp = 0.0, vy = 0.0;
-        for (int i = k + 1 + lane; i < n; i += 64) {
+        for (int i = k + 1 + gl; i < n; i += G) {
             const int ti = tri(i);
             double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;   // four chains hide the FMA latency
             int j = k + 1;
@@ -145,17 +167,17 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
             vp = fma(v[i], p, vp);
             vy = fma(v[i], y[i], vy);
         }
-        vp = wave_sum64(vp);
-        vy = wave_sum64(vy);
+        vp = group_sum<G>(vp);
+        vy = group_sum<G>(vy);
         const double K = 0.5 * beta * vp, gam = beta * vy;
-        for (int i = k + 1 + lane; i < n; i += 64) {
+        for (int i = k + 1 + gl; i < n; i += G) {
             q[i] = fma(-K, v[i], q[i]);
             y[i] = fma(-gam, v[i], y[i]);
         }
         __syncthreads();
         // A' <- A' - v q^T - q v^T on the lower triangle (j <= i).  tri(i) + j stays inside
         // the packed array for j < n; past the row's end it is read and left alone.
-        for (int i = k + 1 + lane; i < n; i += 64) {
+        for (int i = k + 1 + gl; i < n; i += G) {
             double *row = A + tri(i);
             const double vi = v[i], qi = q[i];
 #pragma unroll 4
@@ -165,22 +187,24 @@ __global__ __launch_bounds__(64) void tridiag_dwest_kernel(double *__restrict__ 
             }
         }
         // column k itself becomes alpha e_1 (only the subdiagonal is read later)
-        if (lane == 0) A[tri(k + 1) + k] = alpha;
+        if (gl == 0 && refl) A[tri(k + 1) + k] = alpha;
         __syncthreads();
     }
     // d, e, y -> the start of the pixel's workspace (the matrix is in LDS now), or to the
     // pixel's column of dey
-    for (int i = lane; i < n; i += 64) {
-        const double di = A[tri(i) + i], ei = i + 1 < n ? A[tri(i + 1) + i] : 0.0;
-        if (dey) {
-            double *c = dey + local;
-            c[(int64_t)i * S] = di;
-            c[(int64_t)(n + i) * S] = ei;
-            c[(int64_t)(2 * n + i) * S] = y[i];
-        } else {
-            pix[i] = di;
-            pix[n + i] = ei;
-            pix[2 * n + i] = y[i];
+    if (active) {
+        for (int i = gl; i < n; i += G) {
+            const double di = A[tri(i) + i], ei = i + 1 < n ? A[tri(i + 1) + i] : 0.0;
+            if (dey) {
+                double *c = dey + local;
+                c[(int64_t)i * S] = di;
+                c[(int64_t)(n + i) * S] = ei;
+                c[(int64_t)(2 * n + i) * S] = y[i];
+            } else {
+                pix[i] = di;
+                pix[n + i] = ei;
+                pix[2 * n + i] = y[i];
+            }
         }
     }
 }
@@ -372,13 +396,22 @@ static int ql_pixels(int64_t n)
 
 int ql_lds_pixels(int64_t n) { return ql_pixels(n); }
 
+// lanes per pixel of the tridiagonalisation: the smallest group of 16, 32 or 64 lanes that
+// holds one row per lane (0: chosen by L'; tests force a size through hsad_internal_dwest_lanes)
+static int g_tridiag_lanes = 0;
+
 int tridiag_dwest_launch(double *ws, int64_t n, int npix, double *dey, int64_t S, hipStream_t s, int raw)
 {
-    const size_t sh = eig_smem(n);
-    if (int rc = allow_lds((const void *)tridiag_dwest_kernel, sh, "tridiag_dwest_kernel")) return rc;
-    const int64_t stride = raw ? (int64_t)((2 * n + 3) * n) : (int64_t)((n + 2) * n);
-    hipLaunchKernelGGL(tridiag_dwest_kernel, dim3((unsigned)npix), dim3(64), sh, s, ws, (int)n, npix, dey, S, stride,
-                       raw);
+    const int G = g_tridiag_lanes ? g_tridiag_lanes : n <= 16 ? 16 : n <= 32 ? 32 : 64;
+    const size_t sh = eig_smem(n) * (size_t)(64 / G);
+    const void *k = G == 16 ? (const void *)tridiag_dwest_kernel<16>
+                    : G == 32 ? (const void *)tridiag_dwest_kernel<32> : (const void *)tridiag_dwest_kernel<64>;
+    if (int rc = allow_lds(k, sh, "tridiag_dwest_kernel")) return rc;
+    int64_t stride = raw ? (int64_t)((2 * n + 3) * n) : (int64_t)((n + 2) * n);
+    int ni = (int)n;
+    void *args[] = {(void *)&ws, &ni, &npix, (void *)&dey, &S, &stride, &raw};
+    if (hipLaunchKernel(k, dim3((unsigned)((npix + 64 / G - 1) / (64 / G))), dim3(64), args, sh, s) != hipSuccess)
+        return fail(HSAD_EHIP, "tridiag_dwest_kernel: launch failed");
     return check_launch("tridiag_dwest_kernel");
 }
 
@@ -403,3 +436,10 @@ int eig_dwest_launch(double *ws, int64_t n, int npix, int64_t pix0, float *score
 }
 
 }  // namespace hsad
+
+extern "C" int hsad_internal_dwest_lanes(int g)
+{
+    if (g != 0 && g != 16 && g != 32 && g != 64) return HSAD_EINVAL;
+    hsad::g_tridiag_lanes = g;
+    return 0;
+}

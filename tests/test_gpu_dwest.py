@@ -81,6 +81,28 @@ def test_dwest_full_size_sampled(levels):
     assert np.array_equal(gn.cpu().numpy().ravel()[idx], rn)
 
 
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+@pytest.mark.parametrize("levels,stats", [(5, 0), (4, 0), (4, 1), (3, 0)])
+def test_dwest_tridiag_lane_groups(lanes, levels, stats):
+    # 16, 32 or 64 lanes per pixel in the tridiagonalisation (4, 2 or 1 pixels per
+    # wavefront) at L' = 7, 14 and 28; 13 x 11 = 143 pixels leave idle groups in the last
+    # workgroup
+    s = scene(500 + levels, 13, 11, 224)
+    x = oracle.dwt_approx(s.cube, levels).astype(np.float32)
+    L_ = hs.lib()
+    try:
+        assert L_.hsad_internal_dwest_lanes(lanes) == 0
+        L_.hsad_internal_dwest_stats(stats)
+        gs, gl, gn = _gpu(x, 3, 9)
+    finally:
+        L_.hsad_internal_dwest_lanes(0)
+        L_.hsad_internal_dwest_stats(0)
+    rs, rl, rn = oracle.dwest(x.astype(np.float64), 3, 9)
+    assert np.array_equal(gn, rn)
+    assert score_rel_err(gs, rs).max() <= TOL
+    assert score_rel_err(gl, rl).max() <= TOL
+
+
 def test_dwest_degenerate_and_short_spectra(solver):
     # L' = 1 and 2 (no reflection), a constant cube (C_diff = 0: no positive eigenvalue,
     # score 0) and a cube constant in one band
