@@ -683,13 +683,12 @@ def main():
     th_out = torch.empty(4, dtype=torch.float64, device=dev)
 
     def step(i, ev=None):
-        # ev: events around the DWT, whose launch duration the roofline needs (each event
-        # adds a few microseconds to the step, so there are no others in the timed region)
+        # ev: two events that the DWT's kernel dispatch itself records at its start and end
+        # (hsad_dwt_timed), whose difference is the launch duration the roofline needs
         if ev is not None:
-            ev[0].record()
-        hs.hsad_dwt(cubes[i & 1], J, out=approx)
-        if ev is not None:
-            ev[1].record()
+            hs.hsad_dwt_timed(cubes[i & 1], J, ev[0], ev[1], out=approx)
+        else:
+            hs.hsad_dwt(cubes[i & 1], J, out=approx)
         # LRX + DWRX, then eq. (12) on the LRX map and the mask, in one library call
         hs.hsad_detect(approx, inner, outer, load, 3.0, lrx=lrx, dwrx=dwrx, stats=th_out, mask=mask,
                        ws=det_ws)
@@ -697,12 +696,14 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    # the DWT's launch duration (roofline) comes from events around the DWT of every
-    # EV_EVERY-th timed step: an event pair costs a few microseconds of pipeline drain, so
-    # bracketing every step would make every step slower than it is
+    # the DWT's launch duration (roofline) comes from the events that the DWT's dispatch
+    # records in every EV_EVERY-th timed step
     EV_EVERY = 10
     evs = {i: [torch.cuda.Event(enable_timing=True) for _ in range(2)]
            for i in range(args.steps) if i % EV_EVERY == 0}
+    for pair in evs.values():      # torch creates an event on its first record: before the timing
+        for e in pair:
+            e.record()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -719,6 +720,9 @@ def main():
     # the detection call's share, from a separate instrumented pass (not the timed region)
     nsplit = min(args.steps, 50)
     sev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nsplit)]
+    for trip in sev:
+        for e in trip:
+            e.record()
     for i in range(nsplit):
         step(i, sev[i])
         sev[i][2].record()

@@ -110,6 +110,15 @@ int hsad_levels_for(int64_t L, int target);
 int hsad_dwt(const float *cube, int64_t H, int64_t W, int64_t L, int levels, float *approx,
              hipStream_t stream);
 
+/* hsad_dwt, and two caller-created events (hipEventCreate, timing enabled; either may be
+ * NULL) that the transform's kernel dispatch records at its start and its end
+ * (hipExtLaunchKernel), so that the kernel's own duration can be read with
+ * hipEventElapsedTime without event records around the call, which wait for the work
+ * before them.  For callers that time the transform, as a benchmark does.  levels = 0 (a
+ * copy) leaves the events untouched.  Errors as hsad_dwt. */
+int hsad_dwt_timed(const float *cube, int64_t H, int64_t W, int64_t L, int levels, float *approx,
+                   hipStream_t stream, hipEvent_t start, hipEvent_t stop);
+
 /* ---------------------------------------------------------------------------------------
  * Full transform: approximation and every detail band (Sec. 3, Fig. 1), its inverse, and
  * the Daubechies family of any order (Fig. 2 shows the db16 scaling function)

@@ -83,6 +83,7 @@ SIGNATURES = [
     ("hsad_dwt_out_len", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(_i64)]),
     ("hsad_levels_for", ctypes.c_int, [_i64, ctypes.c_int]),
     ("hsad_dwt", ctypes.c_int, [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp]),
+    ("hsad_dwt_timed", ctypes.c_int, [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp]),
     ("hsad_wavelet_filter", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     ("hsad_dwt_full_len", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(_i64)]),
     ("hsad_dwt_full", ctypes.c_int, [_vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp]),
@@ -272,6 +273,28 @@ def hsad_dwt(cube, levels: int, out=None, stream=None):
     if out.numel() != H * W * Lp:
         raise ValueError("out must hold H*W*L' values")
     _check("hsad_dwt", lib().hsad_dwt(pc, H, W, L, int(levels), po, _stream(stream)))
+    return out
+
+
+def hsad_dwt_timed(cube, levels: int, start, stop, out=None, stream=None):
+    """hsad_dwt whose kernel dispatch records its start and end in two timing events
+    (torch.cuda.Event(enable_timing=True); either may be None; an event that torch has not
+    created yet is recorded once first)."""
+    torch = _torch()
+    pc = _dev(cube, "cube", torch.float32, 3)
+    H, W, L = cube.shape
+    Lp = hsad_dwt_out_len(L, levels)
+    if out is None:
+        out = torch.empty((H, W, Lp), dtype=torch.float32, device=cube.device)
+    po = _dev(out, "out", torch.float32)
+    if out.numel() != H * W * Lp:
+        raise ValueError("out must hold H*W*L' values")
+    ev = []
+    for e in (start, stop):
+        if e is not None and e.cuda_event == 0:
+            e.record()          # torch creates its event on the first record
+        ev.append(ctypes.c_void_p(e.cuda_event) if e is not None else ctypes.c_void_p(None))
+    _check("hsad_dwt_timed", lib().hsad_dwt_timed(pc, H, W, L, int(levels), po, _stream(stream), ev[0], ev[1]))
     return out
 
 

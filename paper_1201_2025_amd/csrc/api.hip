@@ -227,6 +227,19 @@ int hsad_dwt(const float *cube, int64_t H, int64_t W, int64_t L, int levels, flo
     return dwt_launch(cube, H * W, L, levels, Lp, approx, stream);
 }
 
+int hsad_dwt_timed(const float *cube, int64_t H, int64_t W, int64_t L, int levels, float *approx,
+                   hipStream_t stream, hipEvent_t start, hipEvent_t stop)
+{
+    clear_error();
+    if (!cube || !approx) return fail(HSAD_EINVAL, "hsad_dwt_timed: NULL pointer");
+    if (H < 1 || W < 1) return fail(HSAD_EINVAL, "hsad_dwt_timed: H and W must be >= 1");
+    int64_t Lp = 0;
+    if (out_len(L, levels, &Lp))
+        return fail(HSAD_EINVAL, "hsad_dwt_timed: L < 1, levels < 0 or levels too deep for L");
+    if (L > (1 << 20)) return fail(HSAD_EUNSUPPORTED, "hsad_dwt_timed: L above 2^20");
+    return dwt_launch(cube, H * W, L, levels, Lp, approx, stream, start, stop);
+}
+
 size_t hsad_workspace_bytes(int op, int64_t H, int64_t W, int64_t Lp,
                             const hsad_window_params *p)
 {

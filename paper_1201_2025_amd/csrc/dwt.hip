@@ -17,6 +17,7 @@
 //    LDS with coalesced loads, then runs the levels in LDS with ping-pong buffers.
 //    Each level is 8 taps per output; the workgroup barriers between levels.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstring>
 #include <map>
@@ -522,34 +523,35 @@ static int g_dwt_nt = 1;   // non-temporal cube loads in the LDS-staged kernel (
 
 template <int LP>
 static int launch_equiv(const float *cube, int64_t npix, int64_t L, const double *coef, int vec,
-                        bool lds, float *out, hipStream_t s)
+                        bool lds, float *out, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (lds) {
         dim3 grid((unsigned)((npix + kEqTP - 1) / kEqTP)), block(kEqTP);
         if (vec == 4 && g_dwt_nt)
-            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4, true>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+            hipExtLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4, true>), grid, block, 0, s, e0, e1, 0, cube, npix, (int)L, coef, out);
         else if (vec == 4)
-            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4, false>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+            hipExtLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 4, false>), grid, block, 0, s, e0, e1, 0, cube, npix, (int)L, coef, out);
         else
-            hipLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 1>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+            hipExtLaunchKernelGGL((dwt_equiv_lds_kernel<LP, 1>), grid, block, 0, s, e0, e1, 0, cube, npix, (int)L, coef, out);
         return check_launch("dwt_equiv_lds_kernel");
     }
     dim3 grid((unsigned)((npix + 255) / 256)), block(256);
     if (vec == 4)
-        hipLaunchKernelGGL((dwt_equiv_kernel<LP, 4>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+        hipExtLaunchKernelGGL((dwt_equiv_kernel<LP, 4>), grid, block, 0, s, e0, e1, 0, cube, npix, (int)L, coef, out);
     else if (vec == 2)
-        hipLaunchKernelGGL((dwt_equiv_kernel<LP, 2>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+        hipExtLaunchKernelGGL((dwt_equiv_kernel<LP, 2>), grid, block, 0, s, e0, e1, 0, cube, npix, (int)L, coef, out);
     else
-        hipLaunchKernelGGL((dwt_equiv_kernel<LP, 1>), grid, block, 0, s, cube, npix, (int)L, coef, out);
+        hipExtLaunchKernelGGL((dwt_equiv_kernel<LP, 1>), grid, block, 0, s, e0, e1, 0, cube, npix, (int)L, coef, out);
     return check_launch("dwt_equiv_kernel");
 }
 
 static int launch_equiv_lp(int64_t Lp, const float *cube, int64_t npix, int64_t L,
-                           const double *coef, int vec, bool lds, float *out, hipStream_t s)
+                           const double *coef, int vec, bool lds, float *out, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1)
 {
     switch (Lp) {
 #define HSAD_EQ_CASE(n) \
-    case n: return launch_equiv<n>(cube, npix, L, coef, vec, lds, out, s);
+    case n: return launch_equiv<n>(cube, npix, L, coef, vec, lds, out, s, e0, e1);
         HSAD_EQ_CASE(1) HSAD_EQ_CASE(2) HSAD_EQ_CASE(3) HSAD_EQ_CASE(4) HSAD_EQ_CASE(5)
         HSAD_EQ_CASE(6) HSAD_EQ_CASE(7) HSAD_EQ_CASE(8) HSAD_EQ_CASE(9) HSAD_EQ_CASE(10)
         HSAD_EQ_CASE(11) HSAD_EQ_CASE(12) HSAD_EQ_CASE(13) HSAD_EQ_CASE(14) HSAD_EQ_CASE(15)
@@ -564,7 +566,7 @@ static int launch_equiv_lp(int64_t Lp, const float *cube, int64_t npix, int64_t 
 static int g_dwt_force = -1;
 
 int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t Lp,
-               float *approx, hipStream_t s)
+               float *approx, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (npix == 0) return HSAD_OK;
     if (levels == 0) {
@@ -580,7 +582,7 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
         const int vec = lds ? 1 : ((L % 4 == 0) ? 4 : ((L % 2 == 0) ? 2 : 1));
         const int ldvec = (L % 4 == 0) ? 4 : 1;
         const double *coef = composite_coefs(L, levels, Lp, vec, s);
-        if (coef) return launch_equiv_lp(Lp, cube, npix, L, coef, lds ? ldvec : vec, lds, approx, s);
+        if (coef) return launch_equiv_lp(Lp, cube, npix, L, coef, lds ? ldvec : vec, lds, approx, s, e0, e1);
     }
     // banded equivalent filter for longer outputs (each output reads <= 7 (2^J - 1) + 1
     // samples); the cascade remains for very long spectra and as a fallback
@@ -603,7 +605,8 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
         const double *cf = bc.coef;
         const int32_t *st = bc.start;
         void *args[] = {(void *)&cube, &npix, &Li, &Lpi, &Wi, (void *)&cf, (void *)&st, &mL, &mLp, &bP, &approx};
-        if (hipLaunchKernel(kern, dim3((unsigned)((npix + bP - 1) / bP)), dim3(wide ? 512 : 256), args, sh, s) !=
+        if (hipExtLaunchKernel(kern, dim3((unsigned)((npix + bP - 1) / bP)), dim3(wide ? 512 : 256), args, sh, s, e0,
+                               e1, 0) !=
             hipSuccess)
             return fail(HSAD_EHIP, "dwt_banded_kernel: launch failed");
         return check_launch("dwt_banded_kernel");
@@ -618,7 +621,7 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
     for (int t = 0; t < 8; ++t) taps.h[t] = h[t];
     const size_t shmem = (size_t)(P * per_pix) * sizeof(double);
     dim3 grid((unsigned)((npix + P - 1) / P)), block(256);
-    hipLaunchKernelGGL(dwt_cascade_kernel, grid, block, shmem, s, cube, npix, (int)L, levels,
+    hipExtLaunchKernelGGL(dwt_cascade_kernel, grid, block, shmem, s, e0, e1, 0, cube, npix, (int)L, levels,
                        (int)Lp, (int)P, taps, approx);
     return check_launch("dwt_cascade_kernel");
 }

@@ -27,8 +27,9 @@ const double *db4_filter();
 // Lp x L, row-major, double.  Pushes unit vectors through the cascade with the
 // odd-length extension.
 void dwt_composite_matrix(int64_t L, int levels, double *A /* Lp*L */);
+// e0 / e1 (may be null): events that take the start and end of the transform's kernel
 int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t Lp,
-               float *approx, hipStream_t s);
+               float *approx, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // ---- window geometry ----
 struct Windows {

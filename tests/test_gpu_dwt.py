@@ -146,3 +146,26 @@ def test_graph_capture_on_unseen_shape(L, levels):
     import oracle
     r = oracle.dwt_approx(cube.cpu().numpy(), levels)
     assert dwt_rel_err(ref[0], r) <= 1e-5
+
+
+@pytest.mark.parametrize("L,levels", [(224, 6), (224, 2), (189, 3)])
+def test_dwt_timed_events(L, levels):
+    # hsad_dwt_timed: the same coefficients, and the kernel's own start / end in the events
+    # (inside the interval of event records around the call)
+    import torch
+    s = scene(80 + levels, 64, 48, L)
+    t = torch.from_numpy(s.cube).cuda()
+    a = hs.hsad_dwt(t, levels)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    o0, o1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    o0.record()
+    b = hs.hsad_dwt_timed(t, levels, e0, e1)
+    o1.record()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    k, outer = e0.elapsed_time(e1), o0.elapsed_time(o1)
+    print("dwt kernel %.1f us, event pair around the call %.1f us" % (k * 1e3, outer * 1e3), flush=True)
+    assert 0.0 < k <= outer
+    c = hs.hsad_dwt_timed(t, levels, None, None)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
