@@ -251,20 +251,24 @@ def test_end_to_end_dwt_lrx(cfg):
     assert np.array_equal(oracle.mask(gl, tau)[~band], oracle.mask(rl, tau)[~band])
 
 
-@pytest.mark.parametrize("levels", [6, 4, 3])
+@pytest.mark.parametrize("levels", [6, 4, 3, 2, 1, 0])
 def test_full_size_sampled_dwt_lrx(levels):
-    # 512 x 512 x 224 at the bench's launch configuration; the oracle scores a sample
+    # 512 x 512 x 224 at the bench's launch configuration (J = 2, 1: box statistics with the
+    # group / panel Cholesky; J = 0: the full band through the workgroup Gram and the blocked
+    # Cholesky in several chunks); the oracle scores a sample
     import torch
     from paper_1201_2025_amd import synth
     c = synth.CONFIGS["cube_512x512x224"]
     s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"],
                          n_blob=c["n_blob"])
     t = torch.from_numpy(s.cube).cuda()
-    a = hs.hsad_dwt(t, levels)
+    a = hs.hsad_dwt(t, levels) if levels else t
+    print("512x512x224 level", levels, flush=True)
     gl, gd = hs.hsad_lrx_dwrx(a, c["inner"], c["outer"], c["load_rel"])
     torch.cuda.synchronize()
-    idx = sample_pixels(512, 512, 1500 if levels == 6 else 400, seed=levels)
-    ra = oracle.dwt_approx(s.cube, levels)
+    n = {6: 1500, 4: 400, 3: 400, 2: 200, 1: 100, 0: 60}[levels]
+    idx = sample_pixels(512, 512, n, seed=levels)
+    ra = oracle.dwt_approx(s.cube, levels) if levels else s.cube.astype(np.float64)
     rl, rd = oracle.lrx_dwrx(ra, c["inner"], c["outer"], c["load_rel"], idx=idx)
     for g, r, nm in ((gl, rl, "lrx"), (gd, rd, "dwrx")):
         e = score_rel_err(g.cpu().numpy().ravel()[idx], r)
