@@ -27,9 +27,11 @@
 namespace hsad {
 
 // smallest tile count T = ceil(L'/16) that takes the workgroup-per-pixel FP64 Gram, and its
-// most accumulator tiles per wavefront and pass (tests choose through hsad_internal_gram_wg)
+// most accumulator tiles per wavefront and pass: 9, three waves per SIMD (at L' = 224 three
+// passes: 285.5 ms per full band against 298.8 with two passes of 14 at two waves per SIMD;
+// tests choose through hsad_internal_gram_wg)
 static int g_gram_wg_min_t = 6;
-static int g_gram_wg_tiles = 14;
+static int g_gram_wg_tiles = 9;
 
 template <int PREC, int kMaxTilesPerPass>
 __global__ __launch_bounds__(256) void gram_kernel(GramArgs a, int waves_per_block)
@@ -307,7 +309,7 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
         const int npass = (nper + g_gram_wg_tiles - 1) / g_gram_wg_tiles;
         const int need = (nper + npass - 1) / npass;
         const void *k = need <= 6    ? (const void *)gram_wg_kernel<6, 2>
-                        : need <= 9  ? (const void *)gram_wg_kernel<9, 2>
+                        : need <= 9  ? (const void *)gram_wg_kernel<9, 3>
                         : need <= 12 ? (const void *)gram_wg_kernel<12, 2>
                         : need <= 14 ? (const void *)gram_wg_kernel<14, 2>
                         : need <= 17 ? (const void *)gram_wg_kernel<17, 2>

@@ -341,7 +341,7 @@ def test_gram_step_against_window_stats(Lp, inner, outer, prec, tol):
 # (min_t 0); L' = 257 is past the workgroup kernel's band limit and takes the per-wavefront one
 @pytest.mark.parametrize("Lp,inner,outer", [(81, 5, 15), (100, 0, 9), (189, 3, 11), (224, 5, 15), (256, 1, 7),
                                             (257, 3, 9)])
-@pytest.mark.parametrize("min_t,tiles", [(6, 17), (6, 28), (6, 6), (0, 17)])
+@pytest.mark.parametrize("min_t,tiles", [(6, 9), (6, 14), (6, 17), (6, 28), (6, 6), (0, 17)])
 def test_workgroup_gram_step(Lp, inner, outer, min_t, tiles):
     import ctypes
     import torch
@@ -361,7 +361,7 @@ def test_workgroup_gram_step(Lp, inner, outer, min_t, tiles):
         assert rc == 0, hs.hsad_last_error()
         torch.cuda.synchronize()
     finally:
-        L_.hsad_internal_gram_wg(6, 14)
+        L_.hsad_internal_gram_wg(6, 9)
     g = ws.cpu().numpy().reshape(npix, Lp + 2, Lp)
     worst = 0.0
     for pix in range(npix):
@@ -411,7 +411,7 @@ def test_workgroup_gram_scores_match_per_wavefront_kernel():
         c, d = hs.hsad_lrx_dwrx(t, 5, 15, 1e-6)
         torch.cuda.synchronize()
     finally:
-        L_.hsad_internal_gram_wg(6, 14)
+        L_.hsad_internal_gram_wg(6, 9)
     for u, v in ((a, c), (b, d)):
         u, v = u.cpu().numpy().ravel().astype(np.float64), v.cpu().numpy().ravel().astype(np.float64)
         assert np.max(np.abs(u - v) / np.abs(v)) <= 1e-6
