@@ -159,6 +159,7 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_dwest_stats", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_chol_cb", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_gram_wg", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    ("hsad_internal_gram_means", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_chol_blk", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_boxg_rb", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_variant", ctypes.c_int, [ctypes.c_int, ctypes.c_int]),

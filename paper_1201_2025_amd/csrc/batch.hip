@@ -171,6 +171,7 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const SceneDev *__restr
         const SceneDev &s = sc[m.scene];
         if (wv < m.b) {
             GramArgs a;
+            a.means_ready = 0;
             a.x = s.approx;
             a.H = s.H;
             a.W = s.W;

@@ -25,6 +25,7 @@ struct GramArgs {
     double *ws;          // chunk workspace, (Lp+2)*Lp doubles per pixel
     uint32_t outer_magic;  // ceil(2^32 / outer) for k / outer
     const int32_t *idx;  // optional pixel list: pixel = idx[pix0 + local] (NULL: pix0 + local)
+    int means_ready;     // workgroup kernel: the means are already in rows L', L'+1 of each record
 };
 
 

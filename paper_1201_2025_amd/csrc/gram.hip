@@ -31,6 +31,8 @@ namespace hsad {
 // passes: 285.5 ms per full band against 298.8 with two passes of 14 at two waves per SIMD;
 // tests choose through hsad_internal_gram_wg)
 static int g_gram_wg_min_t = 6;
+// contiguous chunks take their means from gram_means_kernel (0: the kernel's own first pass)
+static int g_gram_means = 1;
 static int g_gram_wg_tiles = 9;
 
 template <int PREC, int kMaxTilesPerPass>
@@ -72,6 +74,39 @@ __host__ __device__ inline size_t gram_wg_lds_bytes(int K)
     const size_t nsg = ((size_t)(K + 3) / 4 + kWgGroups - 1) / kWgGroups;
     return ((size_t)2 * kWgMaxLpad + 8 * (size_t)kWgGroups * kWgStageLd) * sizeof(double) +
            (size_t)4 * kWgGroups * nsg * sizeof(int);
+}
+
+// FP64 annulus and inner-window means of the chunk's pixels pix0 .. pix0 + npix - 1, into
+// rows L' and L'+1 of each pixel's record (what the workgroup kernel's first pass computes,
+// as the plain sums of the definition: FP32 samples added in FP64).  One thread per (pixel,
+// band), bands fastest, so a wavefront's loads of a window sample are consecutive floats.
+__global__ __launch_bounds__(256) void gram_means_kernel(GramArgs a)
+{
+    const int64_t gt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int Lp = a.Lp;
+    if (gt >= (int64_t)a.npix * Lp) return;
+    const int local = (int)(gt / Lp), b = (int)(gt - (int64_t)local * Lp);
+    const int64_t pix = a.pix0 + local;
+    const int py = (int)(pix / a.W), px = (int)(pix - (int64_t)py * a.W);
+    const int y0 = py - a.R < 0 ? 0 : py - a.R, y1 = py + a.R > a.H - 1 ? a.H - 1 : py + a.R;
+    const int x0 = px - a.R < 0 ? 0 : px - a.R, x1 = px + a.R > a.W - 1 ? a.W - 1 : px + a.R;
+    double sa = 0.0, si = 0.0;
+    for (int y = y0; y <= y1; ++y) {
+        const bool iny = a.has_inner && y - py <= a.RI && py - y <= a.RI;
+        const float *row = a.x + (size_t)y * a.W * Lp + b;
+#pragma unroll 4
+        for (int xx = x0; xx <= x1; ++xx) {
+            const double v = (double)row[(size_t)xx * Lp];
+            const bool inn = iny && xx - px <= a.RI && px - xx <= a.RI;
+            sa += inn ? 0.0 : v;
+            si += inn ? v : 0.0;
+        }
+    }
+    const int n_o = clipn(py, a.R, a.H) * clipn(px, a.R, a.W);
+    const int n_i = a.has_inner ? clipn(py, a.RI, a.H) * clipn(px, a.RI, a.W) : 0;
+    double *out = a.ws + (size_t)local * (Lp + 2) * Lp;
+    out[(size_t)Lp * Lp + b] = sa / (double)(n_o - n_i);
+    out[(size_t)(Lp + 1) * Lp + b] = n_i > 0 ? si / (double)n_i : 0.0;
 }
 
 template <int MT, int WPE>
@@ -123,6 +158,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
     __syncthreads();
 
+    double *out = a.ws + (size_t)local * (Lp + 2) * Lp;
+    if (a.means_ready) {
+        // the means were written into rows L' (annulus) and L'+1 (inner window) beforehand
+        for (int b = tid; b < Lpad; b += 256) {
+            mu[b] = b < Lp ? out[(size_t)Lp * Lp + b] : 0.0;
+            mi[b] = b < Lp ? out[(size_t)(Lp + 1) * Lp + b] : 0.0;
+        }
+    } else {
     // pass 1: FP64 sums over the annulus and the inner window
     {
         double sa[NE], si[NE];
@@ -156,8 +199,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
         mu[b] = b < Lp ? sa / (double)n_a : 0.0;
         mi[b] = (b < Lp && n_i > 0) ? si / (double)n_i : 0.0;
     }
+    }
     __syncthreads();
-    double *out = a.ws + (size_t)local * (Lp + 2) * Lp;
     for (int b = tid; b < Lp; b += 256) {
         out[(size_t)Lp * Lp + b] = (double)a.x[(size_t)pix * Lp + b] - mu[b];
         out[(size_t)(Lp + 1) * Lp + b] = mi[b] - mu[b];
@@ -298,6 +341,7 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
     a.pix0 = pix0;
     a.npix = npix;
     a.ws = ws;
+    a.means_ready = 0;
     const uint32_t outer = (uint32_t)w.outer;
     a.outer_magic = (uint32_t)((((uint64_t)1 << 32) + outer - 1) / outer);
     const int T = (int)((Lp + 15) / 16);
@@ -316,6 +360,13 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
                         : need <= 22 ? (const void *)gram_wg_kernel<22, 1>
                                      : (const void *)gram_wg_kernel<28, 1>;
         if (int rc = allow_lds(k, shw, "gram_wg_kernel")) return rc;
+        if (!idx && g_gram_means) {
+            // contiguous chunk: the means by their own kernel, one thread per (pixel, band)
+            const int64_t nt = (int64_t)npix * Lp;
+            hipLaunchKernelGGL(gram_means_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, a);
+            if (int rc = check_launch("gram_means_kernel")) return rc;
+            a.means_ready = 1;
+        }
         void *args[] = {&a};
         if (hipLaunchKernel(k, dim3((unsigned)npix), dim3(256), args, shw, s) != hipSuccess)
             return fail(HSAD_EHIP, "gram_wg_kernel: launch failed");
@@ -357,6 +408,12 @@ int gram_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows 
 
 // min_t: smallest T = ceil(L'/16) taking the workgroup kernel (< 1: never); tiles: most
 // accumulator tiles per wavefront and pass (6..28)
+extern "C" int hsad_internal_gram_means(int on)
+{
+    hsad::g_gram_means = on != 0;
+    return 0;
+}
+
 extern "C" int hsad_internal_gram_wg(int min_t, int tiles)
 {
     if (tiles < 6 || tiles > 28) return HSAD_EINVAL;

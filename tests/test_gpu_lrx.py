@@ -399,6 +399,36 @@ def test_blocked_cholesky_matches_panel_kernel(Lp):
         assert np.max(np.abs(u - v) / np.abs(v)) <= 1e-6
 
 
+@pytest.mark.parametrize("Lp,inner,outer", [(100, 3, 11), (224, 5, 15), (189, 0, 9)])
+def test_workgroup_gram_means_kernel(Lp, inner, outer):
+    # the means from their own kernel (contiguous chunks) and from the Gram kernel's first
+    # pass: the same FP64 sums, so the same records to rounding
+    import ctypes
+    import torch
+    from paper_1201_2025_amd import synth
+    H, W = 11, 13
+    x = synth.random_cube(Lp + 7, H, W, Lp) * 0.1 + 1.0
+    t = torch.from_numpy(x).cuda()
+    npix = H * W
+    p = hs.WindowParams(inner, outer, 1e-6, 0, 0)
+    L_ = hs.lib()
+    recs = []
+    try:
+        for on in (1, 0):
+            L_.hsad_internal_gram_means(on)
+            ws = torch.zeros(npix * (Lp + 2) * Lp, dtype=torch.float64, device="cuda")
+            rc = L_.hsad_internal_gram(ctypes.c_void_p(t.data_ptr()), H, W, Lp, ctypes.byref(p), 0, 0,
+                                       0, npix, ctypes.c_void_p(ws.data_ptr()), None)
+            assert rc == 0, hs.hsad_last_error()
+            torch.cuda.synchronize()
+            recs.append(ws.cpu().numpy())
+    finally:
+        L_.hsad_internal_gram_means(1)
+    d = np.abs(recs[0] - recs[1]).max() / np.abs(recs[1]).max()
+    print("means kernel vs first pass: max difference %.3g" % d, flush=True)
+    assert d <= 1e-13
+
+
 def test_workgroup_gram_scores_match_per_wavefront_kernel():
     # the two FP64 Gram kernels give the same LRX / DWRX maps up to rounding order
     import torch
