@@ -9,6 +9,8 @@ namespace hsad {
 // Tiles are TXW x 16 output pixels (TXW = 16 or 32), one thread per pixel.  A wider tile
 // spends fewer halo columns per pixel (TXW + 2R columns of vertical sums for TXW outputs).
 constexpr int TY = 16;
+// largest inner half-width summed directly per pixel (box_tile)
+constexpr int kBoxDirectRI = 3;
 constexpr int RB = 4;                 // output rows per vertical-sum job
 constexpr int NRB = TY / RB;
 
@@ -254,6 +256,9 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
     const int ty = tid / TX, tx = tid - ty * TX;
     const int py = y0 + ty, px = x0 + tx;
 
+    // a small inner window (up to 7 x 7) is summed directly per output pixel from the staged
+    // tile after the outer window's box sums, instead of by two more rounds of box sums
+    const bool direct_inner = has_inner && RI <= kBoxDirectRI;
     double S[C::GT];        // annulus sums (outer minus inner)
     double sin_lin[LP];     // inner-window linear sums (DWRX mean)
     double in_bad = 0.0;
@@ -265,7 +270,7 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
 #pragma unroll
     for (int ch = 0; ch < C::NCH; ++ch) {
         const int g0 = ch * C::GC;
-        for (int win = has_inner ? 0 : 1; win < 2; ++win) {
+        for (int win = has_inner && !direct_inner ? 0 : 1; win < 2; ++win) {
             // win 0: inner window (half RI), win 1: outer window (half R)
             const int h = win == 0 ? RI : R;
             const int eoff = R - h;            // first extended row/col of the window
@@ -372,6 +377,22 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
         }
     }
 
+    if (direct_inner) {
+        for (int dy = -RI; dy <= RI; ++dy) {
+#pragma unroll 1
+            for (int dx = -RI; dx <= RI; ++dx) {
+                const size_t t = (size_t)(ty + R + dy) * EX + (tx + R + dx);
+                double f[LP];
+                centred<LP>(xs, t, ref, f);
+                const double b = (double)bad[t];
+#pragma unroll
+                for (int g = 0; g < C::GT; ++g) S[g] -= feat<LP>(f, b, g);
+#pragma unroll
+                for (int i = 0; i < LP; ++i) sin_lin[i] += f[i];
+                in_bad += b;
+            }
+        }
+    }
     const bool inside = py < H && px < W;
     float v = NAN;
     if (inside)
