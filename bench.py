@@ -75,6 +75,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--level", type=int, default=None, help="DWT levels (default: paper rule)")
+    ap.add_argument("--schedule", choices=("fused", "separate"), default="fused",
+                    help="fused: each step is one hsad_dwt_detect_fused call that reduces the next cube "
+                         "and scores the current one in one launch (where L' <= 5 and L %% 4 == 0); "
+                         "separate: hsad_dwt then hsad_detect")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fullband", action="store_true")
@@ -681,10 +685,15 @@ def main():
     det_ws = torch.empty(hs.hsad_detect_workspace_bytes(H, W, Lp, inner, outer, load), dtype=torch.uint8,
                          device=dev)
     th_out = torch.empty(4, dtype=torch.float64, device=dev)
+    # fused schedule: a stream of cubes through a two-stage software pipeline.  Step i scores
+    # cube i (reduced into bufs[i & 1] by step i - 1) and reduces cube i + 1 into the other
+    # buffer, in one launch; every step is one whole DWT and one whole detection.
+    fused = args.schedule == "fused" and Lp <= 5 and L % 4 == 0
+    bufs = [torch.empty((H, W, Lp), dtype=torch.float32, device=dev) for _ in range(2)]
 
-    def step(i, ev=None):
+    def step_separate(i, ev=None):
         # ev: two events that the DWT's kernel dispatch itself records at its start and end
-        # (hsad_dwt_timed), whose difference is the launch duration the roofline needs
+        # (hsad_dwt_timed), whose difference is the launch duration
         if ev is not None:
             hs.hsad_dwt_timed(cubes[i & 1], J, ev[0], ev[1], out=approx)
         else:
@@ -693,10 +702,20 @@ def main():
         hs.hsad_detect(approx, inner, outer, load, 3.0, lrx=lrx, dwrx=dwrx, stats=th_out, mask=mask,
                        ws=det_ws)
 
+    def step_fused(i, ev=None):
+        # ev: events that the shared launch's dispatch records at its start and end
+        hs.hsad_dwt_detect_fused(cubes[(i + 1) & 1], J, bufs[(i + 1) & 1], bufs[i & 1], inner, outer, load, 3.0,
+                                 lrx=lrx, dwrx=dwrx, stats=th_out, mask=mask, ws=det_ws,
+                                 start=ev[0] if ev else None, stop=ev[1] if ev else None)
+
+    step = step_fused if fused else step_separate
+    hs.hsad_dwt(cubes[0], J, out=bufs[0])          # pipeline fill: cube 0 reduced before step 0
     for i in range(args.warmup):
         step(i)
+    if fused:
+        hs.hsad_dwt(cubes[0], J, out=bufs[0])      # step 0 of the timed run scores cube 0 again
     torch.cuda.synchronize()
-    # the DWT's launch duration (roofline) comes from the events that the DWT's dispatch
+    # the dominant launch's duration (roofline) comes from the events that its dispatch
     # records in every EV_EVERY-th timed step
     EV_EVERY = 10
     evs = {i: [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -715,19 +734,32 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = t0.elapsed_time(t1) / args.steps
-    dwt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs.values()]))
+    launch_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs.values()]))
     value = npix / (ms_step * 1e-3)
-    # the detection call's share, from a separate instrumented pass (not the timed region)
+    # the timed run's last step left the scores of its last cube (the same scene)
+    fl, fd = lrx.clone(), dwrx.clone()
+    # the separate schedule's step and its DWT / detection shares, from an instrumented pass
+    # outside the timed region
     nsplit = min(args.steps, 50)
     sev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nsplit)]
     for trip in sev:
         for e in trip:
             e.record()
     for i in range(nsplit):
-        step(i, sev[i])
+        step_separate(i, sev[i])
         sev[i][2].record()
     torch.cuda.synchronize()
+    dwt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in sev]))
     det_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in sev]))
+    sep_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in sev]))
+    if not fused:
+        dwt_ms = launch_ms
+    if fused:
+        # the fused schedule's scores must equal the separate calls' (the instrumented pass
+        # above left those in lrx, dwrx)
+        if not (torch.equal(fl, lrx) and torch.equal(fd, dwrx)):
+            print("bench.py: the fused schedule's scores differ from the separate calls'", file=sys.stderr)
+            sys.exit(1)
 
     if args.profile:
         # plain copies of known size: what FETCH_SIZE / WRITE_SIZE read for 256 MiB moved
@@ -736,17 +768,27 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.steps, "ms_per_step": ms_step, "dwt_ms": dwt_ms,
-                          "detect_ms": det_ms}))
+        print(json.dumps({"profile_steps": args.steps, "schedule": "fused" if fused else "separate",
+                          "ms_per_step": ms_step, "launch_ms": launch_ms, "dwt_ms": dwt_ms, "detect_ms": det_ms,
+                          "separate_ms_per_step": sep_ms}))
         return
 
-    # dominant kernel: the DWT, bound by HBM.  Algorithmic bytes per launch: read the cube
-    # once (H W L 4) and write the approximation matrix (H W L' 4).
+    # dominant kernel, bound by HBM.  Algorithmic bytes per launch of the DWT: read the cube
+    # once (H W L 4) and write the approximation matrix (H W L' 4).  The shared launch adds
+    # the detector's: read the reduced cube once (H W L' 4), write the two score maps
+    # (H W 8) and one (count, mean, M2) partial per 32 x 16 tile.
     dwt_bytes = npix * L * 4 + npix * Lp * 4
-    achieved = dwt_bytes / (dwt_ms * 1e-3)
-    dwt_kernel = "dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_banded_kernel"
-    src_hash = kernel_source_hash(["dwt.hip", "dev_dwt.hpp"])
-    traffic = load_traffic(dwt_kernel, "C2_L%d_J%d" % (L, J), src_hash)
+    ntiles = ((H + 15) // 16) * ((W + 31) // 32)
+    fused_bytes = dwt_bytes + npix * Lp * 4 + npix * 8 + ntiles * 24
+    if fused:
+        kern, launch_bytes = "dwt_box_fused_kernel", fused_bytes
+        src_hash = kernel_source_hash(["box.hip", "dev_box.hpp", "dwt.hip", "dev_dwt.hpp"])
+        traffic = load_traffic(kern, "C2_L%d_J%d_%d_%d" % (L, J, inner, outer), src_hash)
+    else:
+        kern, launch_bytes = ("dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_banded_kernel"), dwt_bytes
+        src_hash = kernel_source_hash(["dwt.hip", "dev_dwt.hpp"])
+        traffic = load_traffic(kern, "C2_L%d_J%d" % (L, J), src_hash)
+    achieved = launch_bytes / (launch_ms * 1e-3)
 
     # ROC AUC of the GPU scores vs the FP64 oracle scores on the same cube
     gl = lrx.cpu().numpy().ravel()
@@ -917,12 +959,19 @@ def main():
                                "outer 15 + eq. 12 mask" % (J, Lp),
                    "H": H, "W": W, "L": L, "levels": J, "Lp": Lp, "inner": inner,
                    "outer": outer, "load_rel": load, "storage": "f32", "parallelism": "1 GPU"},
-        "kernel_ms": {"dwt": dwt_ms, "detect": det_ms, "dwt_event_samples": len(evs)},
+        "schedule": ("fused: one launch per step reduces cube i+1 and scores cube i (two reduced buffers), "
+                     "then the eq. 12 merge and mask" if fused else "separate: hsad_dwt, then hsad_detect"),
+        "kernel_ms": {"launch": launch_ms, "launch_event_samples": len(evs), "dwt": dwt_ms, "detect": det_ms,
+                      "separate_step": sep_ms},
         "wall_s_timed": wall,
-        "roofline": {"bound": "hbm", "kernel": dwt_kernel, "achieved": achieved / 1e9,
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic, "algorithmic_bytes_per_launch": dwt_bytes,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": launch_bytes,
                      "source_hash": src_hash},
+        "dwt_roofline": {"bound": "hbm", "kernel": "dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_banded_kernel",
+                         "achieved": dwt_bytes / (dwt_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": dwt_bytes / (dwt_ms * 1e-3) / HBM_PEAK,
+                         "algorithmic_bytes_per_launch": dwt_bytes},
         "cpu_baseline": cpu,
         "full_band_gpu": full,
         "sweep": sweep,

@@ -207,6 +207,31 @@ int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_win
                 double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,
                 size_t ws_bytes, hipStream_t stream);
 
+/* The DWT of one cube (Sec. 3, as hsad_dwt) and the detection step on another, already
+ * reduced cube (as hsad_detect), with the same results as hsad_dwt followed by hsad_detect.
+ * For a stream of cubes this is one step of a software pipeline: the call that scores cube
+ * k reduces cube k + 1 into the other of two reduced buffers.  The two share one launch
+ * when both halves are given, L' <= 5, L is a multiple of 4, the precision is exact and a
+ * workgroup of each role fits one CU's LDS together (outer windows up to 15 x 15 at
+ * L' = 4, 19 x 19 at L' = 2, 21 x 21 at L' = 5): the transform is bound by HBM bandwidth
+ * and the detector by FP64 arithmetic and LDS, and a CU holds one workgroup of each, so
+ * their times overlap instead of adding.  Otherwise the two run one after the other on the
+ * stream.
+ *   cube_next    : device, H*W*L float32 [y][x][band], or NULL (no transform: hsad_detect)
+ *   L, levels    : as hsad_dwt; their L' must equal Lp
+ *   approx_next  : device, H*W*Lp float32 written; must not overlap any other argument
+ *   x            : device, H*W*Lp float32, the cube to score, or NULL (transform only:
+ *                  hsad_dwt; p, z_alpha, lrx, dwrx, stats, mask and ws are then ignored)
+ *   p ... ws_bytes : as hsad_detect
+ *   start, stop  : events taken when the launch that holds the transform starts and ends
+ *                  (the shared launch, or the transform's own), or NULL
+ * Errors: as hsad_dwt and hsad_detect; HSAD_EINVAL if both cubes are NULL, if the two L'
+ * differ or if approx_next overlaps another argument (nothing is enqueued then). */
+int hsad_dwt_detect_fused(const float *cube_next, int64_t L, int levels, float *approx_next,
+                          const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                          double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,
+                          size_t ws_bytes, hipStream_t stream, hipEvent_t start, hipEvent_t stop);
+
 /* Size of the static device array hsad_detect_noalloc takes its workspace from. */
 #define HSAD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 

@@ -97,6 +97,9 @@ SIGNATURES = [
                                    ctypes.c_size_t, _vp]),
     ("hsad_detect_noalloc", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, ctypes.c_double, _vp, _vp, _vp, _vp,
                                            _vp]),
+    ("hsad_dwt_detect_fused", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, _vp, _i64, _i64, _i64, _P,
+                                             ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp,
+                                             _vp, _vp]),
     ("hsad_dwest", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_global_rx_workspace_bytes", ctypes.c_size_t, [_i64, _i64]),
     ("hsad_global_rx", ctypes.c_int, [_vp, _i64, _i64, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_size_t,
@@ -151,6 +154,7 @@ INTERNAL_SIGNATURES = [
     ("hsad_internal_dwt_force", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwt_banded_wide", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_chunk", ctypes.c_int, [ctypes.c_int]),
+    ("hsad_internal_fused_run", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_box_width", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_feat_cfg", ctypes.c_int, [ctypes.c_int]),
     ("hsad_internal_dwt_nt", ctypes.c_int, [ctypes.c_int]),
@@ -290,11 +294,7 @@ def hsad_dwt_timed(cube, levels: int, start, stop, out=None, stream=None):
     po = _dev(out, "out", torch.float32)
     if out.numel() != H * W * Lp:
         raise ValueError("out must hold H*W*L' values")
-    ev = []
-    for e in (start, stop):
-        if e is not None and e.cuda_event == 0:
-            e.record()          # torch creates its event on the first record
-        ev.append(ctypes.c_void_p(e.cuda_event) if e is not None else ctypes.c_void_p(None))
+    ev = _events(start, stop)
     _check("hsad_dwt_timed", lib().hsad_dwt_timed(pc, H, W, L, int(levels), po, _stream(stream), ev[0], ev[1]))
     return out
 
@@ -395,6 +395,68 @@ def hsad_detect(x, inner: int, outer: int, load_rel: float = 1e-6, z_alpha: floa
                            _ptr_or_null(mask, "mask", torch.uint8), _dev(ws, "ws"),
                            ws.numel() * ws.element_size(), _stream(stream))
     _check("hsad_detect", rc)
+    return lrx, dwrx, stats, mask
+
+
+def _events(start, stop):
+    ev = []
+    for e in (start, stop):
+        if e is not None and e.cuda_event == 0:
+            e.record()          # torch creates its event on the first record
+        ev.append(ctypes.c_void_p(e.cuda_event) if e is not None else ctypes.c_void_p(None))
+    return ev
+
+
+def hsad_dwt_detect_fused(cube_next, levels: int, approx_next, x, inner: int, outer: int,
+                          load_rel: float = 1e-6, z_alpha: float = 3.0, precision: int = HSAD_PREC_AUTO,
+                          lrx=None, dwrx=True, stats=None, mask=True, ws=None, start=None, stop=None,
+                          stream=None):
+    """The DWT of cube_next into approx_next and hsad_detect on the reduced cube x, in one launch
+    where they can share one (the same results as hsad_dwt followed by hsad_detect).  Either
+    cube may be None.  start / stop: timing events for the launch that holds the transform.
+    Returns (lrx, dwrx or None, stats, mask or None), all None when x is None."""
+    torch = _torch()
+    pc = _ptr_or_null(cube_next, "cube_next", torch.float32)
+    L = int(cube_next.shape[-1]) if cube_next is not None else 0
+    pa = _ptr_or_null(approx_next, "approx_next", torch.float32)
+    ev = _events(start, stop)
+    if x is None:
+        if cube_next is None or approx_next is None:
+            raise ValueError("cube_next and approx_next are needed when x is None")
+        H, W = int(cube_next.shape[0]), int(cube_next.shape[1])
+        if approx_next.numel() != H * W * hsad_dwt_out_len(L, levels):
+            raise ValueError("approx_next must hold H*W*L' values")
+        _check("hsad_dwt_detect_fused",
+               lib().hsad_dwt_detect_fused(pc, L, int(levels), pa, None, H, W, 0, None, 0.0, None, None, None,
+                                           None, None, 0, _stream(stream), ev[0], ev[1]))
+        return None, None, None, None
+    px = _dev(x, "x", torch.float32, 3)
+    H, W, Lp = x.shape
+    if cube_next is not None:
+        if tuple(cube_next.shape[:2]) != (H, W) or cube_next.dim() != 3:
+            raise ValueError("cube_next must be (H, W, L) with the H, W of x")
+        if approx_next is None or approx_next.numel() != H * W * Lp:
+            raise ValueError("approx_next must hold H*W*L' values")
+    p = _params(inner, outer, load_rel, precision)
+    dev = x.device
+    lrx = torch.empty((H, W), dtype=torch.float32, device=dev) if lrx is None else lrx
+    if dwrx is True:
+        dwrx = torch.empty((H, W), dtype=torch.float32, device=dev)
+    elif dwrx is False:
+        dwrx = None
+    if mask is True:
+        mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    elif mask is False:
+        mask = None
+    stats = torch.empty(4, dtype=torch.float64, device=dev) if stats is None else stats
+    if ws is None:
+        ws = torch.empty(max(1, hsad_detect_workspace_bytes(H, W, Lp, inner, outer, load_rel, precision)),
+                         dtype=torch.uint8, device=dev)
+    rc = lib().hsad_dwt_detect_fused(pc, L, int(levels), pa, px, H, W, Lp, ctypes.byref(p), float(z_alpha),
+                                     _dev(lrx, "lrx", torch.float32), _ptr_or_null(dwrx, "dwrx", torch.float32),
+                                     _dev(stats, "stats", torch.float64), _ptr_or_null(mask, "mask", torch.uint8),
+                                     _dev(ws, "ws"), ws.numel() * ws.element_size(), _stream(stream), ev[0], ev[1])
+    _check("hsad_dwt_detect_fused", rc)
     return lrx, dwrx, stats, mask
 
 

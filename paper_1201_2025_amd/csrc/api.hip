@@ -385,6 +385,62 @@ int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_win
     return hsad_threshold(lrx, n, z_alpha, stats, mask, part, head, stream);
 }
 
+int hsad_dwt_detect_fused(const float *cube_next, int64_t L, int levels, float *approx_next,
+                          const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
+                          double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,
+                          size_t ws_bytes, hipStream_t stream, hipEvent_t start, hipEvent_t stop)
+{
+    static const char *fn = "hsad_dwt_detect_fused";
+    clear_error();
+    if (!cube_next && !x) return fail(HSAD_EINVAL, std::string(fn) + ": cube_next and x are both NULL");
+    if (H < 1 || W < 1) return fail(HSAD_EINVAL, std::string(fn) + ": H and W must be >= 1");
+    const int64_t n = H * W;
+    int64_t Lpn = 0;
+    if (cube_next) {
+        if (!approx_next) return fail(HSAD_EINVAL, std::string(fn) + ": approx_next is NULL");
+        if (out_len(L, levels, &Lpn))
+            return fail(HSAD_EINVAL, std::string(fn) + ": L < 1, levels < 0 or levels too deep for L");
+        if (L > (1 << 20)) return fail(HSAD_EUNSUPPORTED, std::string(fn) + ": L above 2^20");
+        if (!x) return dwt_launch(cube_next, n, L, levels, Lpn, approx_next, stream, start, stop);
+    }
+    Windows w;
+    int rc = check_windows(fn, p, H, W, Lp, dwrx != nullptr, &w);
+    if (rc) return rc;
+    if (!lrx || !stats) return fail(HSAD_EINVAL, std::string(fn) + ": lrx and stats are required");
+    if (!std::isfinite(z_alpha)) return fail(HSAD_EINVAL, std::string(fn) + ": z_alpha not finite");
+    const size_t head = detect_head_bytes(H, W);
+    if (!ws || ws_bytes < head) return fail(HSAD_ENOMEM, std::string(fn) + ": workspace too small");
+    if (!cube_next) return hsad_detect(x, H, W, Lp, p, z_alpha, lrx, dwrx, stats, mask, ws, ws_bytes, stream);
+    if (Lpn != Lp)
+        return fail(HSAD_EINVAL, std::string(fn) + ": L' of the cube to reduce differs from the L' of x");
+    // what the DWT writes must not meet anything the detector reads or writes
+    const auto meets = [](const void *a, size_t na, const void *b, size_t nb) {
+        if (!a || !b || !na || !nb) return false;
+        const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+        return pa < pb + nb && pb < pa + na;
+    };
+    const size_t red = (size_t)(n * Lp) * sizeof(float);
+    if (meets(approx_next, red, cube_next, (size_t)(n * L) * sizeof(float)) || meets(approx_next, red, x, red) ||
+        meets(approx_next, red, lrx, (size_t)n * sizeof(float)) ||
+        meets(approx_next, red, dwrx, (size_t)n * sizeof(float)) || meets(approx_next, red, mask, (size_t)n) ||
+        meets(approx_next, red, stats, 4 * sizeof(double)) || meets(approx_next, red, ws, ws_bytes))
+        return fail(HSAD_EINVAL, std::string(fn) + ": approx_next overlaps another argument");
+    if (exact(p->precision) && box_supported(Lp, w)) {
+        double *part = (double *)ws;
+        const size_t np = (head / (3 * sizeof(double))) - threshold_fold_doubles() / 3;
+        int64_t nparts = 0;
+        rc = dwt_box_fused_launch(cube_next, L, levels, approx_next, x, H, W, Lp, w, p->load_rel, lrx, dwrx, part,
+                                  &nparts, stream, start, stop);
+        if (rc == HSAD_OK)
+            return threshold_from_partials(lrx, n, part, nparts, z_alpha, stats, mask, part + 3 * np, stream);
+        if (rc != HSAD_EUNSUPPORTED) return rc;
+    }
+    // the two cannot share a launch: one after the other
+    rc = dwt_launch(cube_next, n, L, levels, Lp, approx_next, stream, start, stop);
+    if (rc) return rc;
+    return hsad_detect(x, H, W, Lp, p, z_alpha, lrx, dwrx, stats, mask, ws, ws_bytes, stream);
+}
+
 int hsad_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
                float *scores, float *scores_literal, int32_t *npos, void *ws,
                size_t ws_bytes, hipStream_t stream)

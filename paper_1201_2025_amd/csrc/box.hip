@@ -32,9 +32,11 @@
 //   through d, from the raw values (a rare path that re-reads the inner window).
 // HBM traffic is the reduced cube once (the halo re-reads hit L2) and the score maps.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "internal.hpp"
 #include "dev_box.hpp"
+#include "dev_dwt.hpp"
 
 namespace hsad {
 
@@ -82,10 +84,10 @@ static int g_box_tx = 0;   // 0: widest tile whose LDS fits; 16 forced (tuning, 
 // 5 x 5 / 15 x 15 windows, at 512 x 512 and at 1024 x 1024 alike (32 x 16 tiles).  At
 // 512 x 512, L' = 2: 18.0 vs 21.4 us (5); L' = 3: 24.1 vs 26.0 (8); L' = 4: 28.1 vs 30.4 (5);
 // L' = 5: 40.2 vs 45.8 (15); L' = 6 / 7 / 8: 49.7 / 64.6 / 70.1 vs 59.7 / 73.4 / 94.0 (8)
+static constexpr int kBoxBestGc[9] = {5, 5, 8, 5, 8, 5, 15, 15, 15};
 static int box_gc(int Lp)
 {
-    static const int best[9] = {5, 5, 8, 5, 8, 5, 15, 15, 15};
-    return g_box_gc ? g_box_gc : best[Lp >= 0 && Lp <= 8 ? Lp : 0];
+    return g_box_gc ? g_box_gc : kBoxBestGc[Lp >= 0 && Lp <= 8 ? Lp : 0];
 }
 
 template <int LP, int GCMAX> static int box_width(int R)
@@ -179,7 +181,111 @@ int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const 
     }
 }
 
+// ------------------------------------------------------------------------------------
+// One launch for the DWT of one cube and the detector on another, reduced cube
+// ------------------------------------------------------------------------------------
+// The LDS-staged DWT streams the cube from HBM and leaves the FP64 units mostly idle; the
+// detector tile is bound by FP64 arithmetic, LDS traffic and barrier latency and leaves HBM
+// idle.  Launched back to back their times add.  Here they are two roles of one grid of
+// 512-thread workgroups (two per CU by LDS and registers): a DWT workgroup reduces 512
+// pixels, a detector workgroup scores one 32 x 16 tile.  The roles alternate in runs of
+// `run` workgroup ids, so that most CUs hold one workgroup of each and the detector's
+// arithmetic runs under the DWT's HBM stream (at 512 x 512 x 224, J = 6, 5 / 15 windows:
+// 52.6 us per launch with runs of 128 against 63 us for the two kernels back to back; runs
+// of 8 to 512, two chunks of the cube in flight per DWT workgroup, and 256-thread
+// workgroups with 16 x 16 tiles, three or four per CU, all measured slower).  Each role's
+// arithmetic is that of its own kernel, so the results are bit-identical to the two
+// launches.
+constexpr int kFusedNT = 512;
+static int g_fused_run = 128;   // role run length in workgroup ids (tuning, tests)
+
+template <int LP, int VEC, int GCMAX>
+__global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(4, 4))) void dwt_box_fused_kernel(
+    const float *__restrict__ cube, int64_t npix, int L, const double *__restrict__ coef,
+    float *__restrict__ approx, int nd, const float *__restrict__ x, int H, int W, int R, int RI,
+    int has_inner, double load_rel, float *__restrict__ lrx, float *__restrict__ dwrx,
+    double *__restrict__ part, int nb, int ntx, int run)
+{
+    extern __shared__ double smem[];
+    const int b = blockIdx.x;
+    const int m = min(nd, nb) / run;   // full run pairs
+    int role, idx;
+    if (b < 2 * m * run) {
+        role = (b / run) & 1;
+        idx = (b / (2 * run)) * run + b % run;
+    } else {
+        const int r = b - 2 * m * run, dl = nd - m * run;
+        role = r < dl ? 0 : 1;
+        idx = m * run + (r < dl ? r : r - dl);
+    }
+    if (role == 0)
+        dwt_equiv_lds_block<LP, VEC, true, kFusedNT>(cube, npix, L, coef, approx, reinterpret_cast<float *>(smem),
+                                                     idx);
+    else
+        box_tile<LP, GCMAX, kFusedNT / TY>(x, H, W, R, RI, has_inner, load_rel, lrx, dwrx, idx / ntx, idx % ntx,
+                                           smem, part, ntx);
+}
+
+template <int LP>
+static int fused_launch(const float *cube, int64_t L, const double *coef, float *approx, const float *x,
+                        int64_t H, int64_t W, const Windows &w, double load_rel, float *lrx, float *dwrx,
+                        double *part, int64_t *nparts, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    // the 32 x 16 detector tile with the default feature chunk: what hsad_detect runs
+    constexpr int GC = kBoxBestGc[LP];
+    constexpr int TXW = kFusedNT / TY;
+    if (g_box_gc != 0 || g_box_tx == 16 || box_width<LP, GC>(w.ro) != TXW) return HSAD_EUNSUPPORTED;
+    const size_t dwt_sh = (size_t)kFusedNT * kEqLd * sizeof(float);
+    const size_t box_sh = box_smem<LP, GC, TXW>(w.ro);
+    const size_t sh = box_sh > dwt_sh ? box_sh : dwt_sh;
+    // two workgroups (one of each role) must fit a CU's 160 KiB of LDS
+    if (2 * sh > 160 * 1024) return HSAD_EUNSUPPORTED;
+    const int64_t npix = H * W;
+    const int64_t nd = (npix + kFusedNT - 1) / kFusedNT;
+    const int ntx = (int)((W + TXW - 1) / TXW);
+    const int64_t nb = (int64_t)ntx * ((H + TY - 1) / TY);
+    if (nd + nb > INT32_MAX) return HSAD_EUNSUPPORTED;
+    const void *kern = (const void *)dwt_box_fused_kernel<LP, 4, GC>;
+    if (int rc = allow_lds(kern, sh, "dwt_box_fused_kernel")) return rc;
+    int Li = (int)L, ndi = (int)nd, Hi = (int)H, Wi = (int)W, R = w.ro, RI = w.ri, hi = w.inner > 0 ? 1 : 0;
+    int nbi = (int)nb, ntxi = ntx, runi = g_fused_run;
+    int64_t np = npix;
+    void *args[] = {(void *)&cube, &np, &Li, (void *)&coef, (void *)&approx, &ndi, (void *)&x, &Hi, &Wi, &R, &RI,
+                    &hi, &load_rel, (void *)&lrx, (void *)&dwrx, (void *)&part, &nbi, &ntxi, &runi};
+    if (hipExtLaunchKernel(kern, dim3((unsigned)(nd + nb)), dim3(kFusedNT), args, sh, s, e0, e1, 0) != hipSuccess)
+        return fail(HSAD_EHIP, "dwt_box_fused_kernel: launch failed");
+    *nparts = nb;
+    return check_launch("dwt_box_fused_kernel");
+}
+
+int dwt_box_fused_launch(const float *cube, int64_t L, int levels, float *approx, const float *x,
+                         int64_t H, int64_t W, int64_t Lp, const Windows &w, double load_rel, float *lrx,
+                         float *dwrx, double *part, int64_t *nparts, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    // L' <= 5 and whole float4 band vectors: the forms where both roles fit 128 VGPRs (four
+    // waves per SIMD, two workgroups per CU) without spilling
+    if (Lp < 1 || Lp > 5 || L % 4 != 0 || g_fused_run < 1 || H > (1 << 24) || W > (1 << 24) ||
+        L > INT32_MAX || !box_supported(Lp, w))
+        return HSAD_EUNSUPPORTED;
+    const double *coef = dwt_lds_coefs(L, levels, Lp, s);
+    if (!coef) return HSAD_EUNSUPPORTED;
+    switch (Lp) {
+#define HSAD_FUSED_CASE(n) \
+    case n: return fused_launch<n>(cube, L, coef, approx, x, H, W, w, load_rel, lrx, dwrx, part, nparts, s, e0, e1);
+        HSAD_FUSED_CASE(1) HSAD_FUSED_CASE(2) HSAD_FUSED_CASE(3) HSAD_FUSED_CASE(4) HSAD_FUSED_CASE(5)
+#undef HSAD_FUSED_CASE
+    default: return HSAD_EUNSUPPORTED;
+    }
+}
+
 }  // namespace hsad
+
+extern "C" int hsad_internal_fused_run(int run)
+{
+    if (run < 1) return -1;
+    hsad::g_fused_run = run;
+    return 0;
+}
 
 extern "C" int hsad_internal_box_chunk(int gc)
 {

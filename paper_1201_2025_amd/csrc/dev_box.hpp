@@ -186,7 +186,7 @@ template <int NW> __device__ __forceinline__ double box_block_sum(double v, doub
 
 // (count, mean, centred sum of squares) of the finite values v of a tile's threads, two
 // passes in FP64 -> out[0..2].  The partial statistics of eq. (12) for one tile.
-template <int NW> __device__ inline void box_tile_stats(float v, bool valid, double *out, double *red)
+template <int NW> __device__ __forceinline__ void box_tile_stats(float v, bool valid, double *out, double *red)
 {
     const bool fin = valid && isfinite(v);
     const double c = box_block_sum<NW>(fin ? 1.0 : 0.0, red);
@@ -202,10 +202,10 @@ template <int NW> __device__ inline void box_tile_stats(float v, bool valid, dou
 }
 
 template <int LP, int GCMAX, int TXW = 16>
-__device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R, int RI,
+__device__ __forceinline__ void box_tile(const float *__restrict__ x, int H, int W, int R, int RI,
                                 int has_inner, double load_rel, float *__restrict__ lrx,
                                 float *__restrict__ dwrx, int by, int bx, double *smem,
-                                double *__restrict__ part = nullptr)
+                                double *__restrict__ part = nullptr, int ntx = -1)
 {
     using C = BoxCfg<LP, GCMAX>;
     constexpr int TX = TXW, NT = TXW * TY;
@@ -399,7 +399,10 @@ __device__ inline void box_tile(const float *__restrict__ x, int H, int W, int R
         v = box_score<LP, C::GT>(x, H, W, R, RI, has_inner, load_rel, ref, S, sin_lin, in_bad, py, px, lrx,
                                  dwrx);
     // eq. (12) partials of this tile's LRX scores (the LDS tile is free again here)
-    if (part) box_tile_stats<NT / 64>(v, inside, part + 3 * ((size_t)by * gridDim.x + bx), smem);
+    // partial of tile (by, bx) at by * ntx + bx (ntx: tiles per row, the grid's x extent by
+    // default)
+    if (part)
+        box_tile_stats<NT / 64>(v, inside, part + 3 * ((size_t)by * (ntx < 0 ? (int)gridDim.x : ntx) + bx), smem);
 }
 
 

@@ -1,5 +1,6 @@
-// dev_dwt.hpp -- device body of the LDS cascade DWT (Sec. 3 eqs. 8-9, Fig. 1), shared by the
-// per-cube kernel and the persistent batch kernel.
+// dev_dwt.hpp -- device bodies of the DWT (Sec. 3 eqs. 8-9, Fig. 1): the LDS cascade (per-cube
+// and persistent batch kernels), the banded and the LDS-staged equivalent filters (the
+// per-cube kernels and the fused DWT + detector launch).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -222,6 +223,127 @@ __device__ inline void dwt_banded_tile(const float *__restrict__ cube, int64_t p
     for (int t = tid; t < ototal; t += NT) {
         const uint32_t r = __umulhi((uint32_t)t, magic_Lp);
         dst[t] = os[r * LDO + ((uint32_t)t - r * (uint32_t)Lp)];
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// equivalent filter with coalesced, LDS-staged band chunks (Sec. 3: the J-level
+// approximation as one L' x L matrix applied to each spectrum)
+// ------------------------------------------------------------------------------------
+typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+template <int VEC> struct VecT;
+template <> struct VecT<1> { using T = float; };
+template <> struct VecT<2> { using T = fv2; };
+template <> struct VecT<4> { using T = fv4; };
+
+template <int VEC>
+__device__ __forceinline__ float lane_elem(const typename VecT<VEC>::T &v, int e)
+{
+    if constexpr (VEC == 1) {
+        return v;
+    } else {
+        return v[e];
+    }
+}
+
+// A workgroup of NT threads owns NT consecutive pixels (one per thread) and walks the
+// spectrum in chunks of 32 bands.  Each chunk is loaded with whole 128-byte lines per pixel
+// (8 lanes x 16 bytes, or 32 lanes x 4 bytes when L is not a multiple of 4) into LDS.
+// There it is transposed to one row per pixel (stride 33 floats, conflict-free).  The
+// next chunk's loads are issued into registers before the current chunk is computed, so
+// HBM streaming overlaps the FP64 FMAs.  Load addresses are clamped into the tile (last
+// pixel, last vector of the chunk) so every lane loads unconditionally: loads under a
+// lane-dependent condition cost about 15 % of the bandwidth here.  The clamped duplicates
+// land in LDS cells that are never read.
+//   coef : [L][L'] doubles (band-major composite matrix)
+//   tile : NT * kEqLd floats of LDS
+//   blk  : index of the block of NT pixels
+constexpr int kEqCB = 32, kEqTP = 256, kEqLd = kEqCB + 1;
+
+template <int LP, int VEC, bool NTL, int NT>
+__device__ inline void dwt_equiv_lds_block(const float *__restrict__ cube, int64_t npix, int L,
+                                           const double *__restrict__ coef, float *__restrict__ out,
+                                           float *tile, int64_t blk)
+{
+    constexpr int PER = kEqCB / VEC;              // vectors per thread per chunk
+    static_assert(kEqCB % VEC == 0, "chunk of whole vectors");
+    using V = typename VecT<VEC>::T;
+    const int t = threadIdx.x;
+    const int64_t p0 = blk * NT;
+    const int np = (int)((npix - p0) < NT ? (npix - p0) : NT);
+    const int nchunk = (L + kEqCB - 1) / kEqCB;
+    constexpr int SEG = kEqCB / VEC;              // vectors per pixel segment (= PER: NT pixels, NT threads)
+
+    auto load_chunk = [&](V (&buf)[PER], int c0) {
+        const int cb = (L - c0) < kEqCB ? (L - c0) : kEqCB;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = t + NT * i;
+            const int p = min(q / SEG, np - 1), j = min((q % SEG) * VEC, cb - VEC);
+            // the cube is read exactly once: non-temporal loads keep it from displacing
+            // cached data
+            const V *a = reinterpret_cast<const V *>(cube + (p0 + p) * (int64_t)L + c0 + j);
+            buf[i] = NTL ? __builtin_nontemporal_load(a) : *a;
+        }
+    };
+    auto store_chunk = [&](const V (&buf)[PER]) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = t + NT * i;
+            const int p = q / SEG, j = q % SEG;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) tile[p * kEqLd + j * VEC + e] = lane_elem<VEC>(buf[i], e);
+        }
+    };
+
+    double acc[LP];
+#pragma unroll
+    for (int k = 0; k < LP; ++k) acc[k] = 0.0;
+    auto compute = [&](int c0) {
+        const int cb = (L - c0) < kEqCB ? (L - c0) : kEqCB;
+        const float *row = tile + t * kEqLd;
+        const double *cf = coef + (size_t)c0 * LP;
+        if (cb == kEqCB) {
+#pragma unroll 8
+            for (int b = 0; b < kEqCB; ++b) {
+                const double xv = (double)row[b];
+#pragma unroll
+                for (int k = 0; k < LP; ++k) acc[k] = fma(cf[b * LP + k], xv, acc[k]);
+            }
+        } else {
+            for (int b = 0; b < cb; ++b) {
+                const double xv = (double)row[b];
+#pragma unroll
+                for (int k = 0; k < LP; ++k) acc[k] = fma(cf[b * LP + k], xv, acc[k]);
+            }
+        }
+    };
+
+    V buf[PER];
+    load_chunk(buf, 0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int c0 = ch * kEqCB;
+        store_chunk(buf);
+        __syncthreads();
+        if (ch + 1 < nchunk) load_chunk(buf, c0 + kEqCB);
+        compute(c0);
+        __syncthreads();
+    }
+    if (t >= np) return;
+    float *dst = out + (p0 + t) * LP;
+    if constexpr (LP % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < LP; k += 4)
+            *reinterpret_cast<float4 *>(dst + k) =
+                make_float4((float)acc[k], (float)acc[k + 1], (float)acc[k + 2], (float)acc[k + 3]);
+    } else if constexpr (LP % 2 == 0) {
+#pragma unroll
+        for (int k = 0; k < LP; k += 2)
+            *reinterpret_cast<float2 *>(dst + k) = make_float2((float)acc[k], (float)acc[k + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < LP; ++k) dst[k] = (float)acc[k];
     }
 }
 

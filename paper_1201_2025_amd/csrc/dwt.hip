@@ -290,23 +290,6 @@ static bool banded_coefs(int64_t L, int levels, int64_t Lp, int max_w, hipStream
 // ------------------------------------------------------------------------------------
 // device: equivalent-filter kernel
 // ------------------------------------------------------------------------------------
-typedef float fv2 __attribute__((ext_vector_type(2)));
-typedef float fv4 __attribute__((ext_vector_type(4)));
-template <int VEC> struct VecT;
-template <> struct VecT<1> { using T = float; };
-template <> struct VecT<2> { using T = fv2; };
-template <> struct VecT<4> { using T = fv4; };
-
-template <int VEC>
-__device__ __forceinline__ float lane_elem(const typename VecT<VEC>::T &v, int e)
-{
-    if constexpr (VEC == 1) {
-        return v;
-    } else {
-        return v[e];
-    }
-}
-
 template <int LP, int VEC>
 __global__ __launch_bounds__(256) void dwt_equiv_kernel(const float *__restrict__ cube,
                                                         int64_t npix, int L,
@@ -369,19 +352,8 @@ __global__ __launch_bounds__(256) void dwt_equiv_kernel(const float *__restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// device: equivalent filter with coalesced, LDS-staged band chunks
+// device: equivalent filter with coalesced, LDS-staged band chunks (body in dev_dwt.hpp)
 // ------------------------------------------------------------------------------------
-// A workgroup owns 256 consecutive pixels (one per thread) and walks the spectrum in
-// chunks of 32 bands.  Each chunk is loaded with whole 128-byte lines per pixel (8
-// lanes x 16 bytes, or 32 lanes x 4 bytes when L is not a multiple of 4) into LDS.
-// There it is transposed to one row per pixel (stride 33 floats, conflict-free).  The
-// next chunk's loads are issued into registers before the current chunk is computed, so
-// HBM streaming overlaps the FP64 FMAs.  Load addresses are clamped into the tile (last
-// pixel, last vector of the chunk) so every lane loads unconditionally: loads under a
-// lane-dependent condition cost about 15 % of the bandwidth here.  The clamped duplicates
-// land in LDS cells that are never read.
-constexpr int kEqCB = 32, kEqTP = 256, kEqLd = kEqCB + 1;
-
 template <int LP, int VEC, bool NTL = true>
 __global__ __launch_bounds__(kEqTP) void dwt_equiv_lds_kernel(const float *__restrict__ cube,
                                                               int64_t npix, int L,
@@ -389,83 +361,7 @@ __global__ __launch_bounds__(kEqTP) void dwt_equiv_lds_kernel(const float *__res
                                                               float *__restrict__ out)
 {
     __shared__ float tile[kEqTP * kEqLd];
-    constexpr int PER = kEqCB / VEC;             // vectors per pixel segment = per thread per chunk
-    using V = typename VecT<VEC>::T;
-    const int t = threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.x * kEqTP;
-    const int np = (int)((npix - p0) < kEqTP ? (npix - p0) : kEqTP);
-    const int nchunk = (L + kEqCB - 1) / kEqCB;
-
-    auto load_chunk = [&](V (&buf)[PER], int c0) {
-        const int cb = (L - c0) < kEqCB ? (L - c0) : kEqCB;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int q = t + kEqTP * i;
-            const int p = min(q / PER, np - 1), j = min((q % PER) * VEC, cb - VEC);
-            // the cube is read exactly once: non-temporal loads keep it from displacing
-            // cached data
-            const V *a = reinterpret_cast<const V *>(cube + (p0 + p) * (int64_t)L + c0 + j);
-            buf[i] = NTL ? __builtin_nontemporal_load(a) : *a;
-        }
-    };
-    auto store_chunk = [&](const V (&buf)[PER]) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int q = t + kEqTP * i;
-            const int p = q / PER, j = q % PER;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) tile[p * kEqLd + j * VEC + e] = lane_elem<VEC>(buf[i], e);
-        }
-    };
-
-    double acc[LP];
-#pragma unroll
-    for (int k = 0; k < LP; ++k) acc[k] = 0.0;
-    auto compute = [&](int c0) {
-        const int cb = (L - c0) < kEqCB ? (L - c0) : kEqCB;
-        const float *row = tile + t * kEqLd;
-        const double *cf = coef + (size_t)c0 * LP;
-        if (cb == kEqCB) {
-#pragma unroll 8
-            for (int b = 0; b < kEqCB; ++b) {
-                const double xv = (double)row[b];
-#pragma unroll
-                for (int k = 0; k < LP; ++k) acc[k] = fma(cf[b * LP + k], xv, acc[k]);
-            }
-        } else {
-            for (int b = 0; b < cb; ++b) {
-                const double xv = (double)row[b];
-#pragma unroll
-                for (int k = 0; k < LP; ++k) acc[k] = fma(cf[b * LP + k], xv, acc[k]);
-            }
-        }
-    };
-
-    V buf[PER];
-    load_chunk(buf, 0);
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int c0 = ch * kEqCB;
-        store_chunk(buf);
-        __syncthreads();
-        if (ch + 1 < nchunk) load_chunk(buf, c0 + kEqCB);
-        compute(c0);
-        __syncthreads();
-    }
-    if (t >= np) return;
-    float *dst = out + (p0 + t) * LP;
-    if constexpr (LP % 4 == 0) {
-#pragma unroll
-        for (int k = 0; k < LP; k += 4)
-            *reinterpret_cast<float4 *>(dst + k) =
-                make_float4((float)acc[k], (float)acc[k + 1], (float)acc[k + 2], (float)acc[k + 3]);
-    } else if constexpr (LP % 2 == 0) {
-#pragma unroll
-        for (int k = 0; k < LP; k += 2)
-            *reinterpret_cast<float2 *>(dst + k) = make_float2((float)acc[k], (float)acc[k + 1]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < LP; ++k) dst[k] = (float)acc[k];
-    }
+    dwt_equiv_lds_block<LP, VEC, NTL, kEqTP>(cube, npix, L, coef, out, tile, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------
@@ -624,6 +520,15 @@ int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t L
     hipExtLaunchKernelGGL(dwt_cascade_kernel, grid, block, shmem, s, e0, e1, 0, cube, npix, (int)L, levels,
                        (int)Lp, (int)P, taps, approx);
     return check_launch("dwt_cascade_kernel");
+}
+
+// Band-major composite matrix ([L][L'] doubles) of the LDS-staged equivalent filter, ready
+// for work enqueued next on s, or nullptr when dwt_launch would not run that kernel for
+// (L, levels) (L' > 16, another kernel forced, table arena full).
+const double *dwt_lds_coefs(int64_t L, int levels, int64_t Lp, hipStream_t s)
+{
+    if (levels < 1 || Lp > 16 || (g_dwt_force != -1 && g_dwt_force != 1)) return nullptr;
+    return composite_coefs(L, levels, Lp, 1, s);
 }
 
 }  // namespace hsad

@@ -30,6 +30,9 @@ void dwt_composite_matrix(int64_t L, int levels, double *A /* Lp*L */);
 // e0 / e1 (may be null): events that take the start and end of the transform's kernel
 int dwt_launch(const float *cube, int64_t npix, int64_t L, int levels, int64_t Lp,
                float *approx, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Band-major [L][L'] composite matrix of the LDS-staged equivalent filter on the device, or
+// nullptr when dwt_launch would use another kernel for (L, levels).
+const double *dwt_lds_coefs(int64_t L, int levels, int64_t Lp, hipStream_t s);
 
 // ---- window geometry ----
 struct Windows {
@@ -44,6 +47,16 @@ bool box_supported(int64_t Lp, const Windows &w);
 int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const Windows &w,
                         double load_rel, float *lrx, float *dwrx, hipStream_t s,
                         double *part = nullptr);
+// The LDS-staged DWT of one cube (L bands, `levels` levels, into approx) and the box
+// detector on another, already reduced cube x (as box_lrx_dwrx_launch with its tile
+// partials; *nparts receives their number), in one launch whose workgroups take one role or
+// the other.  The two must not
+// overlap in memory.  Returns HSAD_EUNSUPPORTED, with nothing enqueued and no error set,
+// when the pair cannot share a launch (the caller runs them one after the other).
+int dwt_box_fused_launch(const float *cube, int64_t L, int levels, float *approx, const float *x,
+                         int64_t H, int64_t W, int64_t Lp, const Windows &w, double load_rel, float *lrx,
+                         float *dwrx, double *part, int64_t *nparts, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1);
 size_t box_tiles(int64_t H, int64_t W);
 // tiles of the box kernel as launched for these sizes (at most box_tiles(H, W))
 size_t box_tiles_used(int64_t H, int64_t W, int64_t Lp, const Windows &w);
