@@ -789,6 +789,7 @@ def main():
         src_hash = kernel_source_hash(["dwt.hip", "dev_dwt.hpp"])
         traffic = load_traffic(kern, "C2_L%d_J%d" % (L, J), src_hash)
     achieved = launch_bytes / (launch_ms * 1e-3)
+    dwt_kern = "dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_banded_kernel"
 
     # ROC AUC of the GPU scores vs the FP64 oracle scores on the same cube
     gl = lrx.cpu().numpy().ravel()
@@ -968,9 +969,11 @@ def main():
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": traffic, "algorithmic_bytes_per_launch": launch_bytes,
                      "source_hash": src_hash},
-        "dwt_roofline": {"bound": "hbm", "kernel": "dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_banded_kernel",
+        "dwt_roofline": {"bound": "hbm", "kernel": dwt_kern,
                          "achieved": dwt_bytes / (dwt_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                          "frac": dwt_bytes / (dwt_ms * 1e-3) / HBM_PEAK,
+                         "traffic": load_traffic(dwt_kern, "C2_L%d_J%d" % (L, J),
+                                                 kernel_source_hash(["dwt.hip", "dev_dwt.hpp"])),
                          "algorithmic_bytes_per_launch": dwt_bytes},
         "cpu_baseline": cpu,
         "full_band_gpu": full,

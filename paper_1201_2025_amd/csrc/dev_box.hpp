@@ -184,13 +184,45 @@ template <int NW> __device__ __forceinline__ double box_block_sum(double v, doub
     return t[0];
 }
 
+// Two block sums in one round (each in the order of box_block_sum, so the results are the
+// same); red holds 2 NW doubles.
+template <int NW> __device__ __forceinline__ void box_block_sum2(double &a, double &b, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const double xa = __shfl_xor(a, o), xb = __shfl_xor(b, o);
+        a += xa;
+        b += xb;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = a;
+        red[NW + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
+    double t[NW], u[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        t[i] = red[i];
+        u[i] = red[NW + i];
+    }
+#pragma unroll
+    for (int w = NW / 2; w >= 1; w /= 2)
+#pragma unroll
+        for (int i = 0; i < w; ++i) {
+            t[i] = t[2 * i] + t[2 * i + 1];
+            u[i] = u[2 * i] + u[2 * i + 1];
+        }
+    __syncthreads();
+    a = t[0];
+    b = u[0];
+}
+
 // (count, mean, centred sum of squares) of the finite values v of a tile's threads, two
 // passes in FP64 -> out[0..2].  The partial statistics of eq. (12) for one tile.
 template <int NW> __device__ __forceinline__ void box_tile_stats(float v, bool valid, double *out, double *red)
 {
     const bool fin = valid && isfinite(v);
-    const double c = box_block_sum<NW>(fin ? 1.0 : 0.0, red);
-    const double sum = box_block_sum<NW>(fin ? (double)v : 0.0, red);
+    double c = fin ? 1.0 : 0.0, sum = fin ? (double)v : 0.0;
+    box_block_sum2<NW>(c, sum, red);
     const double mean = c > 0.0 ? sum / c : 0.0;
     const double d = fin ? (double)v - mean : 0.0;
     const double m2 = box_block_sum<NW>(d * d, red);
