@@ -217,16 +217,19 @@ int hsad_detect(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_win
  * and the detector by FP64 arithmetic and LDS, and a CU holds one workgroup of each, so
  * their times overlap instead of adding.  Otherwise the two run one after the other on the
  * stream.
- *   cube_next    : device, H*W*L float32 [y][x][band], or NULL (no transform: hsad_detect)
+ *   cube_next    : device, H*W*L float32 [y][x][band], or NULL (no transform: hsad_detect);
+ *                  must not overlap the detector's outputs
  *   L, levels    : as hsad_dwt; their L' must equal Lp
  *   approx_next  : device, H*W*Lp float32 written; must not overlap any other argument
  *   x            : device, H*W*Lp float32, the cube to score, or NULL (transform only:
  *                  hsad_dwt; p, z_alpha, lrx, dwrx, stats, mask and ws are then ignored)
  *   p ... ws_bytes : as hsad_detect
  *   start, stop  : events taken when the launch that holds the transform starts and ends
- *                  (the shared launch, or the transform's own), or NULL
+ *                  (the shared launch, or the transform's own), or NULL; not recorded when
+ *                  cube_next is NULL
  * Errors: as hsad_dwt and hsad_detect; HSAD_EINVAL if both cubes are NULL, if the two L'
- * differ or if approx_next overlaps another argument (nothing is enqueued then). */
+ * differ, if approx_next overlaps another argument or if cube_next overlaps lrx, dwrx,
+ * mask, stats or ws (nothing is enqueued then). */
 int hsad_dwt_detect_fused(const float *cube_next, int64_t L, int levels, float *approx_next,
                           const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
                           double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,

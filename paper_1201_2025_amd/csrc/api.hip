@@ -413,18 +413,24 @@ int hsad_dwt_detect_fused(const float *cube_next, int64_t L, int levels, float *
     if (!cube_next) return hsad_detect(x, H, W, Lp, p, z_alpha, lrx, dwrx, stats, mask, ws, ws_bytes, stream);
     if (Lpn != Lp)
         return fail(HSAD_EINVAL, std::string(fn) + ": L' of the cube to reduce differs from the L' of x");
-    // what the DWT writes must not meet anything the detector reads or writes
+    // the two halves run at the same time: what the DWT writes must not meet anything the
+    // detector reads or writes, and what the detector writes must not meet the cube the DWT
+    // reads
     const auto meets = [](const void *a, size_t na, const void *b, size_t nb) {
         if (!a || !b || !na || !nb) return false;
         const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
         return pa < pb + nb && pb < pa + na;
     };
-    const size_t red = (size_t)(n * Lp) * sizeof(float);
-    if (meets(approx_next, red, cube_next, (size_t)(n * L) * sizeof(float)) || meets(approx_next, red, x, red) ||
-        meets(approx_next, red, lrx, (size_t)n * sizeof(float)) ||
-        meets(approx_next, red, dwrx, (size_t)n * sizeof(float)) || meets(approx_next, red, mask, (size_t)n) ||
-        meets(approx_next, red, stats, 4 * sizeof(double)) || meets(approx_next, red, ws, ws_bytes))
+    const size_t red = (size_t)(n * Lp) * sizeof(float), raw = (size_t)(n * L) * sizeof(float);
+    const size_t map = (size_t)n * sizeof(float);
+    if (meets(approx_next, red, cube_next, raw) || meets(approx_next, red, x, red) ||
+        meets(approx_next, red, lrx, map) || meets(approx_next, red, dwrx, map) ||
+        meets(approx_next, red, mask, (size_t)n) || meets(approx_next, red, stats, 4 * sizeof(double)) ||
+        meets(approx_next, red, ws, ws_bytes))
         return fail(HSAD_EINVAL, std::string(fn) + ": approx_next overlaps another argument");
+    if (meets(cube_next, raw, lrx, map) || meets(cube_next, raw, dwrx, map) || meets(cube_next, raw, mask, (size_t)n) ||
+        meets(cube_next, raw, stats, 4 * sizeof(double)) || meets(cube_next, raw, ws, ws_bytes))
+        return fail(HSAD_EINVAL, std::string(fn) + ": cube_next overlaps an output of the detector");
     if (exact(p->precision) && box_supported(Lp, w)) {
         double *part = (double *)ws;
         const size_t np = (head / (3 * sizeof(double))) - threshold_fold_doubles() / 3;

@@ -167,6 +167,12 @@ def test_fused_rejects_overlap_and_mismatch():
     with pytest.raises(hs.HsadError) as e:
         hs.hsad_dwt_detect_fused(c, 4, lrx.view(H, W, 4), x, 3, 9, lrx=lrx[: H * W].view(H, W))
     assert e.value.code == hs.HSAD_EINVAL
+    big = torch.empty(H * W * L, dtype=torch.float32, device="cuda")
+    big.copy_(c.reshape(-1))
+    with pytest.raises(hs.HsadError) as e:                       # the detector would write the cube read
+        hs.hsad_dwt_detect_fused(big.view(H, W, L), 4, torch.empty((H, W, 4), device="cuda"), x, 3, 9,
+                                 lrx=big[: H * W].view(H, W))
+    assert e.value.code == hs.HSAD_EINVAL
     with pytest.raises(hs.HsadError) as e:                       # L' 8 for the next cube, 4 for x
         hs.hsad_dwt_detect_fused(c, 3, torch.empty((H, W, 4), device="cuda"), x, 3, 9)
     assert e.value.code == hs.HSAD_EINVAL
