@@ -97,7 +97,7 @@ def parse():
                     help="also time the FP64 oracle, 1 thread and all threads, on every configuration (minutes)")
     ap.add_argument("--profile-workload", type=str, default=None,
                     help="run one named workload 3 times (after one warm-up) for a profiler and exit: "
-                         "fullband, lp56, lp56_bf16, lp4, dwest14, dwest56, grx4, grx224, wavelet")
+                         "fullband, lp56, lp56_bf16, lp4, fused4, dwest14, dwest56, grx4, grx224, wavelet")
     ap.add_argument("--profile", action="store_true",
                     help="timed steps only, then 3 plain 256 MiB device copies (counter calibration)")
     return ap.parse_args()
@@ -630,11 +630,15 @@ def profile_workload(name, dev):
     s = synth.make_scene(c["seed"], c["H"], c["W"], c["L"], K=c["K"], n_single=c["n_single"], n_blob=c["n_blob"])
     cube = torch.from_numpy(s.cube).to(dev)
     H, W = c["H"], c["W"]
+    spare = {}
     works = {
         "fullband": (0, lambda x: hs.hsad_lrx_dwrx(x, 5, 15, 1e-6)),
         "lp56": (2, lambda x: hs.hsad_lrx_dwrx(x, 5, 15, 1e-6)),
         "lp56_bf16": (2, lambda x: hs.hsad_lrx_dwrx(x, 5, 15, 1e-6, hs.HSAD_PREC_GRAM_BF16)),
         "lp4": (6, lambda x: hs.hsad_detect(x, 5, 15, 1e-6, 3.0)),
+        # the headline step's shared launch: the DWT of the cube beside the detector of x
+        "fused4": (6, lambda x: hs.hsad_dwt_detect_fused(cube, 6, spare.setdefault("a", torch.empty_like(x)), x,
+                                                         5, 15, 1e-6, 3.0)),
         "dwest14": (4, lambda x: hs.hsad_dwest(x, 3, 11)),
         "dwest56": (2, lambda x: hs.hsad_dwest(x, 3, 11)),
         "grx4": (6, lambda x: hs.hsad_global_rx(x, 1e-6)),
