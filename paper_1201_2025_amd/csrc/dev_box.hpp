@@ -359,8 +359,11 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ x, int H, int
             static_assert(TY * C::GC * NSEG <= NT, "one horizontal job per thread");
             double hv[HS];
             const bool hjob = tid < TY * C::GC * NSEG;
+            // the feature varies fastest over the lanes, then the segment: the lanes of a
+            // 16-lane group then read 16 different LDS bank pairs (feature stride 2 banks,
+            // segment stride 8 GCP = 72 doubles, 16 banks mod 32)
             const int hr = tid / (C::GC * NSEG), hrem = tid - hr * (C::GC * NSEG);
-            const int hg = hrem / NSEG, hx0 = (hrem - hg * NSEG) * HS;
+            const int hseg = hrem / C::GC, hg = hrem - hseg * C::GC, hx0 = hseg * HS;
             if (hjob) {
                 const double *v = V + ((size_t)hr * EX + hx0 + eoff) * C::GCP + hg;
                 double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
