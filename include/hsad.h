@@ -235,6 +235,38 @@ int hsad_dwt_detect_fused(const float *cube_next, int64_t L, int levels, float *
                           double z_alpha, float *lrx, float *dwrx, double *stats, uint8_t *mask, void *ws,
                           size_t ws_bytes, hipStream_t stream, hipEvent_t start, hipEvent_t stop);
 
+/* One step of a three-stage pipeline over a stream of cubes, for the L' <= 8 box path of the
+ * detection step: the DWT of cube k + 1 (Sec. 3), LRX + DWRX of cube k (eqs. 1, 5) with its
+ * per-tile (count, mean, M2) partials left in ws, and the eq. (12) threshold and mask of
+ * cube k - 1 (Sec. 5.3.2) from the scores and partials the previous call left.  Over two
+ * calls the outputs for one cube equal hsad_detect's bit for bit (the partials are merged in
+ * hsad_detect's fixed order).  When L' <= 5, L is a multiple of 4 and the LDS of the
+ * transform's and the detector's workgroups fits one CU together (as hsad_dwt_detect_fused),
+ * and both cube_next and x are given, the three stages share one launch; otherwise they run
+ * one after the other on the stream.  Any stage is skipped when its input is NULL.
+ *   cube_next, L, levels, approx_next : as hsad_dwt_detect_fused; L' of (L, levels) = Lp
+ *   x      : device, H*W*Lp float32, the reduced cube k, or NULL
+ *   p      : window parameters; exact precision, L' <= 8 and windows the box path takes
+ *   lrx, dwrx : device, H*W float32 written (dwrx may be NULL)
+ *   ws     : device workspace of at least hsad_detect_workspace_bytes; receives cube k's
+ *            partials
+ *   prev_lrx  : device, H*W float32, cube k - 1's LRX map, or NULL
+ *   prev_ws   : the workspace the call that scored cube k - 1 filled (same H, W, Lp and
+ *               windows); also scratch for the merge when the image has more than 1024 tiles
+ *   z_alpha, prev_stats, prev_mask : as hsad_detect's z_alpha, stats and mask (mask may be
+ *               NULL), for cube k - 1
+ *   start, stop : events taken when the launch that holds the transform starts and ends, or
+ *               NULL; not recorded when cube_next is NULL
+ * No two arguments that one stage writes may overlap any other argument.
+ * Errors: HSAD_EINVAL (nothing to do, an overlap, a missing output, the two L' differ);
+ * HSAD_EUNSUPPORTED when the detector is not on the exact box path; as hsad_dwt and
+ * hsad_detect otherwise.  Nothing is enqueued on an error found on the host. */
+int hsad_detect_stream_step(const float *cube_next, int64_t L, int levels, float *approx_next, const float *x,
+                            int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p, float *lrx, float *dwrx,
+                            void *ws, size_t ws_bytes, const float *prev_lrx, void *prev_ws, double z_alpha,
+                            double *prev_stats, uint8_t *prev_mask, hipStream_t stream, hipEvent_t start,
+                            hipEvent_t stop);
+
 /* Size of the static device array hsad_detect_noalloc takes its workspace from. */
 #define HSAD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 

@@ -15,7 +15,7 @@ from ._binding import (  # noqa: F401
     HSAD_OP_DWRX, HSAD_OP_LRX, HSAD_OP_LRX_DWRX, HSAD_PREC_AUTO, HSAD_PREC_FP32,
     HSAD_PREC_FP64, HSAD_PREC_GRAM_BF16, HSAD_PREC_GRAM_FP16, HsadError, WindowParams,
     hsad_detect, hsad_detect_workspace_bytes, hsad_detect_noalloc, NOALLOC_SCRATCH_BYTES, hsad_global_rx, hsad_global_rx_workspace_bytes,
-    hsad_wavelet_filter, hsad_dwt_full_len, hsad_dwt_full, hsad_idwt_full, hsad_dwest, hsad_dwrx, hsad_dwt, hsad_dwt_timed, hsad_dwt_detect_fused, hsad_dwt_out_len, hsad_last_error, hsad_levels_for,
+    hsad_wavelet_filter, hsad_dwt_full_len, hsad_dwt_full, hsad_idwt_full, hsad_dwest, hsad_dwrx, hsad_dwt, hsad_dwt_timed, hsad_dwt_detect_fused, hsad_detect_stream_step, hsad_dwt_out_len, hsad_last_error, hsad_levels_for,
     hsad_lrx, hsad_lrx_dwrx, hsad_version, hsad_workspace_bytes, lib, lib_path,
     hsad_threshold, hsad_threshold_workspace_bytes, hsad_auc, hsad_auc_workspace_bytes,
     auc_from_counts, BatchPlan, BatchOptions, Scene, batch_default_options,

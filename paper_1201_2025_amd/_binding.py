@@ -100,6 +100,9 @@ SIGNATURES = [
     ("hsad_dwt_detect_fused", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, _vp, _i64, _i64, _i64, _P,
                                              ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp,
                                              _vp, _vp]),
+    ("hsad_detect_stream_step", ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, _vp, _i64, _i64, _i64, _P, _vp, _vp,
+                                               _vp, ctypes.c_size_t, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
+                                               _vp, _vp]),
     ("hsad_dwest", ctypes.c_int, [_vp, _i64, _i64, _i64, _P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     ("hsad_global_rx_workspace_bytes", ctypes.c_size_t, [_i64, _i64]),
     ("hsad_global_rx", ctypes.c_int, [_vp, _i64, _i64, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_size_t,
@@ -458,6 +461,41 @@ def hsad_dwt_detect_fused(cube_next, levels: int, approx_next, x, inner: int, ou
                                      _dev(ws, "ws"), ws.numel() * ws.element_size(), _stream(stream), ev[0], ev[1])
     _check("hsad_dwt_detect_fused", rc)
     return lrx, dwrx, stats, mask
+
+
+def hsad_detect_stream_step(cube_next, levels: int, approx_next, x, inner: int, outer: int, lrx, ws,
+                            dwrx=None, prev_lrx=None, prev_ws=None, prev_stats=None, prev_mask=None,
+                            load_rel: float = 1e-6, z_alpha: float = 3.0, H=None, W=None, Lp=None,
+                            start=None, stop=None, stream=None):
+    """One step of the three-stage pipeline: the DWT of cube_next into approx_next, LRX + DWRX of
+    the reduced cube x into lrx / dwrx with its tile partials in ws, and the eq. (12) threshold
+    (prev_stats) and mask (prev_mask) of the previous cube from prev_lrx and the partials its
+    call left in prev_ws.  Any stage is skipped when its input is None.  H, W, Lp are taken
+    from x (or prev_lrx / approx_next) unless given."""
+    torch = _torch()
+    if x is not None:
+        H, W, Lp = x.shape
+    else:
+        if H is None or W is None:
+            src = prev_lrx if prev_lrx is not None else cube_next
+            H, W = int(src.shape[0]), int(src.shape[1])
+        if Lp is None:
+            Lp = int(approx_next.shape[2]) if approx_next is not None else None
+    if Lp is None:
+        raise ValueError("Lp must be given when neither x nor approx_next is")
+    L = int(cube_next.shape[-1]) if cube_next is not None else 0
+    p = _params(inner, outer, load_rel, HSAD_PREC_AUTO)
+    ev = _events(start, stop)
+    rc = lib().hsad_detect_stream_step(
+        _ptr_or_null(cube_next, "cube_next", torch.float32), L, int(levels),
+        _ptr_or_null(approx_next, "approx_next", torch.float32), _ptr_or_null(x, "x", torch.float32),
+        int(H), int(W), int(Lp), ctypes.byref(p), _ptr_or_null(lrx, "lrx", torch.float32),
+        _ptr_or_null(dwrx, "dwrx", torch.float32), _ptr_or_null(ws, "ws", None),
+        (ws.numel() * ws.element_size()) if ws is not None else 0, _ptr_or_null(prev_lrx, "prev_lrx", torch.float32),
+        _ptr_or_null(prev_ws, "prev_ws", None), float(z_alpha),
+        _ptr_or_null(prev_stats, "prev_stats", torch.float64), _ptr_or_null(prev_mask, "prev_mask", torch.uint8),
+        _stream(stream), ev[0], ev[1])
+    _check("hsad_detect_stream_step", rc)
 
 
 def hsad_wavelet_filter(order: int):

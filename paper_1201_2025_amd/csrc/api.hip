@@ -447,6 +447,94 @@ int hsad_dwt_detect_fused(const float *cube_next, int64_t L, int levels, float *
     return hsad_detect(x, H, W, Lp, p, z_alpha, lrx, dwrx, stats, mask, ws, ws_bytes, stream);
 }
 
+int hsad_detect_stream_step(const float *cube_next, int64_t L, int levels, float *approx_next, const float *x,
+                            int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p, float *lrx, float *dwrx,
+                            void *ws, size_t ws_bytes, const float *prev_lrx, void *prev_ws, double z_alpha,
+                            double *prev_stats, uint8_t *prev_mask, hipStream_t stream, hipEvent_t start,
+                            hipEvent_t stop)
+{
+    static const char *fn = "hsad_detect_stream_step";
+    clear_error();
+    if (!cube_next && !x && !prev_lrx) return fail(HSAD_EINVAL, std::string(fn) + ": nothing to do");
+    if (H < 1 || W < 1) return fail(HSAD_EINVAL, std::string(fn) + ": H and W must be >= 1");
+    const int64_t n = H * W;
+    int64_t Lpn = 0;
+    if (cube_next) {
+        if (!approx_next) return fail(HSAD_EINVAL, std::string(fn) + ": approx_next is NULL");
+        if (out_len(L, levels, &Lpn))
+            return fail(HSAD_EINVAL, std::string(fn) + ": L < 1, levels < 0 or levels too deep for L");
+        if (L > (1 << 20)) return fail(HSAD_EUNSUPPORTED, std::string(fn) + ": L above 2^20");
+        if (Lpn != Lp) return fail(HSAD_EINVAL, std::string(fn) + ": L' of the cube to reduce differs from Lp");
+    }
+    // the detector and the threshold work on the box path's tile partials
+    Windows w;
+    int rc = check_windows(fn, p, H, W, Lp, dwrx != nullptr, &w);
+    if (rc) return rc;
+    if (!exact(p->precision) || !box_supported(Lp, w))
+        return fail(HSAD_EUNSUPPORTED, std::string(fn) + ": needs the exact box path (L' <= 8)");
+    const size_t head = detect_head_bytes(H, W);
+    if (x && (!lrx || !ws || ws_bytes < head))
+        return fail(HSAD_EINVAL, std::string(fn) + ": x needs lrx and a workspace of hsad_detect's size");
+    if (prev_lrx && (!prev_stats || !prev_ws)) return fail(HSAD_EINVAL, std::string(fn) + ": prev_lrx needs prev_stats and prev_ws");
+    if (prev_lrx && !std::isfinite(z_alpha)) return fail(HSAD_EINVAL, std::string(fn) + ": z_alpha not finite");
+    // the stages run at the same time: nothing one writes may meet what another reads or writes
+    const auto meets = [](const void *a, size_t na, const void *b, size_t nb) {
+        if (!a || !b || !na || !nb) return false;
+        const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+        return pa < pb + nb && pb < pa + na;
+    };
+    const size_t red = (size_t)(n * Lp) * sizeof(float), map = (size_t)n * sizeof(float);
+    struct Rg {
+        const void *p;
+        size_t n;
+        bool written;
+    } r[] = {{cube_next, cube_next ? (size_t)(n * L) * sizeof(float) : 0, false},
+             {approx_next, cube_next ? red : 0, true},
+             {x, x ? red : 0, false},
+             {lrx, x ? map : 0, true},
+             {dwrx, x ? map : 0, true},
+             {ws, x ? ws_bytes : 0, true},
+             {prev_lrx, prev_lrx ? map : 0, false},
+             {prev_ws, prev_lrx ? head : 0, true},
+             {prev_stats, prev_lrx ? 4 * sizeof(double) : 0, true},
+             {prev_mask, prev_lrx ? (size_t)n : 0, true}};
+    const int nr = (int)(sizeof(r) / sizeof(r[0]));
+    for (int i = 0; i < nr; ++i)
+        for (int j = i + 1; j < nr; ++j)
+            if ((r[i].written || r[j].written) && meets(r[i].p, r[i].n, r[j].p, r[j].n))
+                return fail(HSAD_EINVAL, std::string(fn) + ": two arguments overlap");
+    const size_t np = (head / (3 * sizeof(double))) - threshold_fold_doubles() / 3;
+    const int64_t ntiles = (int64_t)box_tiles_used(H, W, Lp, w);
+    double *part = (double *)ws, *pprev = (double *)prev_ws;
+    if (cube_next && x) {
+        // the threshold joins the shared launch when its partials fit one merge tree
+        const bool thr_in = prev_lrx && ntiles <= 1024;
+        FusedThr thr{prev_lrx, pprev, (int)ntiles, z_alpha, prev_stats, prev_mask};
+        int64_t nparts = 0;
+        rc = dwt_box_fused_launch(cube_next, L, levels, approx_next, x, H, W, Lp, w, p->load_rel, lrx, dwrx, part,
+                                  &nparts, stream, start, stop, thr_in ? &thr : nullptr);
+        if (rc == HSAD_OK) {
+            if (!prev_lrx || thr_in) return HSAD_OK;
+            return threshold_from_partials(prev_lrx, n, pprev, ntiles, z_alpha, prev_stats, prev_mask,
+                                           pprev + 3 * np, stream);
+        }
+        if (rc != HSAD_EUNSUPPORTED) return rc;
+    }
+    // the stages one after the other
+    if (cube_next) {
+        rc = dwt_launch(cube_next, n, L, levels, Lp, approx_next, stream, start, stop);
+        if (rc) return rc;
+    }
+    if (x) {
+        rc = box_lrx_dwrx_launch(x, H, W, Lp, w, p->load_rel, lrx, dwrx, stream, part);
+        if (rc) return rc;
+    }
+    if (prev_lrx)
+        return threshold_from_partials(prev_lrx, n, pprev, ntiles, z_alpha, prev_stats, prev_mask, pprev + 3 * np,
+                                       stream);
+    return HSAD_OK;
+}
+
 int hsad_dwest(const float *x, int64_t H, int64_t W, int64_t Lp, const hsad_window_params *p,
                float *scores, float *scores_literal, int32_t *npos, void *ws,
                size_t ws_bytes, hipStream_t stream)

@@ -37,6 +37,7 @@
 #include "internal.hpp"
 #include "dev_box.hpp"
 #include "dev_dwt.hpp"
+#include "dev_thr.hpp"
 
 namespace hsad {
 
@@ -204,10 +205,35 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(4, 4))
     const float *__restrict__ cube, int64_t npix, int L, const double *__restrict__ coef,
     float *__restrict__ approx, int nd, const float *__restrict__ x, int H, int W, int R, int RI,
     int has_inner, double load_rel, float *__restrict__ lrx, float *__restrict__ dwrx,
-    double *__restrict__ part, int nb, int ntx, int run)
+    double *__restrict__ part, int nb, int ntx, int run, FusedThr thr)
 {
     extern __shared__ double smem[];
     const int b = blockIdx.x;
+    if (b >= nd + nb) {
+        // threshold role: eq. (12) of an earlier map from its tile partials, then the mask of
+        // 2048 of its pixels
+        constexpr int kPF = 4;
+        const int idx = b - nd - nb, t = threadIdx.x;
+        const int64_t i0 = (int64_t)idx * (kFusedNT * kPF) + t;
+        float sv[kPF];
+#pragma unroll
+        for (int k = 0; k < kPF; ++k) {
+            const int64_t i = i0 + k * kFusedNT;
+            sv[k] = thr.s[i < npix ? i : npix - 1];
+        }
+        ThrParts pp;
+        thr_load_parts(thr.part, thr.nblk, t, pp);
+        const double tau = thr_merge_tau(pp, thr.nblk, thr.z, smem, smem + 3 * kThrMergeThreads,
+                                         idx == 0 ? thr.stats : nullptr);
+        if (thr.mask) {
+#pragma unroll
+            for (int k = 0; k < kPF; ++k) {
+                const int64_t i = i0 + k * kFusedNT;
+                if (i < npix) thr.mask[i] = ((double)sv[k] > tau) ? 1 : 0;
+            }
+        }
+        return;
+    }
     const int m = min(nd, nb) / run;   // full run pairs
     int role, idx;
     if (b < 2 * m * run) {
@@ -229,7 +255,8 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(4, 4))
 template <int LP>
 static int fused_launch(const float *cube, int64_t L, const double *coef, float *approx, const float *x,
                         int64_t H, int64_t W, const Windows &w, double load_rel, float *lrx, float *dwrx,
-                        double *part, int64_t *nparts, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                        double *part, int64_t *nparts, const FusedThr *thr, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1)
 {
     // the 32 x 16 detector tile with the default feature chunk: what hsad_detect runs
     constexpr int GC = kBoxBestGc[LP];
@@ -245,14 +272,24 @@ static int fused_launch(const float *cube, int64_t L, const double *coef, float 
     const int ntx = (int)((W + TXW - 1) / TXW);
     const int64_t nb = (int64_t)ntx * ((H + TY - 1) / TY);
     if (nd + nb > INT32_MAX) return HSAD_EUNSUPPORTED;
+    // threshold role: one workgroup per 2048 pixels of the earlier map
+    FusedThr tr{};
+    int64_t nm = 0;
+    if (thr) {
+        if (thr->nblk < 1 || thr->nblk > kThrMergeThreads * kThrMergePer) return HSAD_EUNSUPPORTED;
+        tr = *thr;
+        nm = (npix + 4 * kFusedNT - 1) / (4 * kFusedNT);
+    }
+    if (nd + nb + nm > INT32_MAX) return HSAD_EUNSUPPORTED;
     const void *kern = (const void *)dwt_box_fused_kernel<LP, 4, GC>;
     if (int rc = allow_lds(kern, sh, "dwt_box_fused_kernel")) return rc;
     int Li = (int)L, ndi = (int)nd, Hi = (int)H, Wi = (int)W, R = w.ro, RI = w.ri, hi = w.inner > 0 ? 1 : 0;
     int nbi = (int)nb, ntxi = ntx, runi = g_fused_run;
     int64_t np = npix;
     void *args[] = {(void *)&cube, &np, &Li, (void *)&coef, (void *)&approx, &ndi, (void *)&x, &Hi, &Wi, &R, &RI,
-                    &hi, &load_rel, (void *)&lrx, (void *)&dwrx, (void *)&part, &nbi, &ntxi, &runi};
-    if (hipExtLaunchKernel(kern, dim3((unsigned)(nd + nb)), dim3(kFusedNT), args, sh, s, e0, e1, 0) != hipSuccess)
+                    &hi, &load_rel, (void *)&lrx, (void *)&dwrx, (void *)&part, &nbi, &ntxi, &runi, &tr};
+    if (hipExtLaunchKernel(kern, dim3((unsigned)(nd + nb + nm)), dim3(kFusedNT), args, sh, s, e0, e1, 0) !=
+        hipSuccess)
         return fail(HSAD_EHIP, "dwt_box_fused_kernel: launch failed");
     *nparts = nb;
     return check_launch("dwt_box_fused_kernel");
@@ -260,7 +297,8 @@ static int fused_launch(const float *cube, int64_t L, const double *coef, float 
 
 int dwt_box_fused_launch(const float *cube, int64_t L, int levels, float *approx, const float *x,
                          int64_t H, int64_t W, int64_t Lp, const Windows &w, double load_rel, float *lrx,
-                         float *dwrx, double *part, int64_t *nparts, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                         float *dwrx, double *part, int64_t *nparts, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         const FusedThr *thr)
 {
     // L' <= 5 and whole float4 band vectors: the forms where both roles fit 128 VGPRs (four
     // waves per SIMD, two workgroups per CU) without spilling
@@ -271,7 +309,8 @@ int dwt_box_fused_launch(const float *cube, int64_t L, int levels, float *approx
     if (!coef) return HSAD_EUNSUPPORTED;
     switch (Lp) {
 #define HSAD_FUSED_CASE(n) \
-    case n: return fused_launch<n>(cube, L, coef, approx, x, H, W, w, load_rel, lrx, dwrx, part, nparts, s, e0, e1);
+    case n: \
+        return fused_launch<n>(cube, L, coef, approx, x, H, W, w, load_rel, lrx, dwrx, part, nparts, thr, s, e0, e1);
         HSAD_FUSED_CASE(1) HSAD_FUSED_CASE(2) HSAD_FUSED_CASE(3) HSAD_FUSED_CASE(4) HSAD_FUSED_CASE(5)
 #undef HSAD_FUSED_CASE
     default: return HSAD_EUNSUPPORTED;

@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "dev_thr.hpp"
 
 namespace hsad {
 
@@ -73,24 +74,6 @@ __global__ __launch_bounds__(kRedThreads) void thr_block_kernel(const float *__r
     }
 }
 
-// Chan et al.'s pairwise update of (count, mean, M2).
-__device__ __forceinline__ void chan_merge(double &na, double &ma, double &Ma, double nb, double mb,
-                                           double Mb)
-{
-    const double nn = na + nb;
-    if (nb == 0.0) return;
-    if (na == 0.0) {
-        na = nb;
-        ma = mb;
-        Ma = Mb;
-        return;
-    }
-    const double d = mb - ma;
-    ma += d * (nb / nn);
-    Ma += Mb + d * d * (na * nb / nn);
-    na = nn;
-}
-
 // Every block merges the per-block statistics with the same fixed tree (so they agree
 // bit for bit), block 0 stores stats = {count, mu, sigma, tau}, and all blocks write
 // the mask (s > tau) for their part of the map.
@@ -103,6 +86,7 @@ __global__ __launch_bounds__(kRedThreads) void thr_merge_mask_kernel(const float
 {
     __shared__ double sh[3 * kRedThreads];
     __shared__ double tau_s;
+    static_assert(kRedThreads == kThrMergeThreads, "one merge tree");
     // The thread's first kPF scores and its (at most four) partials are loaded up front,
     // from clamped indices, so all these round trips overlap each other and the merge.
     constexpr int kPF = 4;
@@ -114,53 +98,11 @@ __global__ __launch_bounds__(kRedThreads) void thr_merge_mask_kernel(const float
         const int64_t i = i0 + k * st;
         sv[k] = s[i < n ? i : n - 1];
     }
-    double pn[4], pm[4], pM[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = t + k * kRedThreads, ic = i < nblk ? i : nblk - 1;
-        pn[k] = part[3 * ic];
-        pm[k] = part[3 * ic + 1];
-        pM[k] = part[3 * ic + 2];
-    }
-    // fixed order: thread t merges partials t, t + 256, t + 512, t + 768, then a pairwise
-    // tree (t with t + w for w = 128 ... 1); the last six levels run inside wavefront 0
-    double na = 0.0, ma = 0.0, Ma = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (t + k * kRedThreads < nblk) chan_merge(na, ma, Ma, pn[k], pm[k], pM[k]);
-    sh[3 * t] = na;
-    sh[3 * t + 1] = ma;
-    sh[3 * t + 2] = Ma;
-    __syncthreads();
-    for (int w = kRedThreads / 2; w >= 64; w >>= 1) {
-        if (t < w) {
-            chan_merge(na, ma, Ma, sh[3 * (t + w)], sh[3 * (t + w) + 1], sh[3 * (t + w) + 2]);
-            sh[3 * t] = na;
-            sh[3 * t + 1] = ma;
-            sh[3 * t + 2] = Ma;
-        }
-        __syncthreads();
-    }
-    if (t < 64) {
-        for (int w = 32; w > 0; w >>= 1) {
-            const double nb = __shfl_down(na, w, 64), mb = __shfl_down(ma, w, 64), Mb = __shfl_down(Ma, w, 64);
-            if (t < w) chan_merge(na, ma, Ma, nb, mb, Mb);
-        }
-        if (t == 0) {
-            const double cnt = na, mu = cnt > 0 ? ma : NAN;
-            const double sig = cnt > 0 ? sqrt(Ma / cnt) : NAN;
-            tau_s = mu + z * sig;
-            if (blockIdx.x == 0) {
-                stats[0] = cnt;
-                stats[1] = mu;
-                stats[2] = sig;
-                stats[3] = tau_s;
-            }
-        }
-    }
-    __syncthreads();
+    ThrParts pp;
+    thr_load_parts(part, nblk, t, pp);
+    // block 0 stores stats = {count, mu, sigma, tau}
+    const double tau = thr_merge_tau(pp, nblk, z, sh, &tau_s, blockIdx.x == 0 ? stats : nullptr);
     if (!mask) return;
-    const double tau = tau_s;
 #pragma unroll
     for (int k = 0; k < kPF; ++k) {
         const int64_t i = i0 + k * st;

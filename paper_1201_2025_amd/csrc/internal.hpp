@@ -53,10 +53,20 @@ int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const 
 // the other.  The two must not
 // overlap in memory.  Returns HSAD_EUNSUPPORTED, with nothing enqueued and no error set,
 // when the pair cannot share a launch (the caller runs them one after the other).
+// thr (optional): a third role in the same launch, eq. (12) of an earlier map s from its
+// nblk <= 1024 tile partials, writing stats and mask (as threshold_from_partials).
+struct FusedThr {
+    const float *s;
+    const double *part;
+    int nblk;
+    double z;
+    double *stats;
+    uint8_t *mask;
+};
 int dwt_box_fused_launch(const float *cube, int64_t L, int levels, float *approx, const float *x,
                          int64_t H, int64_t W, int64_t Lp, const Windows &w, double load_rel, float *lrx,
                          float *dwrx, double *part, int64_t *nparts, hipStream_t s, hipEvent_t e0,
-                         hipEvent_t e1);
+                         hipEvent_t e1, const FusedThr *thr = nullptr);
 size_t box_tiles(int64_t H, int64_t W);
 // tiles of the box kernel as launched for these sizes (at most box_tiles(H, W))
 size_t box_tiles_used(int64_t H, int64_t W, int64_t Lp, const Windows &w);

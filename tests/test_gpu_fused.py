@@ -180,3 +180,76 @@ def test_fused_rejects_overlap_and_mismatch():
                                         0, None, None, None)
     assert rc == hs.HSAD_EINVAL
     torch.cuda.synchronize()
+
+
+# hsad_detect_stream_step: the DWT of cube k + 1, the detector of cube k and the eq. (12)
+# threshold + mask of cube k - 1 in one call (one launch where the first two can share one).
+# 720 x 900 has more than 1024 tiles: its threshold stage runs after the shared launch.
+STREAM = [(512, 512, 224, 6, 5, 15), (37, 70, 64, 4, 3, 9), (20, 45, 128, 6, 0, 9), (61, 40, 160, 5, 3, 11),
+          (30, 41, 190, 6, 3, 9), (720, 900, 64, 4, 5, 15)]
+
+
+@pytest.mark.parametrize("H,W,L,levels,inner,outer", STREAM)
+@pytest.mark.parametrize("run", [128, 7])
+def test_stream_step_equals_detect(H, W, L, levels, inner, outer, run):
+    import torch
+    if run != 128 and H * W > 100000:
+        pytest.skip("role interleaving is covered on the smaller images")
+    print("stream", H, W, L, levels, inner, outer, "run", run, flush=True)
+    cubes = [_cube(60 + k + H, H, W, L) for k in range(3)]
+    Lp = hs.hsad_dwt_out_len(L, levels)
+    A = [torch.empty((H, W, Lp), dtype=torch.float32, device="cuda") for _ in range(2)]
+    S = [torch.empty((H, W), dtype=torch.float32, device="cuda") for _ in range(2)]
+    nws = hs.hsad_detect_workspace_bytes(H, W, Lp, inner, outer, 1e-6)
+    WS = [torch.empty(nws, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    dw = torch.empty((H, W), dtype=torch.float32, device="cuda") if inner > 0 else None
+    got = [dict() for _ in cubes]
+    _set_run(run)
+    try:
+        hs.hsad_detect_stream_step(cubes[0], levels, A[0], None, inner, outer, None, None, H=H, W=W, Lp=Lp)
+        for k in range(len(cubes) + 1):
+            nxt = cubes[k + 1] if k + 1 < len(cubes) else None
+            x = A[k % 2] if k < len(cubes) else None
+            st = torch.full((4,), float("nan"), dtype=torch.float64, device="cuda")
+            mk = torch.full((H, W), 7, dtype=torch.uint8, device="cuda")
+            hs.hsad_detect_stream_step(nxt, levels, A[(k + 1) % 2] if nxt is not None else None, x, inner, outer,
+                                       S[k % 2] if x is not None else None, WS[k % 2] if x is not None else None,
+                                       dwrx=dw if x is not None else None,
+                                       prev_lrx=S[(k - 1) % 2] if k >= 1 else None,
+                                       prev_ws=WS[(k - 1) % 2] if k >= 1 else None,
+                                       prev_stats=st if k >= 1 else None, prev_mask=mk if k >= 1 else None,
+                                       H=H, W=W, Lp=Lp)
+            if x is not None:
+                got[k]["lrx"] = S[k % 2].clone()
+                got[k]["dwrx"] = dw.clone() if dw is not None else None
+            if k >= 1:
+                got[k - 1]["stats"], got[k - 1]["mask"] = st, mk
+        torch.cuda.synchronize()
+    finally:
+        _set_run(128)
+    for k, c in enumerate(cubes):
+        l0, d0, s0, m0 = hs.hsad_detect(hs.hsad_dwt(c, levels), inner, outer, 1e-6, 3.0, dwrx=inner > 0)
+        torch.cuda.synchronize()
+        assert _same(got[k]["lrx"], l0) and _same(got[k]["dwrx"], d0), k
+        assert _same(got[k]["stats"], s0) and _same(got[k]["mask"], m0), k
+
+
+def test_stream_step_rejects_bad_arguments():
+    import torch
+    H, W, L = 16, 16, 64
+    c = _cube(9, H, W, L)
+    x = hs.hsad_dwt(c, 4)
+    lrx = torch.empty((H, W), device="cuda")
+    ws = torch.empty(hs.hsad_detect_workspace_bytes(H, W, 4, 3, 9, 1e-6), dtype=torch.uint8, device="cuda")
+    st = torch.empty(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(hs.HsadError) as e:                       # nothing to do
+        hs.hsad_detect_stream_step(None, 4, None, None, 3, 9, None, None, H=H, W=W, Lp=4)
+    assert e.value.code == hs.HSAD_EINVAL
+    with pytest.raises(hs.HsadError) as e:                       # the threshold reads the partials being written
+        hs.hsad_detect_stream_step(None, 4, None, x, 3, 9, lrx, ws, prev_lrx=lrx.clone(), prev_ws=ws, prev_stats=st)
+    assert e.value.code == hs.HSAD_EINVAL
+    with pytest.raises(hs.HsadError) as e:                       # L' 14: not the box path's sizes for the stream
+        hs.hsad_detect_stream_step(None, 2, None, hs.hsad_dwt(_cube(10, H, W, 56), 2), 3, 9, lrx,
+                                   torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == hs.HSAD_EUNSUPPORTED
+    torch.cuda.synchronize()
