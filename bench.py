@@ -73,12 +73,15 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=300,
+                    help="untimed steps first (the pipelined schedules reach their steady rate after ~300: "
+                         "59 / 56 / 54 us per step after 10 / 100 / 300 at 512x512x224)")
     ap.add_argument("--level", type=int, default=None, help="DWT levels (default: paper rule)")
-    ap.add_argument("--schedule", choices=("fused", "separate"), default="fused",
-                    help="fused: each step is one hsad_dwt_detect_fused call that reduces the next cube "
-                         "and scores the current one in one launch (where L' <= 5 and L %% 4 == 0); "
-                         "separate: hsad_dwt then hsad_detect")
+    ap.add_argument("--schedule", choices=("stream", "fused", "separate"), default="stream",
+                    help="stream: each step is one hsad_detect_stream_step call (reduce the next cube, score "
+                         "the current one, threshold the previous one, in one launch where L' <= 5 and "
+                         "L %% 4 == 0); fused: one hsad_dwt_detect_fused call (reduce the next cube, score "
+                         "and threshold the current one); separate: hsad_dwt then hsad_detect")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fullband", action="store_true")
@@ -689,11 +692,19 @@ def main():
     det_ws = torch.empty(hs.hsad_detect_workspace_bytes(H, W, Lp, inner, outer, load), dtype=torch.uint8,
                          device=dev)
     th_out = torch.empty(4, dtype=torch.float64, device=dev)
-    # fused schedule: a stream of cubes through a two-stage software pipeline.  Step i scores
-    # cube i (reduced into bufs[i & 1] by step i - 1) and reduces cube i + 1 into the other
-    # buffer, in one launch; every step is one whole DWT and one whole detection.
-    fused = args.schedule == "fused" and Lp <= 5 and L % 4 == 0
+    # The default schedule treats the run as a stream of cubes (the same scene, two resident
+    # copies).  stream: a three-stage pipeline, step i reduces cube i + 1, scores cube i
+    # (reduced by step i - 1) and thresholds cube i - 1 (scored by step i - 1), in one launch
+    # where the stages can share one (hsad_detect_stream_step).  fused: step i reduces cube
+    # i + 1 and scores and thresholds cube i (hsad_dwt_detect_fused: one shared launch, then
+    # the merge and mask).  separate: hsad_dwt then hsad_detect.  Every step is one whole
+    # DWT, one whole detection and one whole threshold + mask; the pipeline fill runs before
+    # the timed steps.
+    shareable = Lp <= 5 and L % 4 == 0
+    sched = args.schedule if shareable else "separate"
     bufs = [torch.empty((H, W, Lp), dtype=torch.float32, device=dev) for _ in range(2)]
+    smap = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(2)]
+    sws = [torch.empty_like(det_ws) for _ in range(2)]
 
     def step_separate(i, ev=None):
         # ev: two events that the DWT's kernel dispatch itself records at its start and end
@@ -712,12 +723,22 @@ def main():
                                  lrx=lrx, dwrx=dwrx, stats=th_out, mask=mask, ws=det_ws,
                                  start=ev[0] if ev else None, stop=ev[1] if ev else None)
 
-    step = step_fused if fused else step_separate
-    hs.hsad_dwt(cubes[0], J, out=bufs[0])          # pipeline fill: cube 0 reduced before step 0
-    for i in range(args.warmup):
+    def step_stream(i, ev=None):
+        hs.hsad_detect_stream_step(cubes[(i + 1) & 1], J, bufs[(i + 1) & 1], bufs[i & 1], inner, outer,
+                                   smap[i & 1], sws[i & 1], dwrx=dwrx, prev_lrx=smap[(i + 1) & 1],
+                                   prev_ws=sws[(i + 1) & 1], prev_stats=th_out, prev_mask=mask, load_rel=load,
+                                   z_alpha=3.0, start=ev[0] if ev else None, stop=ev[1] if ev else None)
+
+    step = {"stream": step_stream, "fused": step_fused, "separate": step_separate}[sched]
+    # pipeline fill: cube 0 reduced before step 0 (for the stream also scored, and cube 1
+    # reduced, before step 1)
+    hs.hsad_dwt(cubes[0], J, out=bufs[0])
+    if sched == "stream":
+        hs.hsad_detect_stream_step(cubes[1], J, bufs[1], bufs[0], inner, outer, smap[0], sws[0], dwrx=dwrx,
+                                   load_rel=load)
+    i0 = 1 if sched == "stream" else 0
+    for i in range(i0, i0 + args.warmup):
         step(i)
-    if fused:
-        hs.hsad_dwt(cubes[0], J, out=bufs[0])      # step 0 of the timed run scores cube 0 again
     torch.cuda.synchronize()
     # the dominant launch's duration (roofline) comes from the events that its dispatch
     # records in every EV_EVERY-th timed step
@@ -729,22 +750,27 @@ def main():
             e.record()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    ibase = i0 + args.warmup         # the pipeline's buffers continue from the warm-up steps
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record()
     for i in range(args.steps):
-        step(i, evs.get(i))
+        step(ibase + i, evs.get(i))
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = t0.elapsed_time(t1) / args.steps
     launch_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs.values()]))
     value = npix / (ms_step * 1e-3)
-    # the timed run's last step left the scores of its last cube (the same scene)
-    fl, fd = lrx.clone(), dwrx.clone()
+    # the timed run's last step left the scores of its last cube and (stream) the threshold
+    # and mask of the one before (the same scene)
+    last = ibase + args.steps - 1
+    fl = (smap[last & 1] if sched == "stream" else lrx).clone()
+    fd, fs, fm = dwrx.clone(), th_out.clone(), mask.clone()
     # the separate schedule's step and its DWT / detection shares, from an instrumented pass
     # outside the timed region
     nsplit = min(args.steps, 50)
+    step_separate(0)           # first calls load the kernels: not in the instrumented pass
     sev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nsplit)]
     for trip in sev:
         for e in trip:
@@ -756,13 +782,13 @@ def main():
     dwt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in sev]))
     det_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in sev]))
     sep_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in sev]))
-    if not fused:
+    if sched == "separate":
         dwt_ms = launch_ms
-    if fused:
-        # the fused schedule's scores must equal the separate calls' (the instrumented pass
-        # above left those in lrx, dwrx)
-        if not (torch.equal(fl, lrx) and torch.equal(fd, dwrx)):
-            print("bench.py: the fused schedule's scores differ from the separate calls'", file=sys.stderr)
+    else:
+        # the pipelined schedule's outputs must equal the separate calls' bit for bit (the
+        # instrumented pass above left those in lrx, dwrx, th_out, mask)
+        if not (torch.equal(fl, lrx) and torch.equal(fd, dwrx) and torch.equal(fs, th_out) and torch.equal(fm, mask)):
+            print("bench.py: the %s schedule's outputs differ from the separate calls'" % sched, file=sys.stderr)
             sys.exit(1)
 
     if args.profile:
@@ -772,7 +798,7 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.steps, "schedule": "fused" if fused else "separate",
+        print(json.dumps({"profile_steps": args.steps, "schedule": sched,
                           "ms_per_step": ms_step, "launch_ms": launch_ms, "dwt_ms": dwt_ms, "detect_ms": det_ms,
                           "separate_ms_per_step": sep_ms}))
         return
@@ -780,14 +806,18 @@ def main():
     # dominant kernel, bound by HBM.  Algorithmic bytes per launch of the DWT: read the cube
     # once (H W L 4) and write the approximation matrix (H W L' 4).  The shared launch adds
     # the detector's: read the reduced cube once (H W L' 4), write the two score maps
-    # (H W 8) and one (count, mean, M2) partial per 32 x 16 tile.
+    # (H W 8) and one (count, mean, M2) partial per 32 x 16 tile; the stream's adds the
+    # threshold's: read the earlier LRX map (H W 4) and its partials, write its mask (H W).
     dwt_bytes = npix * L * 4 + npix * Lp * 4
     ntiles = ((H + 15) // 16) * ((W + 31) // 32)
     fused_bytes = dwt_bytes + npix * Lp * 4 + npix * 8 + ntiles * 24
-    if fused:
-        kern, launch_bytes = "dwt_box_fused_kernel", fused_bytes
-        src_hash = kernel_source_hash(["box.hip", "dev_box.hpp", "dwt.hip", "dev_dwt.hpp"])
-        traffic = load_traffic(kern, "C2_L%d_J%d_%d_%d" % (L, J, inner, outer), src_hash)
+    stream_bytes = fused_bytes + npix * 5 + ntiles * 24
+    if sched != "separate":
+        kern = "dwt_box_fused_kernel"
+        launch_bytes = stream_bytes if sched == "stream" else fused_bytes
+        src_hash = kernel_source_hash(["box.hip", "dev_box.hpp", "dwt.hip", "dev_dwt.hpp", "dev_thr.hpp"])
+        traffic = load_traffic(kern, "C2_L%d_J%d_%d_%d%s" % (L, J, inner, outer, "_thr" if sched == "stream" else ""),
+                               src_hash)
     else:
         kern, launch_bytes = ("dwt_equiv_lds_kernel" if Lp <= 16 else "dwt_banded_kernel"), dwt_bytes
         src_hash = kernel_source_hash(["dwt.hip", "dev_dwt.hpp"])
@@ -964,8 +994,11 @@ def main():
                                "outer 15 + eq. 12 mask" % (J, Lp),
                    "H": H, "W": W, "L": L, "levels": J, "Lp": Lp, "inner": inner,
                    "outer": outer, "load_rel": load, "storage": "f32", "parallelism": "1 GPU"},
-        "schedule": ("fused: one launch per step reduces cube i+1 and scores cube i (two reduced buffers), "
-                     "then the eq. 12 merge and mask" if fused else "separate: hsad_dwt, then hsad_detect"),
+        "schedule": {"stream": "stream: one launch per step reduces cube i+1, scores cube i and thresholds "
+                               "cube i-1 (two buffers per stage)",
+                     "fused": "fused: one launch per step reduces cube i+1 and scores cube i (two reduced "
+                              "buffers), then the eq. 12 merge and mask",
+                     "separate": "separate: hsad_dwt, then hsad_detect"}[sched],
         "kernel_ms": {"launch": launch_ms, "launch_event_samples": len(evs), "dwt": dwt_ms, "detect": det_ms,
                       "separate_step": sep_ms},
         "wall_s_timed": wall,
