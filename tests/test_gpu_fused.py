@@ -1,6 +1,7 @@
 """GPU tests of hsad_dwt_detect_fused: the DWT of one cube (Sec. 3) and the detection step
 (LRX eq. 1, DWRX eq. 5, the eq. 12 threshold and its mask) on another, reduced cube, in one
-launch where the two can share one.
+launch where the two can share one; and of hsad_detect_stream_step, which also runs the eq. 12
+threshold and mask of the cube before in the same launch.
 
 Each workgroup of the shared launch runs the arithmetic of the kernel its role comes from,
 so every output must equal that of hsad_dwt followed by hsad_detect bit for bit, for any
