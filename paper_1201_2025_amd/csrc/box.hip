@@ -183,7 +183,8 @@ int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const 
 }
 
 // ------------------------------------------------------------------------------------
-// One launch for the DWT of one cube and the detector on another, reduced cube
+// One launch for the DWT of one cube and the detector on another, reduced cube (and the
+// threshold of a third)
 // ------------------------------------------------------------------------------------
 // The LDS-staged DWT streams the cube from HBM and leaves the FP64 units mostly idle; the
 // detector tile is bound by FP64 arithmetic, LDS traffic and barrier latency and leaves HBM
@@ -196,7 +197,10 @@ int box_lrx_dwrx_launch(const float *x, int64_t H, int64_t W, int64_t Lp, const 
 // of 8 to 512, two chunks of the cube in flight per DWT workgroup, and 256-thread
 // workgroups with 16 x 16 tiles, three or four per CU, all measured slower).  Each role's
 // arithmetic is that of its own kernel, so the results are bit-identical to the two
-// launches.
+// launches.  Optionally a third role, placed after the other two, takes the eq. (12)
+// threshold of an earlier map: each of its workgroups merges that map's tile partials in
+// the threshold kernel's order (identical tau) and writes the mask of 2048 pixels, so a
+// stream of cubes needs one launch per cube (53.5 us where the three kernels take 66 us).
 constexpr int kFusedNT = 512;
 static int g_fused_run = 128;   // role run length in workgroup ids (tuning, tests)
 
