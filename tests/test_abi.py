@@ -274,3 +274,41 @@ def test_surrogate_argument_errors():
     assert need >= 64 * 64 * (64 * 2 + 4 + 1 + 4)
     assert run(FAKE, 64, 64, 14, ctypes.byref(p), ctypes.byref(m), ctypes.byref(o), FAKE, FAKE,
                ctypes.byref(rep), FAKE, need - 1, None) == hs.HSAD_ENOMEM
+
+
+def _at(addr):
+    return ctypes.c_void_p(addr)   # distinct fake device addresses, never dereferenced
+
+
+def test_pipelined_calls_reject_before_any_launch():
+    # hsad_dwt_detect_fused and hsad_detect_stream_step validate everything, overlaps between
+    # the stages' buffers included, on the host before anything is enqueued
+    L_ = hs.lib()
+    p = _p(3, 9)
+    H, W = 16, 16
+    cube, a1, x, lrx, dwrx, st, mk = (_at(0x100000 * k) for k in range(1, 8))
+    ws = _at(0x1000000)
+    nws = 1 << 16
+    # nothing to do
+    assert L_.hsad_dwt_detect_fused(None, 64, 4, None, None, H, W, 4, ctypes.byref(p), 3.0, lrx, dwrx, st, mk, ws,
+                                    nws, None, None, None) == hs.HSAD_EINVAL
+    # the reduced cube written over the cube being scored
+    assert L_.hsad_dwt_detect_fused(cube, 64, 4, x, x, H, W, 4, ctypes.byref(p), 3.0, lrx, dwrx, st, mk, ws, nws,
+                                    None, None, None) == hs.HSAD_EINVAL
+    assert "overlaps" in hs.hsad_last_error()
+    # L' of (64, 3) is 8, x has 4
+    assert L_.hsad_dwt_detect_fused(cube, 64, 3, a1, x, H, W, 4, ctypes.byref(p), 3.0, lrx, dwrx, st, mk, ws, nws,
+                                    None, None, None) == hs.HSAD_EINVAL
+    f = L_.hsad_detect_stream_step
+    pw, pl = _at(0x2000000), _at(0x3000000)
+    assert f(None, 64, 4, None, None, H, W, 4, ctypes.byref(p), None, None, None, 0, None, None, 3.0, None, None,
+             None, None, None) == hs.HSAD_EINVAL                       # nothing to do
+    assert f(None, 64, 4, None, x, H, W, 4, ctypes.byref(p), lrx, dwrx, None, 0, None, None, 3.0, None, None,
+             None, None, None) == hs.HSAD_EINVAL                       # the detector needs a workspace
+    assert f(None, 64, 4, None, x, H, W, 4, ctypes.byref(p), lrx, dwrx, ws, nws, pl, ws, 3.0, st, mk,
+             None, None, None) == hs.HSAD_EINVAL                       # partials read while written
+    assert "overlap" in hs.hsad_last_error()
+    assert f(None, 64, 4, None, x, H, W, 4, ctypes.byref(p), lrx, dwrx, ws, nws, pl, pw, float("nan"), st, mk,
+             None, None, None) == hs.HSAD_EINVAL                       # z not finite
+    assert f(None, 64, 4, None, x, H, W, 14, ctypes.byref(p), lrx, dwrx, ws, nws, None, None, 3.0, None, None,
+             None, None, None) == hs.HSAD_EUNSUPPORTED                 # not the box path
