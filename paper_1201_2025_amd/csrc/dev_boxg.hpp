@@ -34,6 +34,10 @@ namespace hsad {
 
 constexpr int BG_TX = 16, BG_TY = 16, BG_NT = 256, BG_RB = 4;   // RB: output rows per vertical job
 constexpr int BG_VS = 9;                 // odd LDS stride of the vertical-sum rows (>= 8 features)
+// odd LDS stride of a pixel's horizontal window sums (>= 8 features): a 16-lane group reading
+// its 16 pixels' sums, or writing a row's, then touches 16 different bank pairs (a stride of
+// 8 doubles put every pixel of a row on the same two banks)
+constexpr int BG_HS = 9;
 constexpr int BG_MAX_LP = 128, BG_MAX_R = 15;
 
 __host__ __device__ inline int bg_lpad(int Lp) { return (Lp + 3) & ~3; }
@@ -44,7 +48,7 @@ __host__ __device__ inline size_t bg_smem_chunked(int Lp, int R)
     const size_t EX = BG_TX + 2 * R, EY = BG_TY + 2 * R;
     return (size_t)bg_lpad(Lp) * 8            // ref
            + (size_t)BG_TY * EX * BG_VS * 8     // V (vertical sums)
-           + (size_t)BG_TY * BG_TX * 8 * 8      // horizontal window sums
+           + (size_t)BG_TY * BG_TX * BG_HS * 8  // horizontal window sums
            + EY * EX * 4                        // bad flags
            + EY * EX * 6 * 4;                   // xi (2 bands) + xj (4 bands)
 }
@@ -52,7 +56,7 @@ __host__ __device__ inline size_t bg_smem_chunked(int Lp, int R)
 __host__ __device__ inline size_t bg_smem_resident(int Lp, int R)
 {
     const size_t EX = BG_TX + 2 * R, EY = BG_TY + 2 * R;
-    return (size_t)bg_lpad(Lp) * 8 + (size_t)BG_TY * EX * BG_VS * 8 + (size_t)BG_TY * BG_TX * 8 * 8 + EY * EX * 4 +
+    return (size_t)bg_lpad(Lp) * 8 + (size_t)BG_TY * EX * BG_VS * 8 + (size_t)BG_TY * BG_TX * BG_HS * 8 + EY * EX * 4 +
            EY * EX * (size_t)bg_lpad(Lp) * 4;
 }
 // resident staging when the whole extended tile fits this many KiB of LDS (kernel argument,
@@ -139,17 +143,17 @@ __device__ inline void bg_window_sums(const Feat &feat, int EX, int R, int RI, i
             }
             for (; k <= 2 * h; ++k) r0 += v[(size_t)k * BG_VS];
             double run = (r0 + r1) + (r2 + r3);
-            double *hs = Hs + ((size_t)r * BG_TX + x0) * 8 + g;
+            double *hs = Hs + ((size_t)r * BG_TX + x0) * BG_HS + g;
             hs[0] = run;
 #pragma unroll
             for (int q = 1; q < HSG; ++q) {
                 run += v[(size_t)(q + 2 * h) * BG_VS] - v[(size_t)(q - 1) * BG_VS];
-                hs[(size_t)q * 8] = run;
+                hs[(size_t)q * BG_HS] = run;
             }
         }
         __syncthreads();
         double *S = win == 0 ? S_in : S_out;
-        const double *hp = Hs + ((size_t)ty * BG_TX + tx) * 8;
+        const double *hp = Hs + ((size_t)ty * BG_TX + tx) * BG_HS;
 #pragma unroll
         for (int g = 0; g < NF; ++g) S[g] = hp[g];
         __syncthreads();
@@ -253,7 +257,7 @@ __device__ inline void boxg_tile(const float *__restrict__ x, int H, int W, int 
     double *ref = reinterpret_cast<double *>(smem);
     double *V = ref + Lpad;
     double *Hs = V + (size_t)BG_TY * EX * BG_VS;
-    float *bad = reinterpret_cast<float *>(Hs + (size_t)BG_TY * BG_TX * 8);
+    float *bad = reinterpret_cast<float *>(Hs + (size_t)BG_TY * BG_TX * BG_HS);
     float *xs = bad + EY * EX;                  // resident: all bands, stride Lpad
     float *xi = xs, *xj = xs + EY * EX * 2;     // chunked: 2 + 4 bands
     const int tid = threadIdx.x, ty = tid / BG_TX, tx = tid - ty * BG_TX;
