@@ -475,7 +475,8 @@ int hsad_detect_stream_step(const float *cube_next, int64_t L, int levels, float
     const size_t head = detect_head_bytes(H, W);
     if (x && (!lrx || !ws || ws_bytes < head))
         return fail(HSAD_EINVAL, std::string(fn) + ": x needs lrx and a workspace of hsad_detect's size");
-    if (prev_lrx && (!prev_stats || !prev_ws)) return fail(HSAD_EINVAL, std::string(fn) + ": prev_lrx needs prev_stats and prev_ws");
+    if (prev_lrx && (!prev_stats || !prev_ws))
+        return fail(HSAD_EINVAL, std::string(fn) + ": prev_lrx needs prev_stats and prev_ws");
     if (prev_lrx && !std::isfinite(z_alpha)) return fail(HSAD_EINVAL, std::string(fn) + ": z_alpha not finite");
     // the stages run at the same time: nothing one writes may meet what another reads or writes
     const auto meets = [](const void *a, size_t na, const void *b, size_t nb) {
