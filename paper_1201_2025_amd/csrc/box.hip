@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(4, 4))
         dwt_equiv_lds_block<LP, VEC, true, kFusedNT>(cube, npix, L, coef, approx, reinterpret_cast<float *>(smem),
                                                      idx);
     else
-        box_tile<LP, GCMAX, kFusedNT / TY>(x, H, W, R, RI, has_inner, load_rel, lrx, dwrx, idx / ntx, idx % ntx,
+        box_tile<LP, GCMAX, kFusedNT / TY, false>(x, H, W, R, RI, has_inner, load_rel, lrx, dwrx, idx / ntx, idx % ntx,
                                            smem, part, ntx);
 }
 

@@ -233,7 +233,10 @@ template <int NW> __device__ __forceinline__ void box_tile_stats(float v, bool v
     }
 }
 
-template <int LP, int GCMAX, int TXW = 16>
+// FEATLANES: the horizontal jobs take the feature fastest over the lanes (fewer LDS bank
+// conflicts; faster on its own), else the segment (faster beside the DWT in the shared
+// launch).  Either order gives the same sums.
+template <int LP, int GCMAX, int TXW = 16, bool FEATLANES = true>
 __device__ __forceinline__ void box_tile(const float *__restrict__ x, int H, int W, int R, int RI,
                                 int has_inner, double load_rel, float *__restrict__ lrx,
                                 float *__restrict__ dwrx, int by, int bx, double *smem,
@@ -359,11 +362,12 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ x, int H, int
             static_assert(TY * C::GC * NSEG <= NT, "one horizontal job per thread");
             double hv[HS];
             const bool hjob = tid < TY * C::GC * NSEG;
-            // the feature varies fastest over the lanes, then the segment: the lanes of a
-            // 16-lane group then read 16 different LDS bank pairs (feature stride 2 banks,
-            // segment stride 8 GCP = 72 doubles, 16 banks mod 32)
+            // FEATLANES: the feature varies fastest over the lanes, then the segment, so the
+            // lanes of a 16-lane group read 16 different LDS bank pairs (feature stride 2
+            // banks, segment stride 8 GCP = 72 doubles, 16 banks mod 32)
             const int hr = tid / (C::GC * NSEG), hrem = tid - hr * (C::GC * NSEG);
-            const int hseg = hrem / C::GC, hg = hrem - hseg * C::GC, hx0 = hseg * HS;
+            const int hseg = FEATLANES ? hrem / C::GC : hrem % NSEG;
+            const int hg = FEATLANES ? hrem - hseg * C::GC : hrem / NSEG, hx0 = hseg * HS;
             if (hjob) {
                 const double *v = V + ((size_t)hr * EX + hx0 + eoff) * C::GCP + hg;
                 double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
